@@ -1,0 +1,155 @@
+/*
+ * mf.h - C ABI of the MI355X (gfx950) sparse, albedo-corrected matched-filter
+ * methane retrieval.
+ *
+ * The library computes, for every detector partition (one cross-track column
+ * of a pushbroom flightline, Sec. II-E), the iteration of the algorithm figure
+ * "AlbedoReWeightL1Filter" (Fig. 1) of Foote et al., "Fast and Accurate
+ * Retrieval of Methane Concentration from Imaging Spectrometer Data Using
+ * Sparsity Prior", IEEE TGRS 2020:
+ *
+ *   mu^0 = mean L_i,  C^0 = sample covariance,  r_i = L_i.mu^0 / mu^0.mu^0 (Eq. 7)
+ *   alpha^0_i = (L_i - mu^0)^T C^0^-1 t^0 / (r_i t^0^T C^0^-1 t^0),  t = mu (.) s (Eq. 9)
+ *   for k = 1..K:
+ *     w_i   = lambda / (alpha_i^{k-1} + eps)                            (Eq. 5)
+ *     mu^k  = mean (L_i - r_i alpha_i^{k-1} mu^{k-1} (.) s)              (Eq. 10)
+ *     C^k   = mean d_i d_i^T, d_i = L_i - r_i alpha_i^{k-1} t^k - mu^k  (Eq. 11)
+ *     alpha_i^k = max(((L_i - mu^k)^T C^k^-1 t^k - w_i) / (r_i t^k^T C^k^-1 t^k), 0)
+ *                                                                     (Eqs. 6, 8)
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers on the plan's device, owned by the
+ *    caller, unless stated otherwise.  The library does not keep them.
+ *  - Work is enqueued on the caller's HIP stream (hipStream_t passed as void*;
+ *    NULL = the default stream).  No entry point synchronises the stream.
+ *  - Argument and shape errors are detected on the host before anything is
+ *    enqueued and returned as an mf_status; nothing is launched then.
+ *  - Numerical failures are per column and asynchronous: they are written to
+ *    column_status (see MF_COL_*) and the column's alpha is set to 0.
+ *  - No C++ exception crosses this boundary.
+ *
+ * Radiance layout: float32, band-contiguous pixels ("[px][B]").  Flightline f
+ * has n_columns columns of n_lines pixels each; pixel (column c, line l) of
+ * flightline f is the global pixel index first_px + c * n_lines + l, so each
+ * column is a contiguous run of n_lines * B floats.  Flightlines may be
+ * ragged and need not be adjacent, but their pixel ranges must not overlap.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define MF_API __attribute__((visibility("default")))
+#else
+#define MF_API
+#endif
+
+#define MF_ABI_VERSION 1
+#define MF_MAX_BANDS 78      /* B + 2 <= 80: five 16-band MFMA blocks */
+
+typedef struct mf_plan_s* mf_plan;
+
+typedef enum {
+  MF_OK = 0,
+  MF_E_ARG = 1,          /* NULL pointer, bad option value, bad struct_size */
+  MF_E_SHAPE = 2,        /* inconsistent or overlapping flightline geometry */
+  MF_E_UNSUPPORTED = 3,  /* e.g. n_bands outside [2, MF_MAX_BANDS] */
+  MF_E_DEVICE = 4,       /* a HIP runtime call failed */
+  MF_E_STATE = 5         /* mf_backward without a saved forward */
+} mf_status;
+
+/* Per-column status written by mf_retrieve (int32 per column). */
+enum {
+  MF_COL_OK = 0,
+  MF_COL_FEW_PIXELS = 1, /* N_valid <= B: the sample covariance is singular */
+  MF_COL_NOT_SPD = 2,    /* Cholesky pivot <= 0, or t^T C^-1 t <= 0 */
+  MF_COL_NONFINITE = 3   /* a valid pixel holds NaN or Inf */
+};
+
+typedef enum {
+  MF_GRAM_FP32 = 0,      /* covariance Gram on FP32 MFMA, flushed to FP64 every 64 px */
+  MF_GRAM_BF16 = 1       /* Gram operands rounded to BF16 on MFMA (FP32 accumulate) */
+} mf_gram;
+
+typedef struct {
+  uint32_t struct_size;   /* = sizeof(mf_options); guards ABI drift */
+  int32_t  n_bands;       /* B, 2..MF_MAX_BANDS (74 for the 2122-2487 nm window) */
+  int32_t  n_iter;        /* K >= 0 reweighting iterations (the paper uses 30).
+                             K = 0 returns alpha^0 unclamped (the non-iterative
+                             filter, which has negative values). */
+  int32_t  albedo;        /* 1: r_i from Eq. 7; 0: r_i = 1 (Fig. 1 caption) */
+  double   lambda;        /* >= 0, weight scale: w = lambda / (alpha + eps).
+                             1 = the paper's Eq. 5; 0 = no sparsity prior. */
+  double   epsilon;       /* > 0, ppm*m (Eq. 5) */
+  int32_t  gram;          /* mf_gram */
+  int32_t  refine_steps;  /* iterative-refinement steps of C^-1 t (0..4; 1 = default) */
+  int32_t  save_for_backward; /* reserved, must be 0 in ABI version 1 */
+  int32_t  chunk_lines;   /* pixels per work item along a column (multiple of
+                             128; 0 = library default) */
+} mf_options;
+
+typedef struct {
+  int64_t first_px;       /* global index of pixel (column 0, line 0) */
+  int32_t n_columns;      /* detectors (cross-track), >= 1 */
+  int32_t n_lines;        /* along-track lines, >= 1 */
+} mf_flightline;
+
+/* Library ABI version (MF_ABI_VERSION). */
+MF_API int mf_abi_version(void);
+
+/* Fills *opt with defaults: B = 74, K = 30, albedo on, lambda 1, eps 1e-9,
+   FP32 Gram, one refinement step, automatic chunking. */
+MF_API void mf_options_default(mf_options* opt);
+
+/* Static text for a status code (never NULL). */
+MF_API const char* mf_status_str(mf_status s);
+
+/* Text of the last error raised on this thread by any mf_* call ("" if none). */
+MF_API const char* mf_last_error(void);
+
+/* Builds a plan for a batch of flightlines on the current HIP device.  The
+   flightline array is host memory and is copied.  The plan owns small device
+   tables (work items, column descriptors) allocated here; all per-call device
+   memory comes from the caller's workspace.  *out is NULL on error. */
+MF_API mf_status mf_plan_create(const mf_options* opt, const mf_flightline* flightlines,
+                         int32_t n_flightlines, mf_plan* out);
+
+/* Bytes of device workspace mf_retrieve needs (256-byte aligned start). */
+MF_API size_t mf_workspace_bytes(mf_plan plan);
+
+/* Total number of columns and of pixels (sum of n_columns * n_lines) of the plan. */
+MF_API int64_t mf_plan_columns(mf_plan plan);
+MF_API int64_t mf_plan_pixels(mf_plan plan);
+
+/* Runs Fig. 1 on every column of the plan.
+     radiance       [max_px][B] float32, uW cm^-2 sr^-1 nm^-1 (read only)
+     valid          [max_px] uint8, nonzero = valid pixel, or NULL (all valid).
+                    Invalid pixels are excluded from every mean and covariance
+                    (censored data is skipped, Sec. III-C) and get alpha = 0;
+                    their radiance values are ignored (the memory must exist).
+     s              [B] float32 unit absorption spectrum, (ppm*m)^-1 (Sec. II-D)
+     alpha          [max_px] float32 output, ppm*m; only the plan's pixels are written
+     column_status  [mf_plan_columns] int32 output (MF_COL_*), or NULL
+     workspace      device memory of mf_workspace_bytes(plan), 256-byte aligned;
+                    contents need not be initialised and are clobbered
+     stream         hipStream_t or NULL
+   max_px is the largest first_px + n_columns * n_lines over the flightlines.
+   Calls that share a workspace must be ordered on one stream. */
+MF_API mf_status mf_retrieve(mf_plan plan, const float* radiance, const uint8_t* valid,
+                      const float* s, float* alpha, int32_t* column_status,
+                      void* workspace, void* stream);
+
+/* Releases the plan and its device tables (synchronises the device first). */
+MF_API void mf_plan_destroy(mf_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MF_H */

@@ -1,0 +1,195 @@
+"""Python binding of libmf.so, the MI355X retrieval library (see include/mf.h).
+
+Argument marshalling only: every step of the retrieval runs in the library's
+HIP kernels.  PyTorch supplies device memory and the stream.  If the library
+is missing, importing the binding works but every call raises: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmf.so")
+
+MF_OK, MF_E_ARG, MF_E_SHAPE, MF_E_UNSUPPORTED, MF_E_DEVICE, MF_E_STATE = range(6)
+MF_COL_OK, MF_COL_FEW_PIXELS, MF_COL_NOT_SPD, MF_COL_NONFINITE = range(4)
+GRAM = {"fp32": 0, "bf16": 1}
+
+# Every symbol declared in include/mf.h.
+EXPORTS = ("mf_abi_version", "mf_options_default", "mf_status_str", "mf_last_error",
+           "mf_plan_create", "mf_workspace_bytes", "mf_plan_columns", "mf_plan_pixels",
+           "mf_retrieve", "mf_plan_destroy")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("n_bands", ctypes.c_int32),
+                ("n_iter", ctypes.c_int32), ("albedo", ctypes.c_int32),
+                ("lambda_", ctypes.c_double), ("epsilon", ctypes.c_double),
+                ("gram", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("save_for_backward", ctypes.c_int32), ("chunk_lines", ctypes.c_int32)]
+
+
+class Flightline(ctypes.Structure):
+    _fields_ = [("first_px", ctypes.c_int64), ("n_columns", ctypes.c_int32),
+                ("n_lines", ctypes.c_int32)]
+
+
+class MFError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mf error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmf.so (built by paper_2003_02978_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2003_02978_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.mf_abi_version.restype = ctypes.c_int
+    lib.mf_options_default.argtypes = [ctypes.POINTER(Options)]
+    lib.mf_status_str.restype = ctypes.c_char_p
+    lib.mf_status_str.argtypes = [ctypes.c_int]
+    lib.mf_last_error.restype = ctypes.c_char_p
+    lib.mf_plan_create.restype = ctypes.c_int
+    lib.mf_plan_create.argtypes = [ctypes.POINTER(Options), ctypes.POINTER(Flightline), i32,
+                                   ctypes.POINTER(vp)]
+    lib.mf_workspace_bytes.restype = sz
+    lib.mf_workspace_bytes.argtypes = [vp]
+    lib.mf_plan_columns.restype = i64
+    lib.mf_plan_columns.argtypes = [vp]
+    lib.mf_plan_pixels.restype = i64
+    lib.mf_plan_pixels.argtypes = [vp]
+    lib.mf_retrieve.restype = ctypes.c_int
+    lib.mf_retrieve.argtypes = [vp] * 8
+    lib.mf_plan_destroy.argtypes = [vp]
+    if lib.mf_abi_version() != 1:
+        raise ImportError("libmf.so ABI version mismatch")
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != MF_OK:
+        lib = load_library()
+        raise MFError(code, lib.mf_last_error().decode() or lib.mf_status_str(code).decode())
+
+
+def default_options() -> Options:
+    o = Options()
+    load_library().mf_options_default(ctypes.byref(o))
+    return o
+
+
+class Plan:
+    """A retrieval plan for a batch of flightlines (see mf_plan_create).
+
+    flightlines: iterable of (first_px, n_columns, n_lines).  Must be created
+    with the target GPU current (torch.cuda.set_device).
+    """
+
+    def __init__(self, flightlines: Iterable[Tuple[int, int, int]], n_bands: int = 74,
+                 n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9, albedo: bool = True,
+                 gram: str = "fp32", refine_steps: int = 1, chunk_lines: int = 0):
+        lib = load_library()
+        o = default_options()
+        o.n_bands, o.n_iter, o.albedo = n_bands, n_iter, int(bool(albedo))
+        o.lambda_, o.epsilon, o.gram = float(lam), float(eps), GRAM[gram]
+        o.refine_steps, o.chunk_lines = refine_steps, chunk_lines
+        fls = list(flightlines)
+        arr = (Flightline * max(1, len(fls)))(*[Flightline(int(a), int(b), int(c)) for a, b, c in fls])
+        h = ctypes.c_void_p()
+        _check(lib.mf_plan_create(ctypes.byref(o), arr, len(fls), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        self.options = o
+        self.flightlines = fls
+        self.n_bands = n_bands
+        self.workspace_bytes = int(lib.mf_workspace_bytes(h))
+        self.n_columns = int(lib.mf_plan_columns(h))
+        self.n_pixels = int(lib.mf_plan_pixels(h))
+        self.max_px = max(a + b * c for a, b, c in fls)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc_workspace(self, device=None):
+        import torch
+        return torch.empty(self.workspace_bytes + 256, dtype=torch.uint8,
+                           device=device or torch.cuda.current_device())
+
+    def retrieve(self, radiance, s, alpha, valid=None, column_status=None, workspace=None,
+                 stream=None):
+        """Enqueue one retrieval; tensors are CUDA tensors (contiguous)."""
+        import torch
+        B = self.n_bands
+        _need(radiance, torch.float32, "radiance")
+        _need(s, torch.float32, "s")
+        _need(alpha, torch.float32, "alpha")
+        if radiance.numel() < self.max_px * B or alpha.numel() < self.max_px or s.numel() != B:
+            raise ValueError("radiance/alpha/s are smaller than the plan's geometry")
+        if valid is not None:
+            _need(valid, torch.uint8, "valid")
+            if valid.numel() < self.max_px:
+                raise ValueError("valid is smaller than the plan's geometry")
+        if column_status is not None:
+            _need(column_status, torch.int32, "column_status")
+            if column_status.numel() < self.n_columns:
+                raise ValueError("column_status is smaller than the number of columns")
+        if workspace is None:
+            workspace = self.alloc_workspace(radiance.device)
+        ws = workspace.data_ptr()
+        ws_al = (ws + 255) & ~255
+        if ws_al + self.workspace_bytes > ws + workspace.numel() * workspace.element_size():
+            raise ValueError("workspace too small (allocate workspace_bytes + 256)")
+        if stream is None:
+            stream = torch.cuda.current_stream(radiance.device)
+        _check(self._lib.mf_retrieve(
+            self._h, radiance.data_ptr(), None if valid is None else valid.data_ptr(),
+            s.data_ptr(), alpha.data_ptr(),
+            None if column_status is None else column_status.data_ptr(), ws_al,
+            stream.cuda_stream))
+        return alpha
+
+
+def _need(t, dtype, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def retrieve(radiance, s, n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9,
+             albedo: bool = True, gram: str = "fp32", valid=None, refine_steps: int = 1,
+             chunk_lines: int = 0):
+    """Retrieve alpha (ppm*m) for a [S, N, B] float32 radiance cube on the GPU.
+
+    Returns (alpha [S, N] float32, column_status [S] int32), both on the GPU.
+    """
+    import torch
+    S, N, B = radiance.shape
+    plan = Plan([(0, S, N)], B, n_iter, lam, eps, albedo, gram, refine_steps, chunk_lines)
+    alpha = torch.empty((S, N), dtype=torch.float32, device=radiance.device)
+    status = torch.empty((S,), dtype=torch.int32, device=radiance.device)
+    plan.retrieve(radiance.contiguous(), s.contiguous(), alpha,
+                  None if valid is None else valid.contiguous(), status)
+    return alpha, status

@@ -1,0 +1,800 @@
+// MI355X (gfx950) kernels and C ABI of the albedo-corrected reweighted-l1
+// matched filter (Foote et al., IEEE TGRS 2020, Fig. 1; Eqs. 5-11).
+//
+// Data flow of one retrieval (one stream, no host synchronisation):
+//   setup      one wave per column: shift point z = first valid pixel
+//   pass j=0   per pixel y = L - z; Gram of [y, 1] on MFMA      -> partials
+//   solve j=0  FP64: mu^0, C^0, Cholesky, v^0 = C^0^-1 t^0, q^0  -> column state
+//   pass j     (1 <= j <= K+1) per pixel p = (L - mu^{j-1}).v^{j-1},
+//              r = L.mu^0/|mu^0|^2, alpha^{j-1} (soft threshold, Eq. 6/8),
+//              c = r alpha^{j-1}, y = L - mu^{j-1} - c t^{j-1};
+//              Gram of [y, 1, c] on MFMA (j <= K)               -> partials
+//   solve j    FP64: mu^j = mean(L) - mean(c) t^{j-1} (Eq. 10), the covariance
+//              of Eq. 11 from the shifted Gram, Cholesky, v^j, q^j
+// The last pass writes alpha^K to the caller's buffer and computes no Gram.
+//
+// Shifted Gram (exact algebra): with d_i = L_i - c_i t^j - mu^j the residual
+// of Eq. 11 and y_i as computed by the pass,
+//   d_i = y_i + D + c_i e,   D = mu_used - mu^j,   e = t_used - t^j,
+// where mu_used/t_used are the FP32 values the pass actually subtracted, so
+//   N C^j = G + g1 D^T + D g1^T + g2 e^T + e g2^T + N D D^T
+//           + S1 (D e^T + e D^T) + S2 e e^T,
+// G = sum y y^T, g1 = sum y, g2 = sum c y, S1 = sum c, S2 = sum c^2, N = sum 1.
+// The pass gets g1, g2, N, S1, S2 for free by appending the constants 1 and c
+// to each pixel's vector as two extra "bands" of the MFMA Gram.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mf.h"
+
+namespace {
+
+constexpr int kBlock = 256;      // 4 waves of 64
+constexpr int kPad = 80;         // bands of the per-column state (5 x 16)
+constexpr int kMaxTri = 80 * 81 / 2;
+constexpr int kDefaultChunk = 2048;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct ColInfo {
+  int64_t first_px;
+  int32_t n_lines;
+  int32_t first_item;
+  int32_t n_items;
+  int32_t pad;
+};
+
+struct WorkItem {
+  int64_t px_begin;
+  int32_t col;
+  int32_t n_px;
+};
+
+// Per-column state, written by the solve kernel and read by the next pass.
+struct alignas(16) ColState {
+  float mu_f[kPad];    // mean subtracted by the next pass (FP32)
+  float t_f[kPad];     // target t = mu (.) s used by the next pass (FP32)
+  float v_f[kPad];     // v = C^-1 t (FP32)
+  float m0_f[kPad];    // mu^0 / |mu^0|^2, the albedo projection of Eq. 7
+  double mu[kPad];     // FP64 mu^j
+  double t[kPad];      // FP64 t^j
+  double lbar[kPad];   // FP64 plain mean mu^0
+  double q;            // t^T C^-1 t
+  float q_f;
+  int32_t status;
+  int32_t pad[2];
+};
+
+struct PassArgs {
+  const float* L;
+  const uint8_t* valid;
+  const WorkItem* items;
+  const ColState* state;
+  const float* alpha_prev;   // alpha^{j-2} (j >= 2)
+  float* alpha_out;          // alpha^{j-1} (j >= 1)
+  double* partials;          // [item][T][16][16] FP64
+  int B;
+  int j;
+  int albedo;
+  int unclamped;             // K == 0: return alpha^0 without the clamp
+  float lam;
+  float eps;
+};
+
+struct SolveArgs {
+  const ColInfo* cols;
+  ColState* state;
+  const double* partials;
+  const float* s;
+  int B;
+  int j;
+  int refine;
+};
+
+__host__ __device__ constexpr int n_tiles(int nb) { return nb * (nb + 1) / 2; }
+__device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // j <= i
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+      0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 16 lanes of a DPP row (one pixel per row in the pass layout).
+__device__ __forceinline__ float row_sum16(float x) {
+  x += dpp<0xB1>(x);    // quad_perm [1,0,3,2]
+  x += dpp<0x4E>(x);    // quad_perm [2,3,0,1]
+  x += dpp<0x124>(x);   // row_ror:4
+  x += dpp<0x128>(x);   // row_ror:8
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// setup: per column, the shift point z (first valid pixel) and a clean state.
+
+__global__ void __launch_bounds__(64) setup_kernel(const float* __restrict__ L,
+                                                   const uint8_t* __restrict__ valid,
+                                                   const ColInfo* __restrict__ cols,
+                                                   ColState* __restrict__ state, int B) {
+  const int col = blockIdx.x;
+  const int lane = threadIdx.x;
+  const ColInfo ci = cols[col];
+  int64_t z = -1;
+  if (valid == nullptr) {
+    z = ci.n_lines > 0 ? ci.first_px : -1;
+  } else {
+    for (int64_t l0 = 0; l0 < ci.n_lines; l0 += 64) {
+      const bool v = (l0 + lane < ci.n_lines) && valid[ci.first_px + l0 + lane] != 0;
+      const unsigned long long m = __ballot(v);
+      if (m) {
+        z = ci.first_px + l0 + (__ffsll(m) - 1);
+        break;
+      }
+    }
+  }
+  ColState& st = state[col];
+  for (int b = lane; b < kPad; b += 64) {
+    st.mu_f[b] = (z >= 0 && b < B) ? L[z * B + b] : 0.f;
+    st.t_f[b] = 0.f;
+    st.v_f[b] = 0.f;
+    st.m0_f[b] = 0.f;
+    st.mu[b] = 0.0;
+    st.t[b] = 0.0;
+    st.lbar[b] = 0.0;
+  }
+  if (lane == 0) {
+    st.q = 1.0;
+    st.q_f = 1.f;
+    st.status = z >= 0 ? MF_COL_OK : MF_COL_FEW_PIXELS;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass: one streaming pass over a work item (a run of pixels of one column).
+//
+// Wave layout: a wave handles 4 pixels per sub-step, one per 16-lane row; the
+// lane in column c of the row holds bands c, c+16, ..., c+16(NB-1).  This is
+// at the same time the operand layout of v_mfma_f32_16x16x4_f32 (A[m][k] and
+// B[k][n] from lane m|n + 16k), so y of band block I against block J is one
+// MFMA per 4 pixels.  Eight sub-steps make a 32-pixel super-step, and the
+// same registers, packed to BF16, are the operands of v_mfma_f32_16x16x32_bf16
+// with pixel 4s+g of the super-step in k = 8g+s.  MFMA accumulators are
+// flushed to FP64 registers every FLUSH super-steps, which keeps the FP32
+// accumulation runs short (64 px for the FP32 Gram).
+
+template <int NB>
+__device__ __forceinline__ void load_super(const PassArgs& a, int64_t base, int64_t end,
+                                           int row, int c16, float (&Lv)[8][NB],
+                                           float (&ap)[8], unsigned& okmask) {
+  okmask = 0;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int64_t px = base + 4 * s + row;
+    const bool inb = px < end;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const int b = c16 + 16 * k;
+      Lv[s][k] = (inb && b < a.B) ? a.L[px * a.B + b] : 0.f;
+    }
+    ap[s] = (inb && a.alpha_prev) ? a.alpha_prev[px] : 0.f;
+    bool ok = inb;
+    if (inb && a.valid) ok = a.valid[px] != 0;
+    okmask |= (ok ? 1u : 0u) << s;
+  }
+}
+
+template <int NB, int GRAM, bool MOMENTS>
+__global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
+  constexpr int T = n_tiles(NB);
+  constexpr int FLUSH = GRAM == MF_GRAM_FP32 ? 2 : 8;   // super-steps between FP64 flushes
+  const WorkItem it = a.items[blockIdx.x];
+  const ColState& st = a.state[it.col];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int row = lane >> 4, c16 = lane & 15;
+  const int B = a.B;
+  const int64_t begin = it.px_begin, end = begin + it.n_px;
+
+  if (st.status != MF_COL_OK) {          // failed column: alpha = 0, no moments
+    if (a.alpha_out)
+      for (int64_t px = begin + tid; px < end; px += kBlock) a.alpha_out[px] = 0.f;
+    return;
+  }
+
+  float mu[NB], vv[NB], tt[NB], m0[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int b = c16 + 16 * k;
+    const bool in = b < B;
+    mu[k] = in ? st.mu_f[b] : 0.f;
+    vv[k] = in ? st.v_f[b] : 0.f;
+    tt[k] = in ? st.t_f[b] : 0.f;
+    m0[k] = in ? st.m0_f[b] : 0.f;
+  }
+  const float q = st.q_f;
+  const int j = a.j;
+
+  floatx4 acc[MOMENTS ? T : 1];
+  double acc64[MOMENTS ? T : 1][4];
+  if constexpr (MOMENTS) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc64[t][i] = 0.0;
+    }
+  }
+
+  float Lc[8][NB], apc[8];
+  unsigned okc;
+  int64_t base = begin + 32 * wid;
+  if (base < end) load_super<NB>(a, base, end, row, c16, Lc, apc, okc);
+  int nsuper = 0;
+
+  for (; base < end; base += 128) {
+    float Ln[8][NB], apn[8];
+    unsigned okn = 0;
+    if (base + 128 < end) load_super<NB>(a, base + 128, end, row, c16, Ln, apn, okn);
+
+    [[maybe_unused]] bf16x8 ybf[NB];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int64_t px = base + 4 * s + row;
+      const bool ok = (okc >> s) & 1u;
+      float x[NB];
+      float pp = 0.f, rr = 0.f;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const float l = ok ? Lc[s][k] : 0.f;
+        x[k] = ok ? l - mu[k] : 0.f;
+        pp = fmaf(x[k], vv[k], pp);
+        rr = fmaf(l, m0[k], rr);
+      }
+      pp = row_sum16(pp);
+      rr = row_sum16(rr);
+      float c = 0.f;
+      if (j >= 1) {
+        const float r = a.albedo ? rr : 1.f;
+        const float num = (j == 1) ? pp : pp - a.lam / (apc[s] + a.eps);
+        float al = num / (r * q);
+        const bool dark = !(r > 0.f);
+        if (!a.unclamped) al = al > 0.f ? al : 0.f;
+        if (!ok || dark) al = 0.f;
+        if (c16 == 0 && px < end) a.alpha_out[px] = al;
+        c = (ok && !dark && al > 0.f) ? r * al : 0.f;
+      }
+      if constexpr (MOMENTS) {
+        float y[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const int b = c16 + 16 * k;
+          y[k] = fmaf(-c, tt[k], x[k]);
+          if (b == B) y[k] = ok ? 1.f : 0.f;
+          if (b == B + 1) y[k] = c;
+        }
+        if constexpr (GRAM == MF_GRAM_FP32) {
+#pragma unroll
+          for (int I = 0; I < NB; ++I)
+#pragma unroll
+            for (int J = 0; J <= I; ++J)
+              acc[n_tiles(I) + J] =
+                  __builtin_amdgcn_mfma_f32_16x16x4f32(y[I], y[J], acc[n_tiles(I) + J], 0, 0, 0);
+        } else {
+#pragma unroll
+          for (int k = 0; k < NB; ++k) ybf[k][s] = (__bf16)y[k];
+        }
+      }
+    }
+    if constexpr (MOMENTS) {
+      if constexpr (GRAM == MF_GRAM_BF16) {
+#pragma unroll
+        for (int I = 0; I < NB; ++I)
+#pragma unroll
+          for (int J = 0; J <= I; ++J)
+            acc[n_tiles(I) + J] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(ybf[I], ybf[J], acc[n_tiles(I) + J], 0, 0, 0);
+      }
+      if (++nsuper == FLUSH) {
+        nsuper = 0;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc64[t][i] += (double)acc[t][i];
+          acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      apc[s] = apn[s];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) Lc[s][k] = Ln[s][k];
+    }
+    okc = okn;
+  }
+
+  if constexpr (MOMENTS) {
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc64[t][i] += (double)acc[t][i];
+    // Deterministic cross-wave reduction in LDS, wave 0 first.
+    __shared__ double red[T * 256];
+    for (int w = 0; w < 4; ++w) {
+      if (wid == w) {
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            // D[m][n] of tile t lives in lane n + 16 (m / 4), register m % 4
+            const int e = t * 256 + (4 * row + i) * 16 + c16;
+            red[e] = (w == 0 ? 0.0 : red[e]) + acc64[t][i];
+          }
+      }
+      __syncthreads();
+    }
+    double* out = a.partials + (int64_t)blockIdx.x * (T * 256);
+    for (int e = tid; e < T * 256; e += kBlock) out[e] = red[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// solve: per column, FP64 combine of the partial Grams, the covariance of
+// Eq. 11 (or the sample covariance for j = 0), Cholesky, v = C^-1 t with
+// iterative refinement, q = t^T v.
+
+template <int NB>
+__device__ __forceinline__ double gram_elem(const double* __restrict__ P, int n_items,
+                                            int i, int j) {  // i >= j
+  constexpr int T = n_tiles(NB);
+  const int I = i >> 4, J = j >> 4;
+  const int e = (n_tiles(I) + J) * 256 + (i & 15) * 16 + (j & 15);
+  double g = 0.0;
+  for (int it = 0; it < n_items; ++it) g += P[(int64_t)it * T * 256 + e];
+  return g;
+}
+
+__device__ void chol_solve(const double* A, double* y, int B, int tid) {
+  // forward: L y' = y
+  for (int k = 0; k < B; ++k) {
+    if (tid == 0) y[k] /= A[tri(k, k)];
+    __syncthreads();
+    for (int i = k + 1 + tid; i < B; i += kBlock) y[i] -= A[tri(i, k)] * y[k];
+    __syncthreads();
+  }
+  // backward: L^T v = y'
+  for (int k = B - 1; k >= 0; --k) {
+    if (tid == 0) y[k] /= A[tri(k, k)];
+    __syncthreads();
+    for (int i = tid; i < k; i += kBlock) y[i] -= A[tri(k, i)] * y[k];
+    __syncthreads();
+  }
+}
+
+template <int NB>
+__global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
+  const int col = blockIdx.x;
+  const int tid = threadIdx.x;
+  ColState& st = a.state[col];
+  if (st.status != MF_COL_OK) return;
+  const ColInfo ci = a.cols[col];
+  const int B = a.B;
+  const int j = a.j;
+  constexpr int T = n_tiles(NB);
+  const double* P = a.partials + (int64_t)ci.first_item * T * 256;
+
+  __shared__ double A0[kMaxTri];     // C (kept for refinement)
+  __shared__ double A[kMaxTri];      // its Cholesky factor
+  __shared__ double g1[kPad], g2[kPad], D[kPad], E[kPad], tn[kPad], mun[kPad];
+  __shared__ double vv[kPad], rr[kPad];
+  __shared__ double sc[4];
+  __shared__ int fail;
+
+  if (tid == 0) {
+    sc[0] = gram_elem<NB>(P, ci.n_items, B, B);          // N
+    sc[1] = gram_elem<NB>(P, ci.n_items, B + 1, B);      // S1 = sum c
+    sc[2] = gram_elem<NB>(P, ci.n_items, B + 1, B + 1);  // S2 = sum c^2
+    fail = 0;
+  }
+  for (int b = tid; b < B; b += kBlock) {
+    g1[b] = gram_elem<NB>(P, ci.n_items, B, b);
+    g2[b] = gram_elem<NB>(P, ci.n_items, B + 1, b);
+  }
+  __syncthreads();
+  const double N = sc[0], S1 = sc[1], S2 = sc[2];
+  for (int b = tid; b < B; b += kBlock) {
+    const double mu_used = (double)st.mu_f[b];
+    const double t_used = (double)st.t_f[b];
+    const double sb = (double)a.s[b];
+    double m;
+    if (j == 0) {
+      m = mu_used + g1[b] / N;                 // mu^0 = z + mean(L - z)
+    } else {
+      m = st.lbar[b] - (S1 / N) * st.t[b];     // Eq. 10: mean(L) - mean(c) t^{j-1}
+    }
+    mun[b] = m;
+    tn[b] = m * sb;                            // Eq. 9
+    D[b] = mu_used - m;
+    E[b] = j == 0 ? 0.0 : t_used - tn[b];
+  }
+  __syncthreads();
+  const int npk = B * (B + 1) / 2;
+  for (int p = tid; p < npk; p += kBlock) {
+    int i = (int)((sqrtf(8.f * p + 1.f) - 1.f) * 0.5f);
+    while (tri(i, 0) > p) --i;
+    while (tri(i + 1, 0) <= p) ++i;
+    const int jj = p - tri(i, 0);
+    double c = gram_elem<NB>(P, ci.n_items, i, jj);
+    c += g1[i] * D[jj] + D[i] * g1[jj] + g2[i] * E[jj] + E[i] * g2[jj] + N * D[i] * D[jj] +
+         S1 * (D[i] * E[jj] + E[i] * D[jj]) + S2 * E[i] * E[jj];
+    c /= N;
+    if (!isfinite(c)) fail = 1;
+    A0[p] = c;
+    A[p] = c;
+  }
+  __syncthreads();
+  if (N <= (double)B) {
+    if (tid == 0) st.status = MF_COL_FEW_PIXELS;
+    return;
+  }
+  if (j == 0 && fail) {
+    if (tid == 0) st.status = MF_COL_NONFINITE;
+    return;
+  }
+  if (fail) {
+    if (tid == 0) st.status = MF_COL_NOT_SPD;
+    return;
+  }
+  // Right-looking Cholesky, packed lower triangle.
+  for (int k = 0; k < B; ++k) {
+    if (tid == 0) {
+      const double d = A[tri(k, k)];
+      if (!(d > 0.0) || !isfinite(d)) fail = 1;
+      A[tri(k, k)] = sqrt(d > 0.0 ? d : 1.0);
+    }
+    __syncthreads();
+    if (fail) break;
+    const double piv = A[tri(k, k)];
+    for (int i = k + 1 + tid; i < B; i += kBlock) A[tri(i, k)] /= piv;
+    __syncthreads();
+    const int m = B - 1 - k;
+    const int ne = m * (m + 1) / 2;
+    for (int e = tid; e < ne; e += kBlock) {
+      int ii = (int)((sqrtf(8.f * e + 1.f) - 1.f) * 0.5f);
+      while (tri(ii, 0) > e) --ii;
+      while (tri(ii + 1, 0) <= e) ++ii;
+      const int i = k + 1 + ii, jx = k + 1 + (e - tri(ii, 0));
+      A[tri(i, jx)] -= A[tri(i, k)] * A[tri(jx, k)];
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (tid == 0) st.status = MF_COL_NOT_SPD;
+    return;
+  }
+  for (int b = tid; b < B; b += kBlock) vv[b] = tn[b];
+  __syncthreads();
+  chol_solve(A, vv, B, tid);
+  for (int step = 0; step < a.refine; ++step) {
+    for (int i = tid; i < B; i += kBlock) {
+      double acc = tn[i];
+      for (int k = 0; k < B; ++k) acc -= A0[i >= k ? tri(i, k) : tri(k, i)] * vv[k];
+      rr[i] = acc;
+    }
+    __syncthreads();
+    chol_solve(A, rr, B, tid);
+    for (int i = tid; i < B; i += kBlock) vv[i] += rr[i];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double q = 0.0, m2 = 0.0;
+    for (int b = 0; b < B; ++b) {
+      q += tn[b] * vv[b];
+      m2 += mun[b] * mun[b];
+    }
+    sc[3] = m2;
+    st.q = q;
+    st.q_f = (float)q;
+    if (!(q > 0.0) || !isfinite(q)) st.status = MF_COL_NOT_SPD;
+  }
+  __syncthreads();
+  for (int b = tid; b < kPad; b += kBlock) {
+    const bool in = b < B;
+    st.mu[b] = in ? mun[b] : 0.0;
+    st.t[b] = in ? tn[b] : 0.0;
+    st.mu_f[b] = in ? (float)mun[b] : 0.f;
+    st.t_f[b] = in ? (float)tn[b] : 0.f;
+    st.v_f[b] = in ? (float)vv[b] : 0.f;
+    if (j == 0) {
+      st.lbar[b] = in ? mun[b] : 0.0;
+      st.m0_f[b] = in ? (float)(mun[b] / sc[3]) : 0.f;
+    }
+  }
+}
+
+__global__ void status_kernel(const ColState* __restrict__ state, int32_t* __restrict__ out,
+                              int64_t n) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) out[c] = state[c].status;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+
+thread_local std::string g_last_error;
+
+mf_status fail_with(mf_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct mf_plan_s {
+  mf_options opt;
+  int nb = 0;
+  int device = 0;
+  int64_t n_cols = 0, n_items = 0, n_px = 0, max_px = 0;
+  ColInfo* cols_d = nullptr;
+  WorkItem* items_d = nullptr;
+  size_t off_state = 0, off_partials = 0, off_alpha0 = 0, off_alpha1 = 0, ws_bytes = 0;
+};
+
+namespace {
+
+template <int NB, int GRAM, bool MOM>
+void launch_pass(const mf_plan_s* p, const PassArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((pass_kernel<NB, GRAM, MOM>), dim3((unsigned)p->n_items), dim3(kBlock), 0,
+                     s, a);
+}
+
+template <int NB>
+void launch_pass_nb(const mf_plan_s* p, const PassArgs& a, bool mom, hipStream_t s) {
+  if (p->opt.gram == MF_GRAM_FP32) {
+    if (mom) launch_pass<NB, MF_GRAM_FP32, true>(p, a, s);
+    else launch_pass<NB, MF_GRAM_FP32, false>(p, a, s);
+  } else {
+    if (mom) launch_pass<NB, MF_GRAM_BF16, true>(p, a, s);
+    else launch_pass<NB, MF_GRAM_BF16, false>(p, a, s);
+  }
+}
+
+void dispatch_pass(const mf_plan_s* p, const PassArgs& a, bool mom, hipStream_t s) {
+  switch (p->nb) {
+    case 1: launch_pass_nb<1>(p, a, mom, s); break;
+    case 2: launch_pass_nb<2>(p, a, mom, s); break;
+    case 3: launch_pass_nb<3>(p, a, mom, s); break;
+    case 4: launch_pass_nb<4>(p, a, mom, s); break;
+    default: launch_pass_nb<5>(p, a, mom, s); break;
+  }
+}
+
+void dispatch_solve(const mf_plan_s* p, const SolveArgs& a, hipStream_t s) {
+  const dim3 g((unsigned)p->n_cols), b(kBlock);
+  switch (p->nb) {
+    case 1: hipLaunchKernelGGL(solve_kernel<1>, g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(solve_kernel<2>, g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(solve_kernel<3>, g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(solve_kernel<4>, g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL(solve_kernel<5>, g, b, 0, s, a); break;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mf_abi_version(void) { return MF_ABI_VERSION; }
+
+void mf_options_default(mf_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(mf_options);
+  o->n_bands = 74;
+  o->n_iter = 30;
+  o->albedo = 1;
+  o->lambda = 1.0;
+  o->epsilon = 1e-9;
+  o->gram = MF_GRAM_FP32;
+  o->refine_steps = 1;
+  o->save_for_backward = 0;
+  o->chunk_lines = 0;
+}
+
+const char* mf_status_str(mf_status s) {
+  switch (s) {
+    case MF_OK: return "ok";
+    case MF_E_ARG: return "invalid argument";
+    case MF_E_SHAPE: return "invalid shape";
+    case MF_E_UNSUPPORTED: return "unsupported configuration";
+    case MF_E_DEVICE: return "HIP runtime error";
+    case MF_E_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* mf_last_error(void) { return g_last_error.c_str(); }
+
+mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t n_fl,
+                         mf_plan* out) {
+  if (!out) return fail_with(MF_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!opt || !fl) return fail_with(MF_E_ARG, "options or flightlines is NULL");
+  if (opt->struct_size != sizeof(mf_options))
+    return fail_with(MF_E_ARG, "mf_options.struct_size mismatch");
+  if (opt->n_bands < 2 || opt->n_bands > MF_MAX_BANDS)
+    return fail_with(MF_E_UNSUPPORTED, "n_bands must be in [2, 78]");
+  if (opt->n_iter < 0) return fail_with(MF_E_ARG, "n_iter must be >= 0");
+  if (!(opt->lambda >= 0.0) || !std::isfinite(opt->lambda))
+    return fail_with(MF_E_ARG, "lambda must be finite and >= 0");
+  if (!(opt->epsilon > 0.0) || !std::isfinite(opt->epsilon))
+    return fail_with(MF_E_ARG, "epsilon must be finite and > 0");
+  if (opt->albedo != 0 && opt->albedo != 1) return fail_with(MF_E_ARG, "albedo must be 0 or 1");
+  if (opt->gram != MF_GRAM_FP32 && opt->gram != MF_GRAM_BF16)
+    return fail_with(MF_E_ARG, "gram must be MF_GRAM_FP32 or MF_GRAM_BF16");
+  if (opt->refine_steps < 0 || opt->refine_steps > 4)
+    return fail_with(MF_E_ARG, "refine_steps must be in [0, 4]");
+  if (opt->save_for_backward != 0)
+    return fail_with(MF_E_UNSUPPORTED, "save_for_backward is not available in ABI version 1");
+  if (opt->chunk_lines < 0 || opt->chunk_lines % 128 != 0)
+    return fail_with(MF_E_ARG, "chunk_lines must be a non-negative multiple of 128");
+  if (n_fl < 1) return fail_with(MF_E_SHAPE, "need at least one flightline");
+
+  const int chunk = opt->chunk_lines ? opt->chunk_lines : kDefaultChunk;
+  std::vector<ColInfo> cols;
+  std::vector<WorkItem> items;
+  std::vector<std::pair<int64_t, int64_t>> ranges;
+  int64_t n_px = 0, max_px = 0;
+  for (int f = 0; f < n_fl; ++f) {
+    const mf_flightline& F = fl[f];
+    if (F.n_columns < 1 || F.n_lines < 1 || F.first_px < 0)
+      return fail_with(MF_E_SHAPE, "flightline " + std::to_string(f) + " has an empty or negative shape");
+    const int64_t np = (int64_t)F.n_columns * F.n_lines;
+    ranges.push_back({F.first_px, F.first_px + np});
+    n_px += np;
+    max_px = std::max(max_px, F.first_px + np);
+    for (int c = 0; c < F.n_columns; ++c) {
+      ColInfo ci{};
+      ci.first_px = F.first_px + (int64_t)c * F.n_lines;
+      ci.n_lines = F.n_lines;
+      ci.first_item = (int32_t)items.size();
+      const int nit = (F.n_lines + chunk - 1) / chunk;
+      // split evenly, in multiples of 128 pixels
+      int per = (F.n_lines + nit - 1) / nit;
+      per = (per + 127) / 128 * 128;
+      int done = 0;
+      for (int k = 0; k < nit && done < F.n_lines; ++k) {
+        WorkItem w{};
+        w.px_begin = ci.first_px + done;
+        w.col = (int32_t)cols.size();
+        w.n_px = std::min(per, F.n_lines - done);
+        done += w.n_px;
+        items.push_back(w);
+      }
+      ci.n_items = (int32_t)items.size() - ci.first_item;
+      cols.push_back(ci);
+      if (items.size() > (size_t)INT32_MAX) return fail_with(MF_E_SHAPE, "too many work items");
+    }
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t i = 1; i < ranges.size(); ++i)
+    if (ranges[i].first < ranges[i - 1].second)
+      return fail_with(MF_E_SHAPE, "flightline pixel ranges overlap");
+
+  mf_plan_s* p = new (std::nothrow) mf_plan_s();
+  if (!p) return fail_with(MF_E_ARG, "out of host memory");
+  p->opt = *opt;
+  p->nb = (opt->n_bands + 2 + 15) / 16;
+  p->n_cols = (int64_t)cols.size();
+  p->n_items = (int64_t)items.size();
+  p->n_px = n_px;
+  p->max_px = max_px;
+  if (hipGetDevice(&p->device) != hipSuccess ||
+      hipMalloc(&p->cols_d, cols.size() * sizeof(ColInfo)) != hipSuccess ||
+      hipMalloc(&p->items_d, items.size() * sizeof(WorkItem)) != hipSuccess ||
+      hipMemcpy(p->cols_d, cols.data(), cols.size() * sizeof(ColInfo), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->items_d, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice) != hipSuccess) {
+    const std::string e = hipGetErrorString(hipGetLastError());
+    if (p->cols_d) (void)hipFree(p->cols_d);
+    if (p->items_d) (void)hipFree(p->items_d);
+    delete p;
+    return fail_with(MF_E_DEVICE, "plan tables: " + e);
+  }
+  const size_t T = (size_t)n_tiles(p->nb);
+  size_t off = 0;
+  p->off_state = off;
+  off = align256(off + (size_t)p->n_cols * sizeof(ColState));
+  p->off_partials = off;
+  off = align256(off + (size_t)p->n_items * T * 256 * sizeof(double));
+  p->off_alpha0 = off;
+  off = align256(off + (size_t)max_px * sizeof(float));
+  p->off_alpha1 = off;
+  off = align256(off + (size_t)max_px * sizeof(float));
+  p->ws_bytes = off;
+  *out = p;
+  g_last_error.clear();
+  return MF_OK;
+}
+
+size_t mf_workspace_bytes(mf_plan p) { return p ? p->ws_bytes : 0; }
+int64_t mf_plan_columns(mf_plan p) { return p ? p->n_cols : 0; }
+int64_t mf_plan_pixels(mf_plan p) { return p ? p->n_px : 0; }
+
+mf_status mf_retrieve(mf_plan p, const float* radiance, const uint8_t* valid, const float* s,
+                      float* alpha, int32_t* column_status, void* workspace, void* stream) {
+  if (!p) return fail_with(MF_E_ARG, "plan is NULL");
+  if (!radiance || !s || !alpha || !workspace)
+    return fail_with(MF_E_ARG, "radiance, s, alpha and workspace must be non-NULL");
+  if (((uintptr_t)workspace & 255) != 0) return fail_with(MF_E_ARG, "workspace must be 256-byte aligned");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail_with(MF_E_DEVICE, "current device differs from the plan's device");
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  ColState* state = (ColState*)(ws + p->off_state);
+  double* partials = (double*)(ws + p->off_partials);
+  float* abuf[2] = {(float*)(ws + p->off_alpha0), (float*)(ws + p->off_alpha1)};
+  const int B = p->opt.n_bands;
+  const int K = p->opt.n_iter;
+
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(setup_kernel, dim3((unsigned)p->n_cols), dim3(64), 0, st, radiance, valid,
+                     p->cols_d, state, B);
+  PassArgs pa{};
+  pa.L = radiance;
+  pa.valid = valid;
+  pa.items = p->items_d;
+  pa.state = state;
+  pa.partials = partials;
+  pa.B = B;
+  pa.albedo = p->opt.albedo;
+  pa.lam = (float)p->opt.lambda;
+  pa.eps = (float)p->opt.epsilon;
+  SolveArgs sa{};
+  sa.cols = p->cols_d;
+  sa.state = state;
+  sa.partials = partials;
+  sa.s = s;
+  sa.B = B;
+  sa.refine = p->opt.refine_steps;
+  for (int j = 0; j <= K + 1; ++j) {
+    pa.j = j;
+    pa.unclamped = (j == 1 && K == 0) ? 1 : 0;
+    pa.alpha_prev = j >= 2 ? abuf[(j - 2) & 1] : nullptr;
+    pa.alpha_out = j == K + 1 ? alpha : (j >= 1 ? abuf[(j - 1) & 1] : nullptr);
+    const bool mom = j <= K;
+    dispatch_pass(p, pa, mom, st);
+    if (mom) {
+      sa.j = j;
+      dispatch_solve(p, sa, st);
+    }
+  }
+  if (column_status) {
+    const unsigned nb = (unsigned)((p->n_cols + 255) / 256);
+    hipLaunchKernelGGL(status_kernel, dim3(nb), dim3(256), 0, st, state, column_status, p->n_cols);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail_with(MF_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+  return MF_OK;
+}
+
+void mf_plan_destroy(mf_plan p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  if (p->cols_d) (void)hipFree(p->cols_d);
+  if (p->items_d) (void)hipFree(p->items_d);
+  delete p;
+}
+
+}  // extern "C"

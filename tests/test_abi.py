@@ -1,0 +1,86 @@
+"""C ABI contract checks that need no GPU: the library loads, exports every
+symbol include/mf.h declares, and rejects bad arguments on the host before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2003_02978_amd as mf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mf.h")).read()
+    return sorted(set(re.findall(r"MF_API\s+[\w\s\*]+?\b(mf_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mf.load_library()
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(mf.EXPORTS)
+    assert lib.mf_abi_version() == 1
+
+
+def test_options_default_and_struct_layout():
+    o = mf.default_options()
+    assert o.struct_size == ctypes.sizeof(mf.Options)
+    assert (o.n_bands, o.n_iter, o.albedo, o.gram, o.refine_steps) == (74, 30, 1, 0, 1)
+    assert o.lambda_ == 1.0 and o.epsilon == 1e-9
+
+
+def _create(**kw):
+    lib = mf.load_library()
+    o = mf.default_options()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    fl = (mf.Flightline * 1)(mf.Flightline(0, 4, 1000))
+    h = ctypes.c_void_p()
+    rc = lib.mf_plan_create(ctypes.byref(o), fl, 1, ctypes.byref(h))
+    return rc, h, lib.mf_last_error().decode()
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("struct_size", 8, mf.MF_E_ARG),
+    ("n_bands", 1, mf.MF_E_UNSUPPORTED),
+    ("n_bands", 79, mf.MF_E_UNSUPPORTED),
+    ("n_iter", -1, mf.MF_E_ARG),
+    ("lambda_", -1.0, mf.MF_E_ARG),
+    ("lambda_", float("nan"), mf.MF_E_ARG),
+    ("epsilon", 0.0, mf.MF_E_ARG),
+    ("albedo", 2, mf.MF_E_ARG),
+    ("gram", 7, mf.MF_E_ARG),
+    ("refine_steps", 9, mf.MF_E_ARG),
+    ("chunk_lines", 100, mf.MF_E_ARG),
+    ("save_for_backward", 1, mf.MF_E_UNSUPPORTED),
+])
+def test_bad_options_rejected_on_host(field, value, code):
+    rc, h, msg = _create(**{field: value})
+    assert rc == code and not h.value and msg
+
+
+def test_bad_geometry_rejected_on_host():
+    lib = mf.load_library()
+    o = mf.default_options()
+    h = ctypes.c_void_p()
+    fl = (mf.Flightline * 2)(mf.Flightline(0, 4, 1000), mf.Flightline(3000, 2, 1000))
+    assert lib.mf_plan_create(ctypes.byref(o), fl, 2, ctypes.byref(h)) == mf.MF_E_SHAPE
+    assert b"overlap" in lib.mf_last_error()
+    fl = (mf.Flightline * 1)(mf.Flightline(0, 0, 1000))
+    assert lib.mf_plan_create(ctypes.byref(o), fl, 1, ctypes.byref(h)) == mf.MF_E_SHAPE
+    assert lib.mf_plan_create(ctypes.byref(o), fl, 0, ctypes.byref(h)) == mf.MF_E_SHAPE
+    assert lib.mf_plan_create(None, fl, 1, ctypes.byref(h)) == mf.MF_E_ARG
+    assert lib.mf_plan_create(ctypes.byref(o), fl, 1, None) == mf.MF_E_ARG
+
+
+def test_null_arguments_of_retrieve():
+    lib = mf.load_library()
+    assert lib.mf_retrieve(None, None, None, None, None, None, None, None) == mf.MF_E_ARG
+    assert lib.mf_workspace_bytes(None) == 0
+    lib.mf_plan_destroy(None)
+    assert lib.mf_status_str(3) == b"unsupported configuration"

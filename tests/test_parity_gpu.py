@@ -1,0 +1,132 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded scenes.  Sizes span several work items per column and ragged
+tails; the full-size flightline is checked on sampled columns."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2003_02978_amd as mf  # noqa: E402
+from oracle.mf64 import retrieve as oracle_retrieve  # noqa: E402
+from synth.scenes import SceneSpec, make_scene, tiny_spec, flightline_spec, make_globals, make_column  # noqa: E402
+from tests.parity_util import assert_fp32_parity, compare, config_lambda  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _gpu(sc, **kw):
+    L = torch.from_numpy(sc.radiance).to(DEV)
+    s = torch.from_numpy(sc.s).to(DEV)
+    valid = None if sc.valid is None else torch.from_numpy(sc.valid).to(DEV)
+    a, st = mf.retrieve(L, s, valid=valid, **kw)
+    torch.cuda.synchronize()
+    return a.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return make_scene(tiny_spec())
+
+
+@pytest.mark.parametrize("chunk", [0, 128])
+def test_tiny_scene_fp32(tiny, chunk):
+    lam = config_lambda("tiny")
+    a, st = _gpu(tiny, n_iter=30, lam=lam, chunk_lines=chunk)
+    ref, rst = oracle_retrieve(tiny.radiance, tiny.s, 30, lam, workers=8)
+    np.testing.assert_array_equal(st, rst)
+    assert np.all(a >= 0)
+    assert_fp32_parity(a, ref, label=f"tiny chunk={chunk}")
+
+
+@pytest.mark.parametrize("albedo", [True, False])
+def test_zero_iterations_is_the_unclamped_filter(tiny, albedo):
+    a, st = _gpu(tiny, n_iter=0, lam=1.0, albedo=albedo)
+    ref, _ = oracle_retrieve(tiny.radiance, tiny.s, 0, 1.0, albedo=albedo, workers=8)
+    assert (a < 0).any()
+    assert_fp32_parity(a, ref, iterative=False, label=f"K=0 albedo={albedo}")
+
+
+@pytest.mark.parametrize("lam,albedo,K", [(0.0, True, 5), (0.0, False, 5), (1.0, False, 12)])
+def test_variants(tiny, lam, albedo, K):
+    sub = make_scene(tiny_spec())
+    sub.radiance = sub.radiance[:16].copy()
+    a, _ = _gpu(sub, n_iter=K, lam=lam, albedo=albedo)
+    ref, _ = oracle_retrieve(sub.radiance, sub.s, K, lam, albedo=albedo, workers=8)
+    assert_fp32_parity(a, ref, label=f"lam={lam} albedo={albedo} K={K}")
+
+
+def test_ragged_lengths_and_many_items():
+    spec = SceneSpec(6, 1000, 74, 2, (500.0, 5000.0), (3.0, 30.0), seed=5)
+    sc = make_scene(spec)
+    for chunk in (128, 256, 0):
+        a, st = _gpu(sc, n_iter=15, lam=3.0, chunk_lines=chunk)
+        ref, rst = oracle_retrieve(sc.radiance, sc.s, 15, 3.0)
+        np.testing.assert_array_equal(st, rst)
+        assert_fp32_parity(a, ref, label=f"ragged chunk={chunk}")
+
+
+def test_masks_skip_invalid_pixels():
+    spec = SceneSpec(8, 1500, 74, 3, (500.0, 5000.0), (3.0, 30.0), seed=9, mask_max_frac=0.2)
+    sc = make_scene(spec)
+    a, st = _gpu(sc, n_iter=20, lam=3.0, chunk_lines=512)
+    ref, rst = oracle_retrieve(sc.radiance, sc.s, 20, 3.0, valid=sc.valid)
+    np.testing.assert_array_equal(st, rst)
+    assert np.all(a[sc.valid == 0] == 0)
+    assert np.all(np.isfinite(a))
+    assert_fp32_parity(a, ref, label="masked")
+
+
+def test_degenerate_columns_get_status_and_zero():
+    spec = SceneSpec(4, 600, 74, 1, (500.0, 5000.0), (3.0, 30.0), seed=11, mask_max_frac=0.0)
+    sc = make_scene(spec)
+    valid = np.ones((4, 600), np.uint8)
+    valid[0, 50:] = 0               # 50 valid pixels <= 74 bands
+    sc.radiance[0, 50:] = np.nan
+    sc.radiance[1, 123, 7] = np.nan  # a valid pixel with NaN
+    valid[3, :] = 0                  # no valid pixel at all
+    sc.valid = valid
+    a, st = _gpu(sc, n_iter=5, lam=2.0)
+    ref, rst = oracle_retrieve(sc.radiance, sc.s, 5, 2.0, valid=valid)
+    assert list(st) == [mf.MF_COL_FEW_PIXELS, mf.MF_COL_NONFINITE, mf.MF_COL_OK,
+                        mf.MF_COL_FEW_PIXELS]
+    np.testing.assert_array_equal(st, rst)
+    assert np.all(a[[0, 1, 3]] == 0)
+    assert_fp32_parity(a[2:3], ref[2:3], label="degenerate, healthy column")
+
+
+def test_bf16_gram_reports_error(tiny):
+    lam = config_lambda("tiny")
+    a, st = _gpu(tiny, n_iter=30, lam=lam, gram="bf16")
+    ref, _ = oracle_retrieve(tiny.radiance, tiny.s, 30, lam, workers=8)
+    rep = compare(a, ref)
+    print("bf16 vs FP64:", rep, flush=True)
+    assert rep["pattern_agreement"] >= 0.99
+    assert rep["rmse"] < 50.0
+
+
+def test_deterministic_and_column_independent(tiny):
+    lam = config_lambda("tiny")
+    a1, _ = _gpu(tiny, n_iter=30, lam=lam)
+    a2, _ = _gpu(tiny, n_iter=30, lam=lam)
+    np.testing.assert_array_equal(a1, a2)
+    sub = make_scene(tiny_spec())
+    sub.radiance = sub.radiance[17:18].copy()
+    a3, _ = _gpu(sub, n_iter=30, lam=lam)
+    np.testing.assert_array_equal(a3[0], a1[17])
+
+
+def test_full_flightline_sampled_columns():
+    """598 x 8000 x 74, 30 iterations, the benchmark's launch configuration;
+    columns through plumes and random columns are recomputed by the oracle."""
+    spec = flightline_spec()
+    lam = config_lambda("flightline")
+    sc = make_scene(spec)
+    a, st = _gpu(sc, n_iter=30, lam=lam)
+    assert np.all(st == 0)
+    g = make_globals(spec)
+    rng = np.random.default_rng(0)
+    cols = sorted(set([int(g.plumes[i, 0]) for i in range(3)] + list(rng.choice(598, 3, replace=False))))
+    ref, _ = oracle_retrieve(sc.radiance, sc.s, 30, lam, columns=cols, workers=6)
+    assert_fp32_parity(a[cols], ref, label=f"flightline cols {cols}")

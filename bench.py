@@ -1,0 +1,200 @@
+"""Throughput benchmark of the MI355X retrieval on one full flightline.
+
+Workload: 598 columns x 8000 lines x 74 bands (FP32 radiance, synthetic, seeded),
+30 reweighting iterations, lambda from configs/flightline.json.  One "step" is
+one whole retrieval (every pass of the hot path) of the flightline, with the
+radiance already resident in HBM.
+
+Prints ONE JSON line (rank 0).  Usage:
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms lowrank,fp64,fp32,bf16]
+                    [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "retrieved pixels/s (74 bands, 30 iters): BF16-MFMA vs FP32 plain; fwd+bwd px/s"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes of one streaming pass per pixel: the 74-band FP32
+# spectrum, alpha^{j-2} read and alpha^{j-1} written.
+PASS_BYTES_PER_PX = 74 * 4 + 4 + 4
+SOURCE = os.path.join(ROOT, "paper_2003_02978_amd", "csrc", "mf.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest():
+    return hashlib.sha256(open(SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--forms", default="lowrank,fp64,fp32,bf16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n-lines", type=int, default=8000)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: every column is an independent problem, "
+              "so N GPUs would each run their own share; run it with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2003_02978_amd as mf
+    from synth.scenes import flightline_spec, make_scene
+
+    cfg = json.load(open(os.path.join(ROOT, "configs", "flightline.json")))
+    lam, K, eps = cfg["lambda"], cfg["n_iter"], cfg["epsilon"]
+    spec = flightline_spec(n_lines=args.n_lines)
+    t0 = time.time()
+    sc = make_scene(spec)
+    S, N, B = sc.radiance.shape
+    n_px = S * N
+    log(f"scene {S}x{N}x{B} generated in {time.time() - t0:.1f}s")
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    L = torch.from_numpy(sc.radiance).to(dev)
+    s = torch.from_numpy(sc.s).to(dev)
+    alpha = torch.empty((S, N), dtype=torch.float32, device=dev)
+    status = torch.empty((S,), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    forms = [f for f in args.forms.split(",") if f]
+    head = forms[0]
+    results = {}
+    outputs = {}
+    for form in forms:
+        plan = mf.Plan([(0, S, N)], B, K, lam, eps, True, form)
+        ws = plan.alloc_workspace(dev)
+        for _ in range(args.warmup):
+            plan.retrieve(L, s, alpha, None, status, ws)
+        torch.cuda.synchronize()
+        steps = args.steps if form == head else max(3, args.steps // 4)
+        # timed region (no instrumentation)
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            plan.retrieve(L, s, alpha, None, status, ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        # instrumented region: per-kernel durations from HIP events recorded on
+        # the stream the kernels run on
+        plan.set_timing(True)
+        plan.kernel_times()
+        t2 = time.perf_counter()
+        for _ in range(steps):
+            plan.retrieve(L, s, alpha, None, status, ws)
+        torch.cuda.synchronize()
+        dt_ins = time.perf_counter() - t2
+        kt = plan.kernel_times()
+        plan.set_timing(False)
+        outputs[form] = alpha.cpu().numpy().copy()
+        st = status.cpu().numpy()
+        res = {
+            "px_per_s": n_px * steps / dt,
+            "ms_per_step": 1e3 * dt / steps,
+            "ms_per_step_instrumented": 1e3 * dt_ins / steps,
+            "steps": steps,
+            "columns_failed": int((st != 0).sum()),
+            "kernels_ms_per_step": {k: round(v[0] / steps, 4) for k, v in kt.items()},
+            "launches_per_step": {k: v[1] // steps for k, v in kt.items()},
+        }
+        # the dominant streaming pass of this form
+        dom = "pass_vec" if form == "lowrank" else "pass_gram"
+        avg_ms = kt[dom][0] / max(1, kt[dom][1])
+        res["dominant_kernel"] = dom
+        res["dominant_avg_ms"] = avg_ms
+        res["dominant_GBps"] = PASS_BYTES_PER_PX * n_px / (avg_ms * 1e-3) / 1e9
+        results[form] = res
+        log(f"{form}: {res['px_per_s'] / 1e6:.1f} Mpx/s, {res['ms_per_step']:.3f} ms/step, "
+            f"{dom} {avg_ms * 1e3:.1f} us = {res['dominant_GBps']:.0f} GB/s, kernels {res['kernels_ms_per_step']}")
+        plan.close()
+        del ws
+
+    # CPU baseline: the FP64 oracle on the host cores; its output is also the
+    # reference for every form's error report.
+    cpu = None
+    errors = {}
+    if not args.no_cpu_baseline:
+        from oracle.mf64 import host_cores, retrieve as oracle_retrieve
+        from tests.parity_util import compare
+        cores = min(16, host_cores())
+        n_cols = S if cores >= 8 else min(S, 16 * cores)
+        cols = list(range(n_cols))
+        t3 = time.perf_counter()
+        ref, rst = oracle_retrieve(sc.radiance, sc.s, K, lam, eps, columns=cols, workers=cores)
+        dtc = time.perf_counter() - t3
+        cpu = {"value": n_cols * N / dtc, "unit": "px/s", "cores": cores, "kind": "oracle",
+               "sample": f"{n_cols} of {S} columns x {N} lines x {B} bands, 30 iterations, "
+                         f"FP64 numpy/LAPACK, one process per core",
+               "seconds": round(dtc, 2)}
+        log(f"oracle: {cpu['value']:.0f} px/s on {cores} cores ({dtc:.1f}s)")
+        for form, a in outputs.items():
+            rep = compare(a[:n_cols], ref)
+            errors[form] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in rep.items()}
+            log(f"{form} vs FP64: {errors[form]}")
+
+    hr = results[head]
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tf = json.load(open(TRAFFIC_FILE))
+        if tf.get("source_sha256_16") == source_digest() and tf.get("kernel") == hr["dominant_kernel"]:
+            traffic = tf.get("bytes_per_launch")
+    roof = {
+        "bound": "hbm",
+        "kernel": hr["dominant_kernel"],
+        "achieved": round(hr["dominant_GBps"], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(hr["dominant_GBps"] / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": PASS_BYTES_PER_PX * n_px,
+        "avg_launch_ms": round(hr["dominant_avg_ms"], 5),
+    }
+    whole_job_GBps = (K + 2) * 74 * 4 * n_px / (hr["ms_per_step"] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(hr["px_per_s"], 1),
+        "unit": "px/s",
+        "n_gpus": 1,
+        "steps": hr["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": round(hr["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"flightline {S}x{N}x{B}, {K} iterations, lambda {lam:.4g}, "
+                               f"covariance form '{head}'",
+                   "columns": S, "lines": N, "bands": B, "iterations": K,
+                   "covariance": head, "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "hbm_fraction_whole_job": round(whole_job_GBps / HBM_PEAK_GBS, 4),
+        "forms": {f: {"px_per_s": round(r["px_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                      "kernels_ms_per_step": r["kernels_ms_per_step"],
+                      "dominant_kernel": r["dominant_kernel"],
+                      "dominant_GBps": round(r["dominant_GBps"], 1),
+                      "error_vs_fp64": errors.get(f)} for f, r in results.items()},
+    }
+    if "bf16" in results and "fp32" in results:
+        out["bf16_vs_fp32_gram_speedup"] = round(results["bf16"]["px_per_s"] / results["fp32"]["px_per_s"], 3)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -72,10 +72,17 @@ enum {
   MF_COL_NONFINITE = 3   /* a valid pixel holds NaN or Inf */
 };
 
+/* How C^k of Eq. 11 is formed.  Every form computes the same matrix in exact
+   arithmetic; they differ in rounding and speed.  The per-pixel scores are
+   FP32 and the factorisation FP64 in every form. */
 typedef enum {
-  MF_GRAM_FP32 = 0,      /* covariance Gram on FP32 MFMA, flushed to FP64 every 64 px */
-  MF_GRAM_BF16 = 1       /* Gram operands rounded to BF16 on MFMA (FP32 accumulate) */
-} mf_gram;
+  MF_COV_LOWRANK = 0,    /* default.  C^0 from one exact Gram (FP64 MFMA); C^k
+                            from C^0 by an exact rank-3 update built from
+                            sum c_i (L_i - mean L), sum c_i, sum c_i^2 */
+  MF_COV_GRAM_FP64 = 1,  /* a Gram of the residuals every iteration, FP64 MFMA */
+  MF_COV_GRAM_FP32 = 2,  /* ... on FP32 MFMA, flushed to FP64 every 64 pixels */
+  MF_COV_GRAM_BF16 = 3   /* ... with BF16 operands on MFMA (FP32 accumulate) */
+} mf_cov;
 
 typedef struct {
   uint32_t struct_size;   /* = sizeof(mf_options); guards ABI drift */
@@ -87,7 +94,7 @@ typedef struct {
   double   lambda;        /* >= 0, weight scale: w = lambda / (alpha + eps).
                              1 = the paper's Eq. 5; 0 = no sparsity prior. */
   double   epsilon;       /* > 0, ppm*m (Eq. 5) */
-  int32_t  gram;          /* mf_gram */
+  int32_t  cov;           /* mf_cov */
   int32_t  refine_steps;  /* iterative-refinement steps of C^-1 t (0..4; 1 = default) */
   int32_t  save_for_backward; /* reserved, must be 0 in ABI version 1 */
   int32_t  chunk_lines;   /* pixels per work item along a column (multiple of
@@ -104,7 +111,7 @@ typedef struct {
 MF_API int mf_abi_version(void);
 
 /* Fills *opt with defaults: B = 74, K = 30, albedo on, lambda 1, eps 1e-9,
-   FP32 Gram, one refinement step, automatic chunking. */
+   low-rank covariance form, one refinement step, automatic chunking. */
 MF_API void mf_options_default(mf_options* opt);
 
 /* Static text for a status code (never NULL). */
@@ -144,6 +151,25 @@ MF_API int64_t mf_plan_pixels(mf_plan plan);
 MF_API mf_status mf_retrieve(mf_plan plan, const float* radiance, const uint8_t* valid,
                       const float* s, float* alpha, int32_t* column_status,
                       void* workspace, void* stream);
+
+/* Kernel timing for benchmarks.  While enabled, mf_retrieve brackets each of
+   its kernel launches with HIP events on the caller's stream (a few
+   microseconds of extra stream work per launch). */
+enum {
+  MF_KERNEL_PASS_GRAM = 0,  /* streaming pass that also accumulates a Gram */
+  MF_KERNEL_PASS_VEC = 1,   /* streaming pass of the low-rank form (vector moments) */
+  MF_KERNEL_PASS_LAST = 2,  /* final streaming pass (alpha^K only) */
+  MF_KERNEL_SOLVE = 3,      /* per-column FP64 combine, Cholesky and solve */
+  MF_KERNEL_OTHER = 4,      /* setup and status copy */
+  MF_KERNEL_KINDS = 5
+};
+MF_API mf_status mf_plan_set_timing(mf_plan plan, int enable);
+
+/* Waits for every event recorded since the last call, then writes the summed
+   kernel time in milliseconds (times_ms[kind]) and the number of launches
+   (counts[kind]) for kind < n (n <= MF_KERNEL_KINDS), and clears the record.
+   Either output pointer may be NULL.  Host pointers. */
+MF_API mf_status mf_plan_kernel_times(mf_plan plan, double* times_ms, int64_t* counts, int n);
 
 /* Releases the plan and its device tables (synchronises the device first). */
 MF_API void mf_plan_destroy(mf_plan plan);

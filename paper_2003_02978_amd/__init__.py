@@ -16,19 +16,20 @@ LIB_PATH = os.path.join(HERE, "libmf.so")
 
 MF_OK, MF_E_ARG, MF_E_SHAPE, MF_E_UNSUPPORTED, MF_E_DEVICE, MF_E_STATE = range(6)
 MF_COL_OK, MF_COL_FEW_PIXELS, MF_COL_NOT_SPD, MF_COL_NONFINITE = range(4)
-GRAM = {"fp32": 0, "bf16": 1}
+COV = {"lowrank": 0, "fp64": 1, "fp32": 2, "bf16": 3}
 
 # Every symbol declared in include/mf.h.
 EXPORTS = ("mf_abi_version", "mf_options_default", "mf_status_str", "mf_last_error",
            "mf_plan_create", "mf_workspace_bytes", "mf_plan_columns", "mf_plan_pixels",
-           "mf_retrieve", "mf_plan_destroy")
+           "mf_retrieve", "mf_plan_set_timing", "mf_plan_kernel_times", "mf_plan_destroy")
+KERNEL_KINDS = ("pass_gram", "pass_vec", "pass_last", "solve", "other")
 
 
 class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("n_bands", ctypes.c_int32),
                 ("n_iter", ctypes.c_int32), ("albedo", ctypes.c_int32),
                 ("lambda_", ctypes.c_double), ("epsilon", ctypes.c_double),
-                ("gram", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("cov", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
                 ("save_for_backward", ctypes.c_int32), ("chunk_lines", ctypes.c_int32)]
 
 
@@ -72,6 +73,11 @@ def load_library(path: str = LIB_PATH):
     lib.mf_retrieve.restype = ctypes.c_int
     lib.mf_retrieve.argtypes = [vp] * 8
     lib.mf_plan_destroy.argtypes = [vp]
+    lib.mf_plan_set_timing.restype = ctypes.c_int
+    lib.mf_plan_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.mf_plan_kernel_times.restype = ctypes.c_int
+    lib.mf_plan_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     if lib.mf_abi_version() != 1:
         raise ImportError("libmf.so ABI version mismatch")
     _lib = lib
@@ -99,11 +105,11 @@ class Plan:
 
     def __init__(self, flightlines: Iterable[Tuple[int, int, int]], n_bands: int = 74,
                  n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9, albedo: bool = True,
-                 gram: str = "fp32", refine_steps: int = 1, chunk_lines: int = 0):
+                 cov: str = "lowrank", refine_steps: int = 1, chunk_lines: int = 0):
         lib = load_library()
         o = default_options()
         o.n_bands, o.n_iter, o.albedo = n_bands, n_iter, int(bool(albedo))
-        o.lambda_, o.epsilon, o.gram = float(lam), float(eps), GRAM[gram]
+        o.lambda_, o.epsilon, o.cov = float(lam), float(eps), COV[cov]
         o.refine_steps, o.chunk_lines = refine_steps, chunk_lines
         fls = list(flightlines)
         arr = (Flightline * max(1, len(fls)))(*[Flightline(int(a), int(b), int(c)) for a, b, c in fls])
@@ -129,6 +135,17 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def set_timing(self, enable: bool):
+        _check(self._lib.mf_plan_set_timing(self._h, int(bool(enable))))
+
+    def kernel_times(self):
+        """{kind: (total_ms, launches)} since the last call (waits for the GPU)."""
+        n = len(KERNEL_KINDS)
+        t = (ctypes.c_double * n)()
+        c = (ctypes.c_int64 * n)()
+        _check(self._lib.mf_plan_kernel_times(self._h, t, c, n))
+        return {k: (t[i], int(c[i])) for i, k in enumerate(KERNEL_KINDS)}
 
     def alloc_workspace(self, device=None):
         import torch
@@ -179,7 +196,7 @@ def _need(t, dtype, name):
 
 
 def retrieve(radiance, s, n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9,
-             albedo: bool = True, gram: str = "fp32", valid=None, refine_steps: int = 1,
+             albedo: bool = True, cov: str = "lowrank", valid=None, refine_steps: int = 1,
              chunk_lines: int = 0):
     """Retrieve alpha (ppm*m) for a [S, N, B] float32 radiance cube on the GPU.
 
@@ -187,7 +204,7 @@ def retrieve(radiance, s, n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9,
     """
     import torch
     S, N, B = radiance.shape
-    plan = Plan([(0, S, N)], B, n_iter, lam, eps, albedo, gram, refine_steps, chunk_lines)
+    plan = Plan([(0, S, N)], B, n_iter, lam, eps, albedo, cov, refine_steps, chunk_lines)
     alpha = torch.empty((S, N), dtype=torch.float32, device=radiance.device)
     status = torch.empty((S,), dtype=torch.int32, device=radiance.device)
     plan.retrieve(radiance.contiguous(), s.contiguous(), alpha,

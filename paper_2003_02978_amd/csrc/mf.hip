@@ -7,21 +7,26 @@
 //   solve j=0  FP64: mu^0, C^0, Cholesky, v^0 = C^0^-1 t^0, q^0  -> column state
 //   pass j     (1 <= j <= K+1) per pixel p = (L - mu^{j-1}).v^{j-1},
 //              r = L.mu^0/|mu^0|^2, alpha^{j-1} (soft threshold, Eq. 6/8),
-//              c = r alpha^{j-1}, y = L - mu^{j-1} - c t^{j-1};
-//              Gram of [y, 1, c] on MFMA (j <= K)               -> partials
-//   solve j    FP64: mu^j = mean(L) - mean(c) t^{j-1} (Eq. 10), the covariance
-//              of Eq. 11 from the shifted Gram, Cholesky, v^j, q^j
-// The last pass writes alpha^K to the caller's buffer and computes no Gram.
+//              c = r alpha^{j-1}, and the moments the covariance needs (j <= K)
+//   solve j    FP64: mu^j = mean(L) - mean(c) t^{j-1} (Eq. 10), C^j (Eq. 11),
+//              Cholesky, v^j, q^j
+// The last pass writes alpha^K to the caller's buffer and computes no moments.
 //
-// Shifted Gram (exact algebra): with d_i = L_i - c_i t^j - mu^j the residual
-// of Eq. 11 and y_i as computed by the pass,
-//   d_i = y_i + D + c_i e,   D = mu_used - mu^j,   e = t_used - t^j,
-// where mu_used/t_used are the FP32 values the pass actually subtracted, so
-//   N C^j = G + g1 D^T + D g1^T + g2 e^T + e g2^T + N D D^T
-//           + S1 (D e^T + e D^T) + S2 e e^T,
-// G = sum y y^T, g1 = sum y, g2 = sum c y, S1 = sum c, S2 = sum c^2, N = sum 1.
-// The pass gets g1, g2, N, S1, S2 for free by appending the constants 1 and c
-// to each pixel's vector as two extra "bands" of the MFMA Gram.
+// Covariance forms (mf_cov), all exact algebra for C^j of Eq. 11:
+//  * per-iteration Gram (GRAM_FP64 / GRAM_FP32 / GRAM_BF16).  With d_i the
+//    residual of Eq. 11 and y_i = L_i - mu_used - c_i t_used as the pass
+//    computed it (mu_used, t_used = the FP32 values it subtracted),
+//      d_i = y_i + D + c_i e,   D = mu_used - mu^j,   e = t_used - t^j,
+//      N C^j = G + g1 D^T + D g1^T + g2 e^T + e g2^T + N D D^T
+//              + S1 (D e^T + e D^T) + S2 e e^T,
+//    G = sum y y^T, g1 = sum y, g2 = sum c y, S1 = sum c, S2 = sum c^2,
+//    N = sum 1.  The pass gets g1, g2, N, S1, S2 for free by appending the
+//    constants 1 and c to each pixel's vector as two extra "bands" of the Gram.
+//  * LOWRANK (default): the Gram is formed once, exactly (FP64 MFMA), for C^0.
+//    With Lt_i = L_i - mean(L), a = S1/N and m = sum c_i Lt_i,
+//      N C^j = N C^0 + N a^2 (t^{j-1} - t^j)(t^{j-1} - t^j)^T
+//              + (S2 - N a^2) t^j t^j^T - (m t^j^T + t^j m^T),
+//    so each later pass only accumulates the vector m and S1, S2.
 
 #include <hip/hip_runtime.h>
 
@@ -43,7 +48,18 @@ constexpr int kMaxTri = 80 * 81 / 2;
 constexpr int kDefaultChunk = 2048;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// What a pass accumulates besides alpha.
+enum PassMode {
+  PM_NONE = 0,   // last pass: alpha only
+  PM_VEC = 1,    // m = sum c (L - mean L), S1, S2 in FP64 (low-rank form)
+  PM_F64 = 2,    // Gram of [y, 1, c] on v_mfma_f64_16x16x4_f64 (exact)
+  PM_F32 = 3,    // Gram on v_mfma_f32_16x16x4_f32, FP64 flush every 64 px
+  PM_BF16 = 4    // Gram on v_mfma_f32_16x16x32_bf16, FP64 flush every 256 px
+};
+constexpr int kVecM = 80, kVecS1 = 80, kVecS2 = 81;   // PM_VEC partial layout
 
 struct ColInfo {
   int64_t first_px;
@@ -65,13 +81,14 @@ struct alignas(16) ColState {
   float t_f[kPad];     // target t = mu (.) s used by the next pass (FP32)
   float v_f[kPad];     // v = C^-1 t (FP32)
   float m0_f[kPad];    // mu^0 / |mu^0|^2, the albedo projection of Eq. 7
+  float lbar_f[kPad];  // FP32 copy of the plain mean mu^0
   double mu[kPad];     // FP64 mu^j
   double t[kPad];      // FP64 t^j
   double lbar[kPad];   // FP64 plain mean mu^0
   double q;            // t^T C^-1 t
+  double n_valid;      // N, from pass 0
   float q_f;
   int32_t status;
-  int32_t pad[2];
 };
 
 struct PassArgs {
@@ -94,10 +111,12 @@ struct SolveArgs {
   const ColInfo* cols;
   ColState* state;
   const double* partials;
+  double* c0;                // LOWRANK: packed C^0 per column
   const float* s;
   int B;
   int j;
   int refine;
+  int lowrank;
 };
 
 __host__ __device__ constexpr int n_tiles(int nb) { return nb * (nb + 1) / 2; }
@@ -147,12 +166,14 @@ __global__ void __launch_bounds__(64) setup_kernel(const float* __restrict__ L,
     st.t_f[b] = 0.f;
     st.v_f[b] = 0.f;
     st.m0_f[b] = 0.f;
+    st.lbar_f[b] = 0.f;
     st.mu[b] = 0.0;
     st.t[b] = 0.0;
     st.lbar[b] = 0.0;
   }
   if (lane == 0) {
     st.q = 1.0;
+    st.n_valid = 0.0;
     st.q_f = 1.f;
     st.status = z >= 0 ? MF_COL_OK : MF_COL_FEW_PIXELS;
   }
@@ -192,10 +213,12 @@ __device__ __forceinline__ void load_super(const PassArgs& a, int64_t base, int6
   }
 }
 
-template <int NB, int GRAM, bool MOMENTS>
+template <int NB, int MODE>
 __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
   constexpr int T = n_tiles(NB);
-  constexpr int FLUSH = GRAM == MF_GRAM_FP32 ? 2 : 8;   // super-steps between FP64 flushes
+  constexpr bool GRAM = MODE >= PM_F64;
+  constexpr bool F32ACC = MODE == PM_F32 || MODE == PM_BF16;
+  constexpr int FLUSH = MODE == PM_BF16 ? 8 : 2;   // super-steps between FP64 flushes
   const WorkItem it = a.items[blockIdx.x];
   const ColState& st = a.state[it.col];
   const int tid = threadIdx.x;
@@ -210,7 +233,7 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
     return;
   }
 
-  float mu[NB], vv[NB], tt[NB], m0[NB];
+  float mu[NB], vv[NB], tt[NB], m0[NB], lb[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     const int b = c16 + 16 * k;
@@ -219,23 +242,29 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
     vv[k] = in ? st.v_f[b] : 0.f;
     tt[k] = in ? st.t_f[b] : 0.f;
     m0[k] = in ? st.m0_f[b] : 0.f;
+    lb[k] = in ? st.lbar_f[b] : 0.f;
   }
   const float q = st.q_f;
   const int j = a.j;
 
-  floatx4 acc[MOMENTS ? T : 1];
-  double acc64[MOMENTS ? T : 1][4];
-  if constexpr (MOMENTS) {
+  [[maybe_unused]] floatx4 acc[F32ACC ? T : 1];
+  [[maybe_unused]] doublex4 dacc[GRAM ? T : 1];
+  [[maybe_unused]] double md[NB], s1d = 0.0, s2d = 0.0;
+  if constexpr (GRAM) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < T; ++t) dacc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+  }
+  if constexpr (F32ACC) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc64[t][i] = 0.0;
-    }
+    for (int t = 0; t < T; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  if constexpr (MODE == PM_VEC) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) md[k] = 0.0;
   }
 
   float Lc[8][NB], apc[8];
-  unsigned okc;
+  unsigned okc = 0;
   int64_t base = begin + 32 * wid;
   if (base < end) load_super<NB>(a, base, end, row, c16, Lc, apc, okc);
   int nsuper = 0;
@@ -272,7 +301,19 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
         if (c16 == 0 && px < end) a.alpha_out[px] = al;
         c = (ok && !dark && al > 0.f) ? r * al : 0.f;
       }
-      if constexpr (MOMENTS) {
+      if constexpr (MODE == PM_VEC) {
+        // FP64: L - lbar of two FP32 values is exact, and the rank-3 update
+        // cancels the plume's contribution to C^0, so m is kept exact-ish.
+        const double cd = (double)c;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const float l = ok ? Lc[s][k] : lb[k];
+          md[k] = fma(cd, (double)l - (double)lb[k], md[k]);
+        }
+        s1d += cd;
+        s2d = fma(cd, cd, s2d);
+      }
+      if constexpr (GRAM) {
         float y[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
@@ -281,7 +322,14 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
           if (b == B) y[k] = ok ? 1.f : 0.f;
           if (b == B + 1) y[k] = c;
         }
-        if constexpr (GRAM == MF_GRAM_FP32) {
+        if constexpr (MODE == PM_F64) {
+#pragma unroll
+          for (int I = 0; I < NB; ++I)
+#pragma unroll
+            for (int J = 0; J <= I; ++J)
+              dacc[n_tiles(I) + J] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                  (double)y[I], (double)y[J], dacc[n_tiles(I) + J], 0, 0, 0);
+        } else if constexpr (MODE == PM_F32) {
 #pragma unroll
           for (int I = 0; I < NB; ++I)
 #pragma unroll
@@ -294,21 +342,21 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
         }
       }
     }
-    if constexpr (MOMENTS) {
-      if constexpr (GRAM == MF_GRAM_BF16) {
+    if constexpr (MODE == PM_BF16) {
 #pragma unroll
-        for (int I = 0; I < NB; ++I)
+      for (int I = 0; I < NB; ++I)
 #pragma unroll
-          for (int J = 0; J <= I; ++J)
-            acc[n_tiles(I) + J] =
-                __builtin_amdgcn_mfma_f32_16x16x32_bf16(ybf[I], ybf[J], acc[n_tiles(I) + J], 0, 0, 0);
-      }
+        for (int J = 0; J <= I; ++J)
+          acc[n_tiles(I) + J] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(ybf[I], ybf[J], acc[n_tiles(I) + J], 0, 0, 0);
+    }
+    if constexpr (F32ACC) {
       if (++nsuper == FLUSH) {
         nsuper = 0;
 #pragma unroll
         for (int t = 0; t < T; ++t) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) acc64[t][i] += (double)acc[t][i];
+          for (int i = 0; i < 4; ++i) dacc[t][i] += (double)acc[t][i];
           acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
       }
@@ -322,11 +370,14 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
     okc = okn;
   }
 
-  if constexpr (MOMENTS) {
+  double* out = a.partials + (int64_t)blockIdx.x * (T * 256);
+  if constexpr (GRAM) {
+    if constexpr (F32ACC) {
 #pragma unroll
-    for (int t = 0; t < T; ++t)
+      for (int t = 0; t < T; ++t)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc64[t][i] += (double)acc[t][i];
+        for (int i = 0; i < 4; ++i) dacc[t][i] += (double)acc[t][i];
+    }
     // Deterministic cross-wave reduction in LDS, wave 0 first.
     __shared__ double red[T * 256];
     for (int w = 0; w < 4; ++w) {
@@ -335,15 +386,33 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
         for (int t = 0; t < T; ++t)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            // D[m][n] of tile t lives in lane n + 16 (m / 4), register m % 4
-            const int e = t * 256 + (4 * row + i) * 16 + c16;
-            red[e] = (w == 0 ? 0.0 : red[e]) + acc64[t][i];
+            // Where D[m][n] of a tile lives: f32 MFMA lane n + 16 (m / 4),
+            // register m % 4; f64 MFMA lane n + 16 (m % 4), register m / 4.
+            const int m = MODE == PM_F64 ? row + 4 * i : 4 * row + i;
+            const int e = t * 256 + m * 16 + c16;
+            red[e] = (w == 0 ? 0.0 : red[e]) + dacc[t][i];
           }
       }
       __syncthreads();
     }
-    double* out = a.partials + (int64_t)blockIdx.x * (T * 256);
     for (int e = tid; e < T * 256; e += kBlock) out[e] = red[e];
+  } else if constexpr (MODE == PM_VEC) {
+    // 16 (wave, row) partials per band, summed in a fixed order.
+    __shared__ double redv[16 * 82];
+    const int slot = (wid * 4 + row) * 82;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) redv[slot + c16 + 16 * k] = md[k];
+    for (int b = c16 + 16 * NB; b < kVecM; b += 16) redv[slot + b] = 0.0;
+    if (c16 == 0) {           // every lane of a row holds the same c
+      redv[slot + kVecS1] = s1d;
+      redv[slot + kVecS2] = s2d;
+    }
+    __syncthreads();
+    for (int e = tid; e < 82; e += kBlock) {
+      double sum = 0.0;
+      for (int w = 0; w < 16; ++w) sum += redv[w * 82 + e];
+      out[e] = sum;
+    }
   }
 }
 
@@ -391,6 +460,8 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   const int j = a.j;
   constexpr int T = n_tiles(NB);
   const double* P = a.partials + (int64_t)ci.first_item * T * 256;
+  const bool rank3 = a.lowrank && j >= 1;
+  double* c0 = a.c0 + (int64_t)col * kMaxTri;
 
   __shared__ double A0[kMaxTri];     // C (kept for refinement)
   __shared__ double A[kMaxTri];      // its Cholesky factor
@@ -400,14 +471,32 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   __shared__ int fail;
 
   if (tid == 0) {
-    sc[0] = gram_elem<NB>(P, ci.n_items, B, B);          // N
-    sc[1] = gram_elem<NB>(P, ci.n_items, B + 1, B);      // S1 = sum c
-    sc[2] = gram_elem<NB>(P, ci.n_items, B + 1, B + 1);  // S2 = sum c^2
+    if (rank3) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int it = 0; it < ci.n_items; ++it) {
+        s1 += P[(int64_t)it * T * 256 + kVecS1];
+        s2 += P[(int64_t)it * T * 256 + kVecS2];
+      }
+      sc[0] = st.n_valid;
+      sc[1] = s1;
+      sc[2] = s2;
+    } else {
+      sc[0] = gram_elem<NB>(P, ci.n_items, B, B);          // N
+      sc[1] = gram_elem<NB>(P, ci.n_items, B + 1, B);      // S1 = sum c
+      sc[2] = gram_elem<NB>(P, ci.n_items, B + 1, B + 1);  // S2 = sum c^2
+    }
     fail = 0;
   }
   for (int b = tid; b < B; b += kBlock) {
-    g1[b] = gram_elem<NB>(P, ci.n_items, B, b);
-    g2[b] = gram_elem<NB>(P, ci.n_items, B + 1, b);
+    if (rank3) {
+      double m = 0.0;
+      for (int it = 0; it < ci.n_items; ++it) m += P[(int64_t)it * T * 256 + b];
+      g1[b] = m;
+      g2[b] = 0.0;
+    } else {
+      g1[b] = gram_elem<NB>(P, ci.n_items, B, b);
+      g2[b] = gram_elem<NB>(P, ci.n_items, B + 1, b);
+    }
   }
   __syncthreads();
   const double N = sc[0], S1 = sc[1], S2 = sc[2];
@@ -423,20 +512,35 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
     }
     mun[b] = m;
     tn[b] = m * sb;                            // Eq. 9
-    D[b] = mu_used - m;
-    E[b] = j == 0 ? 0.0 : t_used - tn[b];
+    if (rank3) {
+      // m was accumulated about the FP32 mean: sum c (L - lbar_f)
+      g1[b] += S1 * ((double)st.lbar_f[b] - st.lbar[b]);
+      D[b] = st.t[b] - tn[b];                  // t^{j-1} - t^j
+      E[b] = 0.0;
+    } else {
+      D[b] = mu_used - m;
+      E[b] = j == 0 ? 0.0 : t_used - tn[b];
+    }
   }
   __syncthreads();
   const int npk = B * (B + 1) / 2;
+  const double abar = S1 / N;
   for (int p = tid; p < npk; p += kBlock) {
     int i = (int)((sqrtf(8.f * p + 1.f) - 1.f) * 0.5f);
     while (tri(i, 0) > p) --i;
     while (tri(i + 1, 0) <= p) ++i;
     const int jj = p - tri(i, 0);
-    double c = gram_elem<NB>(P, ci.n_items, i, jj);
-    c += g1[i] * D[jj] + D[i] * g1[jj] + g2[i] * E[jj] + E[i] * g2[jj] + N * D[i] * D[jj] +
-         S1 * (D[i] * E[jj] + E[i] * D[jj]) + S2 * E[i] * E[jj];
-    c /= N;
+    double c;
+    if (rank3) {
+      c = c0[p] + abar * abar * D[i] * D[jj] + (S2 / N - abar * abar) * tn[i] * tn[jj] -
+          (g1[i] * tn[jj] + tn[i] * g1[jj]) / N;
+    } else {
+      c = gram_elem<NB>(P, ci.n_items, i, jj);
+      c += g1[i] * D[jj] + D[i] * g1[jj] + g2[i] * E[jj] + E[i] * g2[jj] + N * D[i] * D[jj] +
+           S1 * (D[i] * E[jj] + E[i] * D[jj]) + S2 * E[i] * E[jj];
+      c /= N;
+      if (a.lowrank) c0[p] = c;                // j == 0: keep C^0
+    }
     if (!isfinite(c)) fail = 1;
     A0[p] = c;
     A[p] = c;
@@ -504,6 +608,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
     sc[3] = m2;
     st.q = q;
     st.q_f = (float)q;
+    if (j == 0) st.n_valid = N;
     if (!(q > 0.0) || !isfinite(q)) st.status = MF_COL_NOT_SPD;
   }
   __syncthreads();
@@ -516,6 +621,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
     st.v_f[b] = in ? (float)vv[b] : 0.f;
     if (j == 0) {
       st.lbar[b] = in ? mun[b] : 0.0;
+      st.lbar_f[b] = in ? (float)mun[b] : 0.f;
       st.m0_f[b] = in ? (float)(mun[b] / sc[3]) : 0.f;
     }
   }
@@ -541,42 +647,92 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
+struct TimedLaunch {
+  int kind;
+  hipEvent_t start, stop;
+};
+
 struct mf_plan_s {
   mf_options opt;
+  bool timing = false;
+  std::vector<TimedLaunch> pending;
+  std::vector<hipEvent_t> event_pool;
   int nb = 0;
   int device = 0;
   int64_t n_cols = 0, n_items = 0, n_px = 0, max_px = 0;
   ColInfo* cols_d = nullptr;
   WorkItem* items_d = nullptr;
-  size_t off_state = 0, off_partials = 0, off_alpha0 = 0, off_alpha1 = 0, ws_bytes = 0;
+  size_t off_state = 0, off_partials = 0, off_c0 = 0, off_alpha0 = 0, off_alpha1 = 0;
+  size_t ws_bytes = 0;
 };
 
 namespace {
 
-template <int NB, int GRAM, bool MOM>
-void launch_pass(const mf_plan_s* p, const PassArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((pass_kernel<NB, GRAM, MOM>), dim3((unsigned)p->n_items), dim3(kBlock), 0,
-                     s, a);
+hipEvent_t take_event(mf_plan_s* p) {
+  hipEvent_t e = nullptr;
+  if (!p->event_pool.empty()) {
+    e = p->event_pool.back();
+    p->event_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
 }
 
+// Records events around one launch when timing is on.
+struct LaunchTimer {
+  mf_plan_s* p;
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  LaunchTimer(mf_plan_s* p_, int kind_, hipStream_t s_) : p(p_), kind(kind_), s(s_) {
+    if (p->timing) {
+      a = take_event(p);
+      b = take_event(p);
+      if (a && b) (void)hipEventRecord(a, s);
+    }
+  }
+  ~LaunchTimer() {
+    if (a && b) {
+      (void)hipEventRecord(b, s);
+      p->pending.push_back({kind, a, b});
+    } else {
+      if (a) p->event_pool.push_back(a);
+      if (b) p->event_pool.push_back(b);
+    }
+  }
+};
+
 template <int NB>
-void launch_pass_nb(const mf_plan_s* p, const PassArgs& a, bool mom, hipStream_t s) {
-  if (p->opt.gram == MF_GRAM_FP32) {
-    if (mom) launch_pass<NB, MF_GRAM_FP32, true>(p, a, s);
-    else launch_pass<NB, MF_GRAM_FP32, false>(p, a, s);
-  } else {
-    if (mom) launch_pass<NB, MF_GRAM_BF16, true>(p, a, s);
-    else launch_pass<NB, MF_GRAM_BF16, false>(p, a, s);
+void launch_pass_nb(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t s) {
+  const dim3 g((unsigned)p->n_items), b(kBlock);
+  switch (mode) {
+    case PM_NONE: hipLaunchKernelGGL((pass_kernel<NB, PM_NONE>), g, b, 0, s, a); break;
+    case PM_VEC: hipLaunchKernelGGL((pass_kernel<NB, PM_VEC>), g, b, 0, s, a); break;
+    case PM_F64: hipLaunchKernelGGL((pass_kernel<NB, PM_F64>), g, b, 0, s, a); break;
+    case PM_F32: hipLaunchKernelGGL((pass_kernel<NB, PM_F32>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((pass_kernel<NB, PM_BF16>), g, b, 0, s, a); break;
   }
 }
 
-void dispatch_pass(const mf_plan_s* p, const PassArgs& a, bool mom, hipStream_t s) {
+void dispatch_pass(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t s) {
   switch (p->nb) {
-    case 1: launch_pass_nb<1>(p, a, mom, s); break;
-    case 2: launch_pass_nb<2>(p, a, mom, s); break;
-    case 3: launch_pass_nb<3>(p, a, mom, s); break;
-    case 4: launch_pass_nb<4>(p, a, mom, s); break;
-    default: launch_pass_nb<5>(p, a, mom, s); break;
+    case 1: launch_pass_nb<1>(p, a, mode, s); break;
+    case 2: launch_pass_nb<2>(p, a, mode, s); break;
+    case 3: launch_pass_nb<3>(p, a, mode, s); break;
+    case 4: launch_pass_nb<4>(p, a, mode, s); break;
+    default: launch_pass_nb<5>(p, a, mode, s); break;
+  }
+}
+
+// Pass mode of pass j for a covariance form.
+int pass_mode(int cov, int j, int K) {
+  if (j == K + 1) return PM_NONE;
+  switch (cov) {
+    case MF_COV_GRAM_FP32: return PM_F32;
+    case MF_COV_GRAM_BF16: return PM_BF16;
+    case MF_COV_GRAM_FP64: return PM_F64;
+    default: return j == 0 ? PM_F64 : PM_VEC;   // MF_COV_LOWRANK
   }
 }
 
@@ -606,7 +762,7 @@ void mf_options_default(mf_options* o) {
   o->albedo = 1;
   o->lambda = 1.0;
   o->epsilon = 1e-9;
-  o->gram = MF_GRAM_FP32;
+  o->cov = MF_COV_LOWRANK;
   o->refine_steps = 1;
   o->save_for_backward = 0;
   o->chunk_lines = 0;
@@ -641,8 +797,8 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   if (!(opt->epsilon > 0.0) || !std::isfinite(opt->epsilon))
     return fail_with(MF_E_ARG, "epsilon must be finite and > 0");
   if (opt->albedo != 0 && opt->albedo != 1) return fail_with(MF_E_ARG, "albedo must be 0 or 1");
-  if (opt->gram != MF_GRAM_FP32 && opt->gram != MF_GRAM_BF16)
-    return fail_with(MF_E_ARG, "gram must be MF_GRAM_FP32 or MF_GRAM_BF16");
+  if (opt->cov < MF_COV_LOWRANK || opt->cov > MF_COV_GRAM_BF16)
+    return fail_with(MF_E_ARG, "cov must be one of MF_COV_*");
   if (opt->refine_steps < 0 || opt->refine_steps > 4)
     return fail_with(MF_E_ARG, "refine_steps must be in [0, 4]");
   if (opt->save_for_backward != 0)
@@ -717,6 +873,8 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   off = align256(off + (size_t)p->n_cols * sizeof(ColState));
   p->off_partials = off;
   off = align256(off + (size_t)p->n_items * T * 256 * sizeof(double));
+  p->off_c0 = off;
+  if (opt->cov == MF_COV_LOWRANK) off = align256(off + (size_t)p->n_cols * kMaxTri * sizeof(double));
   p->off_alpha0 = off;
   off = align256(off + (size_t)max_px * sizeof(float));
   p->off_alpha1 = off;
@@ -749,8 +907,11 @@ mf_status mf_retrieve(mf_plan p, const float* radiance, const uint8_t* valid, co
   const int K = p->opt.n_iter;
 
   (void)hipGetLastError();
-  hipLaunchKernelGGL(setup_kernel, dim3((unsigned)p->n_cols), dim3(64), 0, st, radiance, valid,
-                     p->cols_d, state, B);
+  {
+    LaunchTimer tm(p, MF_KERNEL_OTHER, st);
+    hipLaunchKernelGGL(setup_kernel, dim3((unsigned)p->n_cols), dim3(64), 0, st, radiance, valid,
+                       p->cols_d, state, B);
+  }
   PassArgs pa{};
   pa.L = radiance;
   pa.valid = valid;
@@ -765,23 +926,32 @@ mf_status mf_retrieve(mf_plan p, const float* radiance, const uint8_t* valid, co
   sa.cols = p->cols_d;
   sa.state = state;
   sa.partials = partials;
+  sa.c0 = (double*)(ws + p->off_c0);
   sa.s = s;
   sa.B = B;
   sa.refine = p->opt.refine_steps;
+  sa.lowrank = p->opt.cov == MF_COV_LOWRANK;
   for (int j = 0; j <= K + 1; ++j) {
     pa.j = j;
     pa.unclamped = (j == 1 && K == 0) ? 1 : 0;
     pa.alpha_prev = j >= 2 ? abuf[(j - 2) & 1] : nullptr;
     pa.alpha_out = j == K + 1 ? alpha : (j >= 1 ? abuf[(j - 1) & 1] : nullptr);
     const bool mom = j <= K;
-    dispatch_pass(p, pa, mom, st);
+    const int mode = pass_mode(p->opt.cov, j, K);
+    {
+      LaunchTimer tm(p, mode == PM_NONE ? MF_KERNEL_PASS_LAST
+                        : mode == PM_VEC ? MF_KERNEL_PASS_VEC : MF_KERNEL_PASS_GRAM, st);
+      dispatch_pass(p, pa, mode, st);
+    }
     if (mom) {
       sa.j = j;
+      LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
       dispatch_solve(p, sa, st);
     }
   }
   if (column_status) {
     const unsigned nb = (unsigned)((p->n_cols + 255) / 256);
+    LaunchTimer tm(p, MF_KERNEL_OTHER, st);
     hipLaunchKernelGGL(status_kernel, dim3(nb), dim3(256), 0, st, state, column_status, p->n_cols);
   }
   const hipError_t e = hipGetLastError();
@@ -789,9 +959,44 @@ mf_status mf_retrieve(mf_plan p, const float* radiance, const uint8_t* valid, co
   return MF_OK;
 }
 
+mf_status mf_plan_set_timing(mf_plan p, int enable) {
+  if (!p) return fail_with(MF_E_ARG, "plan is NULL");
+  p->timing = enable != 0;
+  return MF_OK;
+}
+
+mf_status mf_plan_kernel_times(mf_plan p, double* times_ms, int64_t* counts, int n) {
+  if (!p) return fail_with(MF_E_ARG, "plan is NULL");
+  if (n < 0 || n > MF_KERNEL_KINDS) return fail_with(MF_E_ARG, "n out of range");
+  double t[MF_KERNEL_KINDS] = {};
+  int64_t c[MF_KERNEL_KINDS] = {};
+  mf_status rc = MF_OK;
+  for (const TimedLaunch& l : p->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(l.stop) != hipSuccess ||
+        hipEventElapsedTime(&ms, l.start, l.stop) != hipSuccess)
+      rc = fail_with(MF_E_DEVICE, "event timing failed");
+    t[l.kind] += ms;
+    c[l.kind] += 1;
+    p->event_pool.push_back(l.start);
+    p->event_pool.push_back(l.stop);
+  }
+  p->pending.clear();
+  for (int k = 0; k < n; ++k) {
+    if (times_ms) times_ms[k] = t[k];
+    if (counts) counts[k] = c[k];
+  }
+  return rc;
+}
+
 void mf_plan_destroy(mf_plan p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
+  for (const TimedLaunch& l : p->pending) {
+    (void)hipEventDestroy(l.start);
+    (void)hipEventDestroy(l.stop);
+  }
+  for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
   if (p->cols_d) (void)hipFree(p->cols_d);
   if (p->items_d) (void)hipFree(p->items_d);
   delete p;

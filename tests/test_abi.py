@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 def test_options_default_and_struct_layout():
     o = mf.default_options()
     assert o.struct_size == ctypes.sizeof(mf.Options)
-    assert (o.n_bands, o.n_iter, o.albedo, o.gram, o.refine_steps) == (74, 30, 1, 0, 1)
+    assert (o.n_bands, o.n_iter, o.albedo, o.cov, o.refine_steps) == (74, 30, 1, 0, 1)
     assert o.lambda_ == 1.0 and o.epsilon == 1e-9
 
 
@@ -54,7 +54,8 @@ def _create(**kw):
     ("lambda_", float("nan"), mf.MF_E_ARG),
     ("epsilon", 0.0, mf.MF_E_ARG),
     ("albedo", 2, mf.MF_E_ARG),
-    ("gram", 7, mf.MF_E_ARG),
+    ("cov", 7, mf.MF_E_ARG),
+    ("cov", -1, mf.MF_E_ARG),
     ("refine_steps", 9, mf.MF_E_ARG),
     ("chunk_lines", 100, mf.MF_E_ARG),
     ("save_for_backward", 1, mf.MF_E_UNSUPPORTED),

@@ -30,47 +30,55 @@ def tiny():
     return make_scene(tiny_spec())
 
 
+EXACT = ["lowrank", "fp64"]    # forms whose covariance is accumulated exactly
+
+
+@pytest.mark.parametrize("cov", EXACT)
 @pytest.mark.parametrize("chunk", [0, 128])
-def test_tiny_scene_fp32(tiny, chunk):
+def test_tiny_scene(tiny, chunk, cov):
     lam = config_lambda("tiny")
-    a, st = _gpu(tiny, n_iter=30, lam=lam, chunk_lines=chunk)
+    a, st = _gpu(tiny, n_iter=30, lam=lam, chunk_lines=chunk, cov=cov)
     ref, rst = oracle_retrieve(tiny.radiance, tiny.s, 30, lam, workers=8)
     np.testing.assert_array_equal(st, rst)
     assert np.all(a >= 0)
-    assert_fp32_parity(a, ref, label=f"tiny chunk={chunk}")
+    assert_fp32_parity(a, ref, label=f"tiny chunk={chunk} cov={cov}")
 
 
+@pytest.mark.parametrize("cov", EXACT)
 @pytest.mark.parametrize("albedo", [True, False])
-def test_zero_iterations_is_the_unclamped_filter(tiny, albedo):
-    a, st = _gpu(tiny, n_iter=0, lam=1.0, albedo=albedo)
+def test_zero_iterations_is_the_unclamped_filter(tiny, albedo, cov):
+    a, st = _gpu(tiny, n_iter=0, lam=1.0, albedo=albedo, cov=cov)
     ref, _ = oracle_retrieve(tiny.radiance, tiny.s, 0, 1.0, albedo=albedo, workers=8)
     assert (a < 0).any()
     assert_fp32_parity(a, ref, iterative=False, label=f"K=0 albedo={albedo}")
 
 
+@pytest.mark.parametrize("cov", EXACT)
 @pytest.mark.parametrize("lam,albedo,K", [(0.0, True, 5), (0.0, False, 5), (1.0, False, 12)])
-def test_variants(tiny, lam, albedo, K):
+def test_variants(tiny, lam, albedo, K, cov):
     sub = make_scene(tiny_spec())
     sub.radiance = sub.radiance[:16].copy()
-    a, _ = _gpu(sub, n_iter=K, lam=lam, albedo=albedo)
+    a, _ = _gpu(sub, n_iter=K, lam=lam, albedo=albedo, cov=cov)
     ref, _ = oracle_retrieve(sub.radiance, sub.s, K, lam, albedo=albedo, workers=8)
     assert_fp32_parity(a, ref, label=f"lam={lam} albedo={albedo} K={K}")
 
 
-def test_ragged_lengths_and_many_items():
+@pytest.mark.parametrize("cov", EXACT)
+def test_ragged_lengths_and_many_items(cov):
     spec = SceneSpec(6, 1000, 74, 2, (500.0, 5000.0), (3.0, 30.0), seed=5)
     sc = make_scene(spec)
     for chunk in (128, 256, 0):
-        a, st = _gpu(sc, n_iter=15, lam=3.0, chunk_lines=chunk)
+        a, st = _gpu(sc, n_iter=15, lam=3.0, chunk_lines=chunk, cov=cov)
         ref, rst = oracle_retrieve(sc.radiance, sc.s, 15, 3.0)
         np.testing.assert_array_equal(st, rst)
         assert_fp32_parity(a, ref, label=f"ragged chunk={chunk}")
 
 
-def test_masks_skip_invalid_pixels():
+@pytest.mark.parametrize("cov", EXACT)
+def test_masks_skip_invalid_pixels(cov):
     spec = SceneSpec(8, 1500, 74, 3, (500.0, 5000.0), (3.0, 30.0), seed=9, mask_max_frac=0.2)
     sc = make_scene(spec)
-    a, st = _gpu(sc, n_iter=20, lam=3.0, chunk_lines=512)
+    a, st = _gpu(sc, n_iter=20, lam=3.0, chunk_lines=512, cov=cov)
     ref, rst = oracle_retrieve(sc.radiance, sc.s, 20, 3.0, valid=sc.valid)
     np.testing.assert_array_equal(st, rst)
     assert np.all(a[sc.valid == 0] == 0)
@@ -78,7 +86,8 @@ def test_masks_skip_invalid_pixels():
     assert_fp32_parity(a, ref, label="masked")
 
 
-def test_degenerate_columns_get_status_and_zero():
+@pytest.mark.parametrize("cov", EXACT + ["fp32"])
+def test_degenerate_columns_get_status_and_zero(cov):
     spec = SceneSpec(4, 600, 74, 1, (500.0, 5000.0), (3.0, 30.0), seed=11, mask_max_frac=0.0)
     sc = make_scene(spec)
     valid = np.ones((4, 600), np.uint8)
@@ -87,46 +96,57 @@ def test_degenerate_columns_get_status_and_zero():
     sc.radiance[1, 123, 7] = np.nan  # a valid pixel with NaN
     valid[3, :] = 0                  # no valid pixel at all
     sc.valid = valid
-    a, st = _gpu(sc, n_iter=5, lam=2.0)
+    a, st = _gpu(sc, n_iter=5, lam=2.0, cov=cov)
     ref, rst = oracle_retrieve(sc.radiance, sc.s, 5, 2.0, valid=valid)
     assert list(st) == [mf.MF_COL_FEW_PIXELS, mf.MF_COL_NONFINITE, mf.MF_COL_OK,
                         mf.MF_COL_FEW_PIXELS]
     np.testing.assert_array_equal(st, rst)
     assert np.all(a[[0, 1, 3]] == 0)
-    assert_fp32_parity(a[2:3], ref[2:3], label="degenerate, healthy column")
+    if cov in EXACT:
+        assert_fp32_parity(a[2:3], ref[2:3], label="degenerate, healthy column")
 
 
-def test_bf16_gram_reports_error(tiny):
+@pytest.mark.parametrize("cov,pattern_min,rmse_max", [("fp32", 0.999, 1.0), ("bf16", 0.99, 50.0)])
+def test_rounded_gram_forms_report_error(tiny, cov, pattern_min, rmse_max):
+    """The FP32- and BF16-MFMA Gram forms round the covariance; their error
+    against FP64 is reported and bounded loosely (it is not the FP32 bar)."""
     lam = config_lambda("tiny")
-    a, st = _gpu(tiny, n_iter=30, lam=lam, gram="bf16")
+    a, st = _gpu(tiny, n_iter=30, lam=lam, cov=cov)
     ref, _ = oracle_retrieve(tiny.radiance, tiny.s, 30, lam, workers=8)
     rep = compare(a, ref)
-    print("bf16 vs FP64:", rep, flush=True)
-    assert rep["pattern_agreement"] >= 0.99
-    assert rep["rmse"] < 50.0
+    print(f"{cov} Gram vs FP64:", rep, flush=True)
+    assert rep["pattern_agreement"] >= pattern_min
+    assert rep["rmse"] < rmse_max
 
 
-def test_deterministic_and_column_independent(tiny):
+@pytest.mark.parametrize("cov", ["lowrank", "fp32"])
+def test_deterministic_and_column_independent(tiny, cov):
     lam = config_lambda("tiny")
-    a1, _ = _gpu(tiny, n_iter=30, lam=lam)
-    a2, _ = _gpu(tiny, n_iter=30, lam=lam)
+    a1, _ = _gpu(tiny, n_iter=30, lam=lam, cov=cov)
+    a2, _ = _gpu(tiny, n_iter=30, lam=lam, cov=cov)
     np.testing.assert_array_equal(a1, a2)
     sub = make_scene(tiny_spec())
     sub.radiance = sub.radiance[17:18].copy()
-    a3, _ = _gpu(sub, n_iter=30, lam=lam)
+    a3, _ = _gpu(sub, n_iter=30, lam=lam, cov=cov)
     np.testing.assert_array_equal(a3[0], a1[17])
 
 
-def test_full_flightline_sampled_columns():
+@pytest.fixture(scope="module")
+def flightline():
+    return make_scene(flightline_spec())
+
+
+@pytest.mark.parametrize("cov", EXACT)
+def test_full_flightline_sampled_columns(flightline, cov):
     """598 x 8000 x 74, 30 iterations, the benchmark's launch configuration;
     columns through plumes and random columns are recomputed by the oracle."""
     spec = flightline_spec()
     lam = config_lambda("flightline")
-    sc = make_scene(spec)
-    a, st = _gpu(sc, n_iter=30, lam=lam)
+    sc = flightline
+    a, st = _gpu(sc, n_iter=30, lam=lam, cov=cov)
     assert np.all(st == 0)
     g = make_globals(spec)
     rng = np.random.default_rng(0)
     cols = sorted(set([int(g.plumes[i, 0]) for i in range(3)] + list(rng.choice(598, 3, replace=False))))
     ref, _ = oracle_retrieve(sc.radiance, sc.s, 30, lam, columns=cols, workers=6)
-    assert_fp32_parity(a[cols], ref, label=f"flightline cols {cols}")
+    assert_fp32_parity(a[cols], ref, label=f"flightline cov={cov} cols {cols}")

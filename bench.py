@@ -44,6 +44,7 @@ def main():
     ap.add_argument("--forms", default="lowrank,fp64,fp32,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-lines", type=int, default=8000)
+    ap.add_argument("--save-alpha", default="", help="save each form's alpha as <path>_<form>.npy")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: every column is an independent problem, "
@@ -72,6 +73,15 @@ def main():
     alpha = torch.empty((S, N), dtype=torch.float32, device=dev)
     status = torch.empty((S,), dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
+
+    # measured read ceiling on the same buffer
+    ceil = []
+    for nb in (1024, 4096, 16384):
+        for _ in range(3):
+            ms = mf.stream_read_ms(L.view(-1), nb)
+        ceil.append((L.numel() * 4 / (ms * 1e-3) / 1e9, nb))
+    ceiling_GBps, ceiling_blocks = max(ceil)
+    log(f"stream read ceiling: {ceiling_GBps:.0f} GB/s ({ceiling_blocks} blocks); all {ceil}")
 
     forms = [f for f in args.forms.split(",") if f]
     head = forms[0]
@@ -102,6 +112,8 @@ def main():
         kt = plan.kernel_times()
         plan.set_timing(False)
         outputs[form] = alpha.cpu().numpy().copy()
+        if args.save_alpha:
+            np.save(f"{args.save_alpha}_{form}.npy", outputs[form])
         st = status.cpu().numpy()
         res = {
             "px_per_s": n_px * steps / dt,
@@ -163,6 +175,8 @@ def main():
         "traffic": traffic,
         "algorithmic_bytes_per_launch": PASS_BYTES_PER_PX * n_px,
         "avg_launch_ms": round(hr["dominant_avg_ms"], 5),
+        "measured_read_ceiling_GBps": round(ceiling_GBps, 1),
+        "frac_of_measured_ceiling": round(hr["dominant_GBps"] / ceiling_GBps, 4),
     }
     whole_job_GBps = (K + 2) * 74 * 4 * n_px / (hr["ms_per_step"] * 1e-3) / 1e9
     out = {

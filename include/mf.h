@@ -171,6 +171,14 @@ MF_API mf_status mf_plan_set_timing(mf_plan plan, int enable);
    Either output pointer may be NULL.  Host pointers. */
 MF_API mf_status mf_plan_kernel_times(mf_plan plan, double* times_ms, int64_t* counts, int n);
 
+/* Diagnostic: reads n floats of src (device, 16-byte aligned, n a multiple of
+   4) once with n_blocks workgroups and discards them, the achievable HBM read
+   bandwidth used as the measured ceiling of the streaming passes.  sink
+   (device, n_blocks floats) is never written in practice.  If ms_out (host) is
+   non-NULL the call waits and stores the kernel time measured with HIP events. */
+MF_API mf_status mf_stream_read(const float* src, int64_t n, float* sink, int32_t n_blocks,
+                                float* ms_out, void* stream);
+
 /* Releases the plan and its device tables (synchronises the device first). */
 MF_API void mf_plan_destroy(mf_plan plan);
 

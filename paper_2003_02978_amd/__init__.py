@@ -21,7 +21,8 @@ COV = {"lowrank": 0, "fp64": 1, "fp32": 2, "bf16": 3}
 # Every symbol declared in include/mf.h.
 EXPORTS = ("mf_abi_version", "mf_options_default", "mf_status_str", "mf_last_error",
            "mf_plan_create", "mf_workspace_bytes", "mf_plan_columns", "mf_plan_pixels",
-           "mf_retrieve", "mf_plan_set_timing", "mf_plan_kernel_times", "mf_plan_destroy")
+           "mf_retrieve", "mf_plan_set_timing", "mf_plan_kernel_times", "mf_stream_read",
+           "mf_plan_destroy")
 KERNEL_KINDS = ("pass_gram", "pass_vec", "pass_last", "solve", "other")
 
 
@@ -78,6 +79,8 @@ def load_library(path: str = LIB_PATH):
     lib.mf_plan_kernel_times.restype = ctypes.c_int
     lib.mf_plan_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    lib.mf_stream_read.restype = ctypes.c_int
+    lib.mf_stream_read.argtypes = [vp, i64, vp, i32, ctypes.POINTER(ctypes.c_float), vp]
     if lib.mf_abi_version() != 1:
         raise ImportError("libmf.so ABI version mismatch")
     _lib = lib
@@ -184,6 +187,18 @@ class Plan:
             None if column_status is None else column_status.data_ptr(), ws_al,
             stream.cuda_stream))
         return alpha
+
+
+def stream_read_ms(x, n_blocks: int = 4096) -> float:
+    """Time one plain read of the float32 tensor x (the HBM read ceiling)."""
+    import torch
+    _need(x, torch.float32, "x")
+    sink = torch.empty(n_blocks, dtype=torch.float32, device=x.device)
+    ms = ctypes.c_float()
+    _check(load_library().mf_stream_read(x.data_ptr(), x.numel() - x.numel() % 4, sink.data_ptr(),
+                                         n_blocks, ctypes.byref(ms),
+                                         torch.cuda.current_stream(x.device).cuda_stream))
+    return ms.value
 
 
 def _need(t, dtype, name):

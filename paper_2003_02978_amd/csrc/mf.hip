@@ -77,18 +77,15 @@ struct WorkItem {
 
 // Per-column state, written by the solve kernel and read by the next pass.
 struct alignas(16) ColState {
-  float mu_f[kPad];    // mean subtracted by the next pass (FP32)
-  float t_f[kPad];     // target t = mu (.) s used by the next pass (FP32)
-  float v_f[kPad];     // v = C^-1 t (FP32)
-  float m0_f[kPad];    // mu^0 / |mu^0|^2, the albedo projection of Eq. 7
-  float lbar_f[kPad];  // FP32 copy of the plain mean mu^0
-  double mu[kPad];     // FP64 mu^j
-  double t[kPad];      // FP64 t^j
-  double lbar[kPad];   // FP64 plain mean mu^0
+  double mu[kPad];     // mu^j, subtracted by the next pass (shift z before pass 0)
+  double t[kPad];      // t^j = mu^j (.) s
+  double v[kPad];      // v^j = C^j^-1 t^j
+  double m0[kPad];     // mu^0 / |mu^0|^2, the albedo projection of Eq. 7
+  double lbar[kPad];   // plain mean mu^0
   double q;            // t^T C^-1 t
   double n_valid;      // N, from pass 0
-  float q_f;
   int32_t status;
+  int32_t pad[3];
 };
 
 struct PassArgs {
@@ -96,8 +93,9 @@ struct PassArgs {
   const uint8_t* valid;
   const WorkItem* items;
   const ColState* state;
-  const float* alpha_prev;   // alpha^{j-2} (j >= 2)
-  float* alpha_out;          // alpha^{j-1} (j >= 1)
+  const double* alpha_prev;  // alpha^{j-2} (j >= 2), FP64 workspace copy
+  double* alpha_out;         // alpha^{j-1} (1 <= j <= K), FP64 workspace copy
+  float* alpha_final;        // alpha^K (j = K + 1), the caller's FP32 output
   double* partials;          // [item][T][16][16] FP64
   int B;
   int j;
@@ -162,19 +160,15 @@ __global__ void __launch_bounds__(64) setup_kernel(const float* __restrict__ L,
   }
   ColState& st = state[col];
   for (int b = lane; b < kPad; b += 64) {
-    st.mu_f[b] = (z >= 0 && b < B) ? L[z * B + b] : 0.f;
-    st.t_f[b] = 0.f;
-    st.v_f[b] = 0.f;
-    st.m0_f[b] = 0.f;
-    st.lbar_f[b] = 0.f;
-    st.mu[b] = 0.0;
+    st.mu[b] = (z >= 0 && b < B) ? (double)L[z * B + b] : 0.0;
     st.t[b] = 0.0;
+    st.v[b] = 0.0;
+    st.m0[b] = 0.0;
     st.lbar[b] = 0.0;
   }
   if (lane == 0) {
     st.q = 1.0;
     st.n_valid = 0.0;
-    st.q_f = 1.f;
     st.status = z >= 0 ? MF_COL_OK : MF_COL_FEW_PIXELS;
   }
 }
@@ -182,38 +176,77 @@ __global__ void __launch_bounds__(64) setup_kernel(const float* __restrict__ L,
 // ---------------------------------------------------------------------------
 // pass: one streaming pass over a work item (a run of pixels of one column).
 //
-// Wave layout: a wave handles 4 pixels per sub-step, one per 16-lane row; the
-// lane in column c of the row holds bands c, c+16, ..., c+16(NB-1).  This is
-// at the same time the operand layout of v_mfma_f32_16x16x4_f32 (A[m][k] and
-// B[k][n] from lane m|n + 16k), so y of band block I against block J is one
-// MFMA per 4 pixels.  Eight sub-steps make a 32-pixel super-step, and the
-// same registers, packed to BF16, are the operands of v_mfma_f32_16x16x32_bf16
-// with pixel 4s+g of the super-step in k = 8g+s.  MFMA accumulators are
-// flushed to FP64 registers every FLUSH super-steps, which keeps the FP32
-// accumulation runs short (64 px for the FP32 Gram).
+// Wave layout: a wave handles 4 pixels per sub-step, one per 16-lane row.
+// The lane in column c of the row holds NB "register blocks" of that pixel;
+// block k, lane c holds band band_of<NB, WIDE>(k, c).  Narrow layout: band
+// c + 16k.  Wide layout (B >= 64): bands 4c..4c+3 in blocks 0..3 (one 16-byte
+// load) and band 64 + c in block 4 (one 4-byte load).  Either way the
+// registers of block I are, per 4 pixels, the A operand (A[m][k] from lane
+// m + 16k) and the B operand of a 16x16x4 MFMA, so the Gram of block I
+// against block J is one MFMA per 4 pixels; the solve undoes the band
+// permutation.  Eight sub-steps make a 32-pixel super-step; packed to BF16
+// the same registers are the operands of the 16x16x32 BF16 MFMA with pixel
+// 4s+g of the super-step in k = 8g+s.
+//
+// Per-pixel arithmetic (scores, albedo factor, alpha, moments) is FP64: near
+// the sparsity threshold the reweighting map alpha <- z - w has a derivative
+// far above 1 and amplifies any rounding, and FP64 costs the same VALU rate
+// as unpacked FP32 on CDNA.
 
-template <int NB>
+template <int NB, bool WIDE>
+__host__ __device__ constexpr int band_of(int k, int c) {
+  return WIDE ? (k < 4 ? 4 * c + k : 64 + c) : c + 16 * k;
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double row_sum16_f64(double x) {
+  x += dpp_f64<0xB1>(x);
+  x += dpp_f64<0x4E>(x);
+  x += dpp_f64<0x124>(x);
+  x += dpp_f64<0x128>(x);
+  return x;
+}
+
+template <int NB, bool WIDE, int S8>
 __device__ __forceinline__ void load_super(const PassArgs& a, int64_t base, int64_t end,
-                                           int row, int c16, float (&Lv)[8][NB],
-                                           float (&ap)[8], unsigned& okmask) {
+                                           int row, int c16, float (&Lv)[S8][NB],
+                                           double (&ap)[S8], unsigned& okmask) {
+  static_assert(S8 == 8, "a super-step is 8 sub-steps");
   okmask = 0;
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     const int64_t px = base + 4 * s + row;
     const bool inb = px < end;
+    const float* pl = a.L + px * a.B;
+    if constexpr (WIDE) {
+      float4 v4 = float4{0.f, 0.f, 0.f, 0.f};
+      if (inb) v4 = *reinterpret_cast<const float4*>(pl + 4 * c16);   // 4-byte aligned rows
+      Lv[s][0] = v4.x;
+      Lv[s][1] = v4.y;
+      Lv[s][2] = v4.z;
+      Lv[s][3] = v4.w;
+      Lv[s][4] = (inb && 64 + c16 < a.B) ? pl[64 + c16] : 0.f;
+    } else {
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      const int b = c16 + 16 * k;
-      Lv[s][k] = (inb && b < a.B) ? a.L[px * a.B + b] : 0.f;
+      for (int k = 0; k < NB; ++k) {
+        const int b = band_of<NB, WIDE>(k, c16);
+        Lv[s][k] = (inb && b < a.B) ? pl[b] : 0.f;
+      }
     }
-    ap[s] = (inb && a.alpha_prev) ? a.alpha_prev[px] : 0.f;
+    ap[s] = (inb && a.alpha_prev) ? a.alpha_prev[px] : 0.0;
     bool ok = inb;
     if (inb && a.valid) ok = a.valid[px] != 0;
     okmask |= (ok ? 1u : 0u) << s;
   }
 }
 
-template <int NB, int MODE>
+template <int NB, bool WIDE, int MODE>
 __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
   constexpr int T = n_tiles(NB);
   constexpr bool GRAM = MODE >= PM_F64;
@@ -228,23 +261,26 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
   const int64_t begin = it.px_begin, end = begin + it.n_px;
 
   if (st.status != MF_COL_OK) {          // failed column: alpha = 0, no moments
-    if (a.alpha_out)
-      for (int64_t px = begin + tid; px < end; px += kBlock) a.alpha_out[px] = 0.f;
+    for (int64_t px = begin + tid; px < end; px += kBlock) {
+      if (a.alpha_out) a.alpha_out[px] = 0.0;
+      if (a.alpha_final) a.alpha_final[px] = 0.f;
+    }
     return;
   }
 
-  float mu[NB], vv[NB], tt[NB], m0[NB], lb[NB];
+  double mu[NB], vv[NB], tt[NB], m0[NB], lb[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
-    const int b = c16 + 16 * k;
+    const int b = band_of<NB, WIDE>(k, c16);
     const bool in = b < B;
-    mu[k] = in ? st.mu_f[b] : 0.f;
-    vv[k] = in ? st.v_f[b] : 0.f;
-    tt[k] = in ? st.t_f[b] : 0.f;
-    m0[k] = in ? st.m0_f[b] : 0.f;
-    lb[k] = in ? st.lbar_f[b] : 0.f;
+    mu[k] = in ? st.mu[b] : 0.0;
+    vv[k] = in ? st.v[b] : 0.0;
+    tt[k] = in ? st.t[b] : 0.0;
+    m0[k] = in ? st.m0[b] : 0.0;
+    lb[k] = in ? st.lbar[b] : 0.0;
   }
-  const float q = st.q_f;
+  const double q = st.q;
+  const double lam = a.lam, eps = a.eps;
   const int j = a.j;
 
   [[maybe_unused]] floatx4 acc[F32ACC ? T : 1];
@@ -263,63 +299,72 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
     for (int k = 0; k < NB; ++k) md[k] = 0.0;
   }
 
-  float Lc[8][NB], apc[8];
+  // The MFMA-bound Gram passes run one wave per SIMD and prefetch the next
+  // super-step explicitly; the streaming passes keep fewer registers and
+  // hide latency with more waves instead.
+  constexpr bool PREFETCH = GRAM;
+  float Lc[8][NB];
+  double apc[8];
   unsigned okc = 0;
   int64_t base = begin + 32 * wid;
-  if (base < end) load_super<NB>(a, base, end, row, c16, Lc, apc, okc);
+  if (PREFETCH && base < end) load_super<NB, WIDE, 8>(a, base, end, row, c16, Lc, apc, okc);
   int nsuper = 0;
 
   for (; base < end; base += 128) {
-    float Ln[8][NB], apn[8];
-    unsigned okn = 0;
-    if (base + 128 < end) load_super<NB>(a, base + 128, end, row, c16, Ln, apn, okn);
+    [[maybe_unused]] float Ln[PREFETCH ? 8 : 1][NB];
+    [[maybe_unused]] double apn[PREFETCH ? 8 : 1];
+    [[maybe_unused]] unsigned okn = 0;
+    if constexpr (PREFETCH) {
+      if (base + 128 < end) load_super<NB, WIDE, 8>(a, base + 128, end, row, c16, Ln, apn, okn);
+    } else {
+      load_super<NB, WIDE, 8>(a, base, end, row, c16, Lc, apc, okc);
+    }
 
     [[maybe_unused]] bf16x8 ybf[NB];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       const int64_t px = base + 4 * s + row;
       const bool ok = (okc >> s) & 1u;
-      float x[NB];
-      float pp = 0.f, rr = 0.f;
+      double x[NB], l[NB];
+      double pp = 0.0, rr = 0.0;
 #pragma unroll
       for (int k = 0; k < NB; ++k) {
-        const float l = ok ? Lc[s][k] : 0.f;
-        x[k] = ok ? l - mu[k] : 0.f;
-        pp = fmaf(x[k], vv[k], pp);
-        rr = fmaf(l, m0[k], rr);
+        const bool in = ok && band_of<NB, WIDE>(k, c16) < B;
+        l[k] = in ? (double)Lc[s][k] : 0.0;
+        x[k] = in ? l[k] - mu[k] : 0.0;
+        pp = fma(x[k], vv[k], pp);
+        rr = fma(l[k], m0[k], rr);
       }
-      pp = row_sum16(pp);
-      rr = row_sum16(rr);
-      float c = 0.f;
+      pp = row_sum16_f64(pp);
+      rr = row_sum16_f64(rr);
+      double c = 0.0;
       if (j >= 1) {
-        const float r = a.albedo ? rr : 1.f;
-        const float num = (j == 1) ? pp : pp - a.lam / (apc[s] + a.eps);
-        float al = num / (r * q);
-        const bool dark = !(r > 0.f);
-        if (!a.unclamped) al = al > 0.f ? al : 0.f;
-        if (!ok || dark) al = 0.f;
-        if (c16 == 0 && px < end) a.alpha_out[px] = al;
-        c = (ok && !dark && al > 0.f) ? r * al : 0.f;
+        const double r = a.albedo ? rr : 1.0;
+        const double num = (j == 1) ? pp : pp - lam / (apc[s] + eps);
+        double al = num / (r * q);
+        const bool dark = !(r > 0.0);
+        if (!a.unclamped) al = al > 0.0 ? al : 0.0;
+        if (!ok || dark) al = 0.0;
+        if (c16 == 0 && px < end) {
+          if (a.alpha_out) a.alpha_out[px] = al;
+          if (a.alpha_final) a.alpha_final[px] = (float)al;
+        }
+        c = (ok && !dark && al > 0.0) ? r * al : 0.0;
       }
       if constexpr (MODE == PM_VEC) {
-        // FP64: L - lbar of two FP32 values is exact, and the rank-3 update
-        // cancels the plume's contribution to C^0, so m is kept exact-ish.
-        const double cd = (double)c;
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-          const float l = ok ? Lc[s][k] : lb[k];
-          md[k] = fma(cd, (double)l - (double)lb[k], md[k]);
-        }
-        s1d += cd;
-        s2d = fma(cd, cd, s2d);
+        for (int k = 0; k < NB; ++k)
+          md[k] = fma(c, l[k] - lb[k], md[k]);   // c = 0 off valid pixels
+        s1d += c;
+        s2d = fma(c, c, s2d);
       }
       if constexpr (GRAM) {
-        float y[NB];
+        double y[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
-          const int b = c16 + 16 * k;
-          y[k] = fmaf(-c, tt[k], x[k]);
-          if (b == B) y[k] = ok ? 1.f : 0.f;
+          const int b = band_of<NB, WIDE>(k, c16);
+          y[k] = fma(-c, tt[k], x[k]);
+          if (b == B) y[k] = ok ? 1.0 : 0.0;
           if (b == B + 1) y[k] = c;
         }
         if constexpr (MODE == PM_F64) {
@@ -327,18 +372,21 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
           for (int I = 0; I < NB; ++I)
 #pragma unroll
             for (int J = 0; J <= I; ++J)
-              dacc[n_tiles(I) + J] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                  (double)y[I], (double)y[J], dacc[n_tiles(I) + J], 0, 0, 0);
+              dacc[n_tiles(I) + J] =
+                  __builtin_amdgcn_mfma_f64_16x16x4f64(y[I], y[J], dacc[n_tiles(I) + J], 0, 0, 0);
         } else if constexpr (MODE == PM_F32) {
+          float yf[NB];
+#pragma unroll
+          for (int k = 0; k < NB; ++k) yf[k] = (float)y[k];
 #pragma unroll
           for (int I = 0; I < NB; ++I)
 #pragma unroll
             for (int J = 0; J <= I; ++J)
               acc[n_tiles(I) + J] =
-                  __builtin_amdgcn_mfma_f32_16x16x4f32(y[I], y[J], acc[n_tiles(I) + J], 0, 0, 0);
+                  __builtin_amdgcn_mfma_f32_16x16x4f32(yf[I], yf[J], acc[n_tiles(I) + J], 0, 0, 0);
         } else {
 #pragma unroll
-          for (int k = 0; k < NB; ++k) ybf[k][s] = (__bf16)y[k];
+          for (int k = 0; k < NB; ++k) ybf[k][s] = (__bf16)(float)y[k];
         }
       }
     }
@@ -361,13 +409,15 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
         }
       }
     }
+    if constexpr (PREFETCH) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      apc[s] = apn[s];
+      for (int s = 0; s < 8; ++s) {
+        apc[s] = apn[s];
 #pragma unroll
-      for (int k = 0; k < NB; ++k) Lc[s][k] = Ln[s][k];
+        for (int k = 0; k < NB; ++k) Lc[s][k] = Ln[s][k];
+      }
+      okc = okn;
     }
-    okc = okn;
   }
 
   double* out = a.partials + (int64_t)blockIdx.x * (T * 256);
@@ -400,9 +450,12 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
     // 16 (wave, row) partials per band, summed in a fixed order.
     __shared__ double redv[16 * 82];
     const int slot = (wid * 4 + row) * 82;
+    for (int b = c16; b < kVecM; b += 16) redv[slot + b] = 0.0;
 #pragma unroll
-    for (int k = 0; k < NB; ++k) redv[slot + c16 + 16 * k] = md[k];
-    for (int b = c16 + 16 * NB; b < kVecM; b += 16) redv[slot + b] = 0.0;
+    for (int k = 0; k < NB; ++k) {
+      const int b = band_of<NB, WIDE>(k, c16);
+      if (b < B) redv[slot + b] = md[k];
+    }
     if (c16 == 0) {           // every lane of a row holds the same c
       redv[slot + kVecS1] = s1d;
       redv[slot + kVecS2] = s2d;
@@ -421,38 +474,81 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
 // Eq. 11 (or the sample covariance for j = 0), Cholesky, v = C^-1 t with
 // iterative refinement, q = t^T v.
 
-template <int NB>
+// Register block and lane column holding band b (inverse of band_of).
+template <int NB, bool WIDE>
+__device__ __forceinline__ void block_of(int b, int& blk, int& m) {
+  if (WIDE) {
+    blk = b < 64 ? (b & 3) : 4;
+    m = b < 64 ? (b >> 2) : b - 64;
+  } else {
+    blk = b >> 4;
+    m = b & 15;
+  }
+}
+
+// G[i][j] summed over the column's work items (tiles hold block I >= J).
+template <int NB, bool WIDE>
 __device__ __forceinline__ double gram_elem(const double* __restrict__ P, int n_items,
-                                            int i, int j) {  // i >= j
+                                            int i, int j) {
   constexpr int T = n_tiles(NB);
-  const int I = i >> 4, J = j >> 4;
-  const int e = (n_tiles(I) + J) * 256 + (i & 15) * 16 + (j & 15);
+  int I, mi, J, mj;
+  block_of<NB, WIDE>(i, I, mi);
+  block_of<NB, WIDE>(j, J, mj);
+  if (I < J) {
+    const int t0 = I, t1 = mi;
+    I = J; mi = mj; J = t0; mj = t1;
+  }
+  const int e = (n_tiles(I) + J) * 256 + mi * 16 + mj;
   double g = 0.0;
   for (int it = 0; it < n_items; ++it) g += P[(int64_t)it * T * 256 + e];
   return g;
 }
 
-__device__ void chol_solve(const double* A, double* y, int B, int tid) {
-  // forward: L y' = y
-  for (int k = 0; k < B; ++k) {
-    if (tid == 0) y[k] /= A[tri(k, k)];
-    __syncthreads();
-    for (int i = k + 1 + tid; i < B; i += kBlock) y[i] -= A[tri(i, k)] * y[k];
-    __syncthreads();
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Wave-synchronous solve of L L^T v = y on one wave (64 lanes); the factor
+// is packed lower-triangular in LDS with inverse diagonal invd; the vector
+// lives in registers, lane l holding entries l and l + 64.
+__device__ void wave_chol_solve(const double* __restrict__ Lf, double invd_lo, double invd_hi,
+                                double& y_lo, double& y_hi, int B, int lane) {
+  const int i0 = lane, i1 = lane + 64;
+  for (int k = 0; k < B; ++k) {                     // forward: L y' = y
+    const bool lo = k < 64;
+    const double yk = readlane_f64(lo ? y_lo : y_hi, k & 63) *
+                      readlane_f64(lo ? invd_lo : invd_hi, k & 63);
+    if (i0 == k) y_lo = yk;
+    if (i1 == k) y_hi = yk;
+    if (i0 > k && i0 < B) y_lo -= Lf[tri(i0, k)] * yk;
+    if (i1 > k && i1 < B) y_hi -= Lf[tri(i1, k)] * yk;
   }
-  // backward: L^T v = y'
-  for (int k = B - 1; k >= 0; --k) {
-    if (tid == 0) y[k] /= A[tri(k, k)];
-    __syncthreads();
-    for (int i = tid; i < k; i += kBlock) y[i] -= A[tri(k, i)] * y[k];
-    __syncthreads();
+  for (int k = B - 1; k >= 0; --k) {                // backward: L^T v = y'
+    const bool lo = k < 64;
+    const double vk = readlane_f64(lo ? y_lo : y_hi, k & 63) *
+                      readlane_f64(lo ? invd_lo : invd_hi, k & 63);
+    if (i0 == k) y_lo = vk;
+    if (i1 == k) y_hi = vk;
+    if (i0 < k) y_lo -= Lf[tri(k, i0)] * vk;
+    if (i1 < k) y_hi -= Lf[tri(k, i1)] * vk;
   }
 }
 
-template <int NB>
+// One workgroup per column.  The symmetric matrix is split in 4x4 blocks of
+// the lower triangle; thread t < 210 keeps block (bi, bj), t = bi(bi+1)/2 + bj,
+// in registers through assembly and a right-looking Cholesky (two barriers
+// per column of the factor).
+constexpr int kBlk = 4;
+constexpr int kNBlkRows = kPad / kBlk;                            // 20
+constexpr int kNBlk = kNBlkRows * (kNBlkRows + 1) / 2;            // 210
+
+template <int NB, bool WIDE>
 __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   const int col = blockIdx.x;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
   ColState& st = a.state[col];
   if (st.status != MF_COL_OK) return;
   const ColInfo ci = a.cols[col];
@@ -461,14 +557,23 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   constexpr int T = n_tiles(NB);
   const double* P = a.partials + (int64_t)ci.first_item * T * 256;
   const bool rank3 = a.lowrank && j >= 1;
-  double* c0 = a.c0 + (int64_t)col * kMaxTri;
+  double* c0 = a.c0 + (int64_t)col * (kNBlk * 16);
 
-  __shared__ double A0[kMaxTri];     // C (kept for refinement)
-  __shared__ double A[kMaxTri];      // its Cholesky factor
+  __shared__ double Lf[kMaxTri];     // the factor, packed lower triangle
   __shared__ double g1[kPad], g2[kPad], D[kPad], E[kPad], tn[kPad], mun[kPad];
-  __shared__ double vv[kPad], rr[kPad];
+  __shared__ double colk[kPad], vbuf[kPad], rbuf[kPad], invd[kPad];
+  __shared__ double prow[kNBlk * kBlk], pcol[kNBlk * kBlk];
   __shared__ double sc[4];
+  __shared__ double sdiag;
   __shared__ int fail;
+
+  // block owned by this thread
+  int bi = 0, bj = 0;
+  const bool owner = tid < kNBlk;
+  if (owner) {
+    while ((bi + 1) * (bi + 2) / 2 <= tid) ++bi;
+    bj = tid - bi * (bi + 1) / 2;
+  }
 
   if (tid == 0) {
     if (rank3) {
@@ -481,9 +586,9 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
       sc[1] = s1;
       sc[2] = s2;
     } else {
-      sc[0] = gram_elem<NB>(P, ci.n_items, B, B);          // N
-      sc[1] = gram_elem<NB>(P, ci.n_items, B + 1, B);      // S1 = sum c
-      sc[2] = gram_elem<NB>(P, ci.n_items, B + 1, B + 1);  // S2 = sum c^2
+      sc[0] = gram_elem<NB, WIDE>(P, ci.n_items, B, B);          // N
+      sc[1] = gram_elem<NB, WIDE>(P, ci.n_items, B + 1, B);      // S1 = sum c
+      sc[2] = gram_elem<NB, WIDE>(P, ci.n_items, B + 1, B + 1);  // S2 = sum c^2
     }
     fail = 0;
   }
@@ -494,15 +599,15 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
       g1[b] = m;
       g2[b] = 0.0;
     } else {
-      g1[b] = gram_elem<NB>(P, ci.n_items, B, b);
-      g2[b] = gram_elem<NB>(P, ci.n_items, B + 1, b);
+      g1[b] = gram_elem<NB, WIDE>(P, ci.n_items, B, b);
+      g2[b] = gram_elem<NB, WIDE>(P, ci.n_items, B + 1, b);
     }
   }
   __syncthreads();
   const double N = sc[0], S1 = sc[1], S2 = sc[2];
   for (int b = tid; b < B; b += kBlock) {
-    const double mu_used = (double)st.mu_f[b];
-    const double t_used = (double)st.t_f[b];
+    const double mu_used = st.mu[b];           // what the pass subtracted
+    const double t_used = st.t[b];
     const double sb = (double)a.s[b];
     double m;
     if (j == 0) {
@@ -513,8 +618,6 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
     mun[b] = m;
     tn[b] = m * sb;                            // Eq. 9
     if (rank3) {
-      // m was accumulated about the FP32 mean: sum c (L - lbar_f)
-      g1[b] += S1 * ((double)st.lbar_f[b] - st.lbar[b]);
       D[b] = st.t[b] - tn[b];                  // t^{j-1} - t^j
       E[b] = 0.0;
     } else {
@@ -523,91 +626,181 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
     }
   }
   __syncthreads();
-  const int npk = B * (B + 1) / 2;
+
+  // ---- assembly of C (Eq. 11) into the register blocks
+  double A_[kBlk][kBlk], C_[kBlk][kBlk];
   const double abar = S1 / N;
-  for (int p = tid; p < npk; p += kBlock) {
-    int i = (int)((sqrtf(8.f * p + 1.f) - 1.f) * 0.5f);
-    while (tri(i, 0) > p) --i;
-    while (tri(i + 1, 0) <= p) ++i;
-    const int jj = p - tri(i, 0);
-    double c;
-    if (rank3) {
-      c = c0[p] + abar * abar * D[i] * D[jj] + (S2 / N - abar * abar) * tn[i] * tn[jj] -
-          (g1[i] * tn[jj] + tn[i] * g1[jj]) / N;
-    } else {
-      c = gram_elem<NB>(P, ci.n_items, i, jj);
-      c += g1[i] * D[jj] + D[i] * g1[jj] + g2[i] * E[jj] + E[i] * g2[jj] + N * D[i] * D[jj] +
-           S1 * (D[i] * E[jj] + E[i] * D[jj]) + S2 * E[i] * E[jj];
-      c /= N;
-      if (a.lowrank) c0[p] = c;                // j == 0: keep C^0
+  int myfail = 0;
+#pragma unroll
+  for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+    for (int y = 0; y < kBlk; ++y) {
+      const int i = kBlk * bi + x, jj = kBlk * bj + y;
+      double c = (i == jj) ? 1.0 : 0.0;        // padding keeps the factor regular
+      if (owner && i < B && jj < B && i >= jj) {
+        if (rank3) {
+          c = c0[tid * 16 + x * kBlk + y] + abar * abar * D[i] * D[jj] +
+              (S2 / N - abar * abar) * tn[i] * tn[jj] - (g1[i] * tn[jj] + tn[i] * g1[jj]) / N;
+        } else {
+          c = gram_elem<NB, WIDE>(P, ci.n_items, i, jj);
+          c += g1[i] * D[jj] + D[i] * g1[jj] + g2[i] * E[jj] + E[i] * g2[jj] +
+               N * D[i] * D[jj] + S1 * (D[i] * E[jj] + E[i] * D[jj]) + S2 * E[i] * E[jj];
+          c /= N;
+        }
+        if (!isfinite(c)) myfail = 1;
+      } else if (owner && i < B && jj < B) {
+        c = 0.0;                               // upper half of a diagonal block: unused
+      }
+      A_[x][y] = c;
+      C_[x][y] = c;
     }
-    if (!isfinite(c)) fail = 1;
-    A0[p] = c;
-    A[p] = c;
+  if (owner && a.lowrank && j == 0) {
+#pragma unroll
+    for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+      for (int y = 0; y < kBlk; ++y) c0[tid * 16 + x * kBlk + y] = A_[x][y];
   }
+  if (myfail) fail = 1;
   __syncthreads();
   if (N <= (double)B) {
     if (tid == 0) st.status = MF_COL_FEW_PIXELS;
     return;
   }
-  if (j == 0 && fail) {
-    if (tid == 0) st.status = MF_COL_NONFINITE;
-    return;
-  }
   if (fail) {
-    if (tid == 0) st.status = MF_COL_NOT_SPD;
+    if (tid == 0) st.status = j == 0 ? MF_COL_NONFINITE : MF_COL_NOT_SPD;
     return;
   }
-  // Right-looking Cholesky, packed lower triangle.
+
+  // ---- right-looking Cholesky on the register blocks
   for (int k = 0; k < B; ++k) {
-    if (tid == 0) {
-      const double d = A[tri(k, k)];
-      if (!(d > 0.0) || !isfinite(d)) fail = 1;
-      A[tri(k, k)] = sqrt(d > 0.0 ? d : 1.0);
+    const int kb = k >> 2, ka = k & 3;
+    if (owner && bi == kb && bj == kb) {
+      double dkk = 0.0;
+#pragma unroll
+      for (int x = 0; x < kBlk; ++x)
+        if (x == ka) dkk = A_[x][x];
+      sdiag = dkk;
     }
     __syncthreads();
-    if (fail) break;
-    const double piv = A[tri(k, k)];
-    for (int i = k + 1 + tid; i < B; i += kBlock) A[tri(i, k)] /= piv;
-    __syncthreads();
-    const int m = B - 1 - k;
-    const int ne = m * (m + 1) / 2;
-    for (int e = tid; e < ne; e += kBlock) {
-      int ii = (int)((sqrtf(8.f * e + 1.f) - 1.f) * 0.5f);
-      while (tri(ii, 0) > e) --ii;
-      while (tri(ii + 1, 0) <= e) ++ii;
-      const int i = k + 1 + ii, jx = k + 1 + (e - tri(ii, 0));
-      A[tri(i, jx)] -= A[tri(i, k)] * A[tri(jx, k)];
+    const double dkk = sdiag;
+    if (!(dkk > 0.0) || !isfinite(dkk)) {      // uniform
+      if (tid == 0) st.status = MF_COL_NOT_SPD;
+      return;
+    }
+    const double d = sqrt(dkk);
+    if (owner && bj == kb) {
+      const double inv = 1.0 / d;
+#pragma unroll
+      for (int x = 0; x < kBlk; ++x) {
+        const int i = kBlk * bi + x;
+#pragma unroll
+        for (int y = 0; y < kBlk; ++y) {
+          if (y != ka) continue;
+          if (i == k) A_[x][y] = d;
+          if (i > k) {
+            A_[x][y] *= inv;
+            colk[i] = A_[x][y];
+          }
+        }
+      }
     }
     __syncthreads();
+    if (owner && kBlk * bi + 3 > k) {
+      double cI[kBlk], cJ[kBlk];
+#pragma unroll
+      for (int x = 0; x < kBlk; ++x) {
+        cI[x] = colk[kBlk * bi + x];
+        cJ[x] = colk[kBlk * bj + x];
+      }
+#pragma unroll
+      for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+        for (int y = 0; y < kBlk; ++y) {
+          const int i = kBlk * bi + x, jj = kBlk * bj + y;
+          if (jj > k && i >= jj && i < B) A_[x][y] -= cI[x] * cJ[y];
+        }
+    }
   }
-  if (fail) {
-    if (tid == 0) st.status = MF_COL_NOT_SPD;
-    return;
+  // factor -> LDS, inverse diagonal
+  if (owner) {
+#pragma unroll
+    for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+      for (int y = 0; y < kBlk; ++y) {
+        const int i = kBlk * bi + x, jj = kBlk * bj + y;
+        if (i < B && jj <= i) {
+          Lf[tri(i, jj)] = A_[x][y];
+          if (i == jj) invd[i] = 1.0 / A_[x][y];
+        }
+      }
   }
-  for (int b = tid; b < B; b += kBlock) vv[b] = tn[b];
   __syncthreads();
-  chol_solve(A, vv, B, tid);
+
+  // ---- v = C^-1 t, then refinement against the assembled C
+  double y_lo = 0.0, y_hi = 0.0, id_lo = 0.0, id_hi = 0.0;
+  if (wid == 0) {
+    y_lo = lane < B ? tn[lane] : 0.0;
+    y_hi = lane + 64 < B ? tn[lane + 64] : 0.0;
+    id_lo = lane < B ? invd[lane] : 0.0;
+    id_hi = lane + 64 < B ? invd[lane + 64] : 0.0;
+    wave_chol_solve(Lf, id_lo, id_hi, y_lo, y_hi, B, lane);
+    if (lane < B) vbuf[lane] = y_lo;
+    if (lane + 64 < B) vbuf[lane + 64] = y_hi;
+  }
+  __syncthreads();
   for (int step = 0; step < a.refine; ++step) {
-    for (int i = tid; i < B; i += kBlock) {
-      double acc = tn[i];
-      for (int k = 0; k < B; ++k) acc -= A0[i >= k ? tri(i, k) : tri(k, i)] * vv[k];
-      rr[i] = acc;
+    // residual r = t - C v from the register blocks.  Block (bi, bj) holds
+    // C[i][jj] for jj <= i; by symmetry it also feeds row jj through C[i][jj]
+    // with jj < i.  prow collects the first kind per row i, pcol the second
+    // per row jj; each row then sums its blocks in a fixed order.
+    if (owner) {
+#pragma unroll
+      for (int x = 0; x < kBlk; ++x) {
+        double sr = 0.0;
+#pragma unroll
+        for (int y = 0; y < kBlk; ++y) {
+          const int i = kBlk * bi + x, jj = kBlk * bj + y;
+          if (i < B && jj <= i) sr += C_[x][y] * vbuf[jj];
+        }
+        prow[tid * kBlk + x] = sr;
+      }
+#pragma unroll
+      for (int y = 0; y < kBlk; ++y) {
+        double s = 0.0;
+#pragma unroll
+        for (int x = 0; x < kBlk; ++x) {
+          const int i = kBlk * bi + x, jj = kBlk * bj + y;
+          if (i < B && jj < i) s += C_[x][y] * vbuf[i];
+        }
+        pcol[tid * kBlk + y] = s;
+      }
     }
     __syncthreads();
-    chol_solve(A, rr, B, tid);
-    for (int i = tid; i < B; i += kBlock) vv[i] += rr[i];
+    for (int i = tid; i < B; i += kBlock) {
+      const int ib = i / kBlk, ix = i % kBlk;
+      double acc = 0.0;
+      for (int c = 0; c <= ib; ++c) acc += prow[(ib * (ib + 1) / 2 + c) * kBlk + ix];
+      for (int r = ib; r < kNBlkRows; ++r) acc += pcol[(r * (r + 1) / 2 + ib) * kBlk + ix];
+      rbuf[i] = tn[i] - acc;
+    }
+    __syncthreads();
+    if (wid == 0) {
+      double r_lo = lane < B ? rbuf[lane] : 0.0;
+      double r_hi = lane + 64 < B ? rbuf[lane + 64] : 0.0;
+      wave_chol_solve(Lf, id_lo, id_hi, r_lo, r_hi, B, lane);
+      if (lane < B) vbuf[lane] += r_lo;
+      if (lane + 64 < B) vbuf[lane + 64] += r_hi;
+    }
     __syncthreads();
   }
   if (tid == 0) {
     double q = 0.0, m2 = 0.0;
     for (int b = 0; b < B; ++b) {
-      q += tn[b] * vv[b];
+      q += tn[b] * vbuf[b];
       m2 += mun[b] * mun[b];
     }
     sc[3] = m2;
     st.q = q;
-    st.q_f = (float)q;
     if (j == 0) st.n_valid = N;
     if (!(q > 0.0) || !isfinite(q)) st.status = MF_COL_NOT_SPD;
   }
@@ -616,15 +809,28 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
     const bool in = b < B;
     st.mu[b] = in ? mun[b] : 0.0;
     st.t[b] = in ? tn[b] : 0.0;
-    st.mu_f[b] = in ? (float)mun[b] : 0.f;
-    st.t_f[b] = in ? (float)tn[b] : 0.f;
-    st.v_f[b] = in ? (float)vv[b] : 0.f;
+    st.v[b] = in ? vbuf[b] : 0.0;
     if (j == 0) {
       st.lbar[b] = in ? mun[b] : 0.0;
-      st.lbar_f[b] = in ? (float)mun[b] : 0.f;
-      st.m0_f[b] = in ? (float)(mun[b] / sc[3]) : 0.f;
+      st.m0[b] = in ? mun[b] / sc[3] : 0.0;
     }
   }
+}
+
+// Plain streaming read: the achievable HBM read bandwidth for this access
+// size, used as the measured ceiling next to the nominal 8 TB/s.
+__global__ void __launch_bounds__(kBlock) stream_read_kernel(const float4* __restrict__ src,
+                                                             int64_t n4, float* __restrict__ sink) {
+  float acc = 0.f;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += 4 * stride) {
+    float4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = (i + u * stride < n4) ? src[i + u * stride] : float4{0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+  }
+  if (acc == 1.2345e-30f) sink[blockIdx.x] = acc;   // keeps the loads alive
 }
 
 __global__ void status_kernel(const ColState* __restrict__ state, int32_t* __restrict__ out,
@@ -654,6 +860,7 @@ struct TimedLaunch {
 
 struct mf_plan_s {
   mf_options opt;
+  bool wide = false;         // band layout of the passes (B >= 64)
   bool timing = false;
   std::vector<TimedLaunch> pending;
   std::vector<hipEvent_t> event_pool;
@@ -703,25 +910,42 @@ struct LaunchTimer {
   }
 };
 
-template <int NB>
+template <int NB, bool WIDE>
 void launch_pass_nb(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t s) {
   const dim3 g((unsigned)p->n_items), b(kBlock);
   switch (mode) {
-    case PM_NONE: hipLaunchKernelGGL((pass_kernel<NB, PM_NONE>), g, b, 0, s, a); break;
-    case PM_VEC: hipLaunchKernelGGL((pass_kernel<NB, PM_VEC>), g, b, 0, s, a); break;
-    case PM_F64: hipLaunchKernelGGL((pass_kernel<NB, PM_F64>), g, b, 0, s, a); break;
-    case PM_F32: hipLaunchKernelGGL((pass_kernel<NB, PM_F32>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((pass_kernel<NB, PM_BF16>), g, b, 0, s, a); break;
+    case PM_NONE: hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_NONE>), g, b, 0, s, a); break;
+    case PM_VEC: hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_VEC>), g, b, 0, s, a); break;
+    case PM_F64: hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F64>), g, b, 0, s, a); break;
+    case PM_F32: hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F32>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16>), g, b, 0, s, a); break;
   }
 }
 
 void dispatch_pass(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t s) {
   switch (p->nb) {
-    case 1: launch_pass_nb<1>(p, a, mode, s); break;
-    case 2: launch_pass_nb<2>(p, a, mode, s); break;
-    case 3: launch_pass_nb<3>(p, a, mode, s); break;
-    case 4: launch_pass_nb<4>(p, a, mode, s); break;
-    default: launch_pass_nb<5>(p, a, mode, s); break;
+    case 1: launch_pass_nb<1, false>(p, a, mode, s); break;
+    case 2: launch_pass_nb<2, false>(p, a, mode, s); break;
+    case 3: launch_pass_nb<3, false>(p, a, mode, s); break;
+    case 4: launch_pass_nb<4, false>(p, a, mode, s); break;
+    default:
+      if (p->wide) launch_pass_nb<5, true>(p, a, mode, s);
+      else launch_pass_nb<5, false>(p, a, mode, s);
+      break;
+  }
+}
+
+void dispatch_solve(const mf_plan_s* p, const SolveArgs& a, hipStream_t s) {
+  const dim3 g((unsigned)p->n_cols), b(kBlock);
+  switch (p->nb) {
+    case 1: hipLaunchKernelGGL((solve_kernel<1, false>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((solve_kernel<2, false>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((solve_kernel<3, false>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((solve_kernel<4, false>), g, b, 0, s, a); break;
+    default:
+      if (p->wide) hipLaunchKernelGGL((solve_kernel<5, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((solve_kernel<5, false>), g, b, 0, s, a);
+      break;
   }
 }
 
@@ -736,16 +960,6 @@ int pass_mode(int cov, int j, int K) {
   }
 }
 
-void dispatch_solve(const mf_plan_s* p, const SolveArgs& a, hipStream_t s) {
-  const dim3 g((unsigned)p->n_cols), b(kBlock);
-  switch (p->nb) {
-    case 1: hipLaunchKernelGGL(solve_kernel<1>, g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL(solve_kernel<2>, g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL(solve_kernel<3>, g, b, 0, s, a); break;
-    case 4: hipLaunchKernelGGL(solve_kernel<4>, g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL(solve_kernel<5>, g, b, 0, s, a); break;
-  }
-}
 
 }  // namespace
 
@@ -852,6 +1066,7 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   if (!p) return fail_with(MF_E_ARG, "out of host memory");
   p->opt = *opt;
   p->nb = (opt->n_bands + 2 + 15) / 16;
+  p->wide = opt->n_bands >= 64;
   p->n_cols = (int64_t)cols.size();
   p->n_items = (int64_t)items.size();
   p->n_px = n_px;
@@ -874,11 +1089,11 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   p->off_partials = off;
   off = align256(off + (size_t)p->n_items * T * 256 * sizeof(double));
   p->off_c0 = off;
-  if (opt->cov == MF_COV_LOWRANK) off = align256(off + (size_t)p->n_cols * kMaxTri * sizeof(double));
+  if (opt->cov == MF_COV_LOWRANK) off = align256(off + (size_t)p->n_cols * kNBlk * 16 * sizeof(double));
   p->off_alpha0 = off;
-  off = align256(off + (size_t)max_px * sizeof(float));
+  off = align256(off + (size_t)max_px * sizeof(double));
   p->off_alpha1 = off;
-  off = align256(off + (size_t)max_px * sizeof(float));
+  off = align256(off + (size_t)max_px * sizeof(double));
   p->ws_bytes = off;
   *out = p;
   g_last_error.clear();
@@ -902,7 +1117,7 @@ mf_status mf_retrieve(mf_plan p, const float* radiance, const uint8_t* valid, co
   char* ws = (char*)workspace;
   ColState* state = (ColState*)(ws + p->off_state);
   double* partials = (double*)(ws + p->off_partials);
-  float* abuf[2] = {(float*)(ws + p->off_alpha0), (float*)(ws + p->off_alpha1)};
+  double* abuf[2] = {(double*)(ws + p->off_alpha0), (double*)(ws + p->off_alpha1)};
   const int B = p->opt.n_bands;
   const int K = p->opt.n_iter;
 
@@ -935,7 +1150,8 @@ mf_status mf_retrieve(mf_plan p, const float* radiance, const uint8_t* valid, co
     pa.j = j;
     pa.unclamped = (j == 1 && K == 0) ? 1 : 0;
     pa.alpha_prev = j >= 2 ? abuf[(j - 2) & 1] : nullptr;
-    pa.alpha_out = j == K + 1 ? alpha : (j >= 1 ? abuf[(j - 1) & 1] : nullptr);
+    pa.alpha_out = (j >= 1 && j <= K) ? abuf[(j - 1) & 1] : nullptr;
+    pa.alpha_final = j == K + 1 ? alpha : nullptr;
     const bool mom = j <= K;
     const int mode = pass_mode(p->opt.cov, j, K);
     {
@@ -957,6 +1173,31 @@ mf_status mf_retrieve(mf_plan p, const float* radiance, const uint8_t* valid, co
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail_with(MF_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
   return MF_OK;
+}
+
+mf_status mf_stream_read(const float* src, int64_t n, float* sink, int32_t n_blocks,
+                         float* ms_out, void* stream) {
+  if (!src || !sink || n < 4 || n % 4 != 0 || ((uintptr_t)src & 15) != 0 || n_blocks < 1)
+    return fail_with(MF_E_ARG, "src/sink NULL, n not a positive multiple of 4, or src not 16-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ms_out && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    return fail_with(MF_E_DEVICE, "event creation failed");
+  if (ms_out) (void)hipEventRecord(e0, st);
+  hipLaunchKernelGGL(stream_read_kernel, dim3((unsigned)n_blocks), dim3(kBlock), 0, st,
+                     (const float4*)src, n / 4, sink);
+  mf_status rc = MF_OK;
+  if (hipGetLastError() != hipSuccess) rc = fail_with(MF_E_DEVICE, "stream_read launch failed");
+  if (ms_out) {
+    float ms = 0.f;
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      rc = fail_with(MF_E_DEVICE, "event timing failed");
+    *ms_out = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  return rc;
 }
 
 mf_status mf_plan_set_timing(mf_plan p, int enable) {

@@ -109,12 +109,14 @@ struct SolveArgs {
   const ColInfo* cols;
   ColState* state;
   const double* partials;
-  double* c0;                // LOWRANK: packed C^0 per column
+  double* c0;                // LOWRANK: C^0 per column, register-block layout
+  double* pinv;              // LOWRANK: (C^0)^-1 per column, same layout
   const float* s;
   int B;
   int j;
   int refine;
   int lowrank;
+  int partial_stride;        // doubles per work item in the partial buffer
 };
 
 __host__ __device__ constexpr int n_tiles(int nb) { return nb * (nb + 1) / 2; }
@@ -544,6 +546,68 @@ constexpr int kBlk = 4;
 constexpr int kNBlkRows = kPad / kBlk;                            // 20
 constexpr int kNBlk = kNBlkRows * (kNBlkRows + 1) / 2;            // 210
 
+// Dot product of two LDS vectors (length B) on one wave; every lane gets it.
+__device__ __forceinline__ double wave_dot(const double* x, const double* y, int B, int lane) {
+  double s = 0.0;
+  for (int i = lane; i < B; i += 64) s += x[i] * y[i];
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
+
+// Block of the lower triangle owned by thread t (t = bi(bi+1)/2 + bj).
+__device__ __forceinline__ void block_coords(int t, int& bi, int& bj) {
+  bi = 0;
+  while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+  bj = t - bi * (bi + 1) / 2;
+}
+
+// y_r = M b_r (r < R) for a symmetric M held as lower 4x4 register blocks:
+// block (bi, bj) of thread t < kNBlk holds M[i][jj] for jj <= i; entries of
+// diagonal blocks above the diagonal and rows or columns >= B are zero, and
+// so are b_r[i >= B].  Vectors are LDS arrays of stride kPad; prow/pcol are
+// LDS scratch of R * kNBlk * kBlk doubles each.  Each row sums its blocks in
+// a fixed order (deterministic).  Contains two barriers.
+template <int R>
+__device__ void block_symv(const double (&M)[kBlk][kBlk], bool owner, int bi, int bj, int tid,
+                           int B, const double* bv, double* yv, double* prow, double* pcol) {
+  if (owner) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double* b = bv + r * kPad;
+#pragma unroll
+      for (int x = 0; x < kBlk; ++x) {
+        double s = 0.0;
+#pragma unroll
+        for (int y = 0; y < kBlk; ++y) s += M[x][y] * b[kBlk * bj + y];
+        prow[(r * kNBlk + tid) * kBlk + x] = s;
+      }
+#pragma unroll
+      for (int y = 0; y < kBlk; ++y) {
+        double s = 0.0;
+#pragma unroll
+        for (int x = 0; x < kBlk; ++x)
+          if (kBlk * bi + x > kBlk * bj + y) s += M[x][y] * b[kBlk * bi + x];
+        pcol[(r * kNBlk + tid) * kBlk + y] = s;
+      }
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < R * kPad; idx += kBlock) {
+    const int r = idx / kPad, i = idx - r * kPad;
+    if (i >= B) {
+      yv[r * kPad + i] = 0.0;
+      continue;
+    }
+    const int ib = i / kBlk, ix = i % kBlk;
+    double acc = 0.0;
+    for (int c = 0; c <= ib; ++c) acc += prow[(r * kNBlk + ib * (ib + 1) / 2 + c) * kBlk + ix];
+    for (int rr = ib; rr < kNBlkRows; ++rr)
+      acc += pcol[(r * kNBlk + rr * (rr + 1) / 2 + ib) * kBlk + ix];
+    yv[r * kPad + i] = acc;
+  }
+  __syncthreads();
+}
+
 template <int NB, bool WIDE>
 __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   const int col = blockIdx.x;
@@ -558,6 +622,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   const double* P = a.partials + (int64_t)ci.first_item * T * 256;
   const bool rank3 = a.lowrank && j >= 1;
   double* c0 = a.c0 + (int64_t)col * (kNBlk * 16);
+  double* pinv = a.pinv + (int64_t)col * (kNBlk * 16);
 
   __shared__ double Lf[kMaxTri];     // the factor, packed lower triangle
   __shared__ double g1[kPad], g2[kPad], D[kPad], E[kPad], tn[kPad], mun[kPad];
@@ -570,10 +635,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   // block owned by this thread
   int bi = 0, bj = 0;
   const bool owner = tid < kNBlk;
-  if (owner) {
-    while ((bi + 1) * (bi + 2) / 2 <= tid) ++bi;
-    bj = tid - bi * (bi + 1) / 2;
-  }
+  if (owner) block_coords(tid, bi, bj);
 
   if (tid == 0) {
     if (rank3) {
@@ -671,6 +733,78 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
     return;
   }
 
+  if (a.lowrank) {
+    // ---- low-rank form, pass 0: invert C^0 by symmetric sweeps on the
+    // register blocks (A <- -A^-1 after all pivots) and keep C^0 and its
+    // inverse for the rank-3 solves of later iterations.
+    for (int k = 0; k < B; ++k) {
+      const int kb = k >> 2, ka = k & 3;
+      if (owner && bi == kb && bj == kb) {
+        double dkk = 0.0;
+#pragma unroll
+        for (int x = 0; x < kBlk; ++x)
+          if (x == ka) dkk = A_[x][x];
+        sdiag = dkk;
+      }
+      __syncthreads();
+      const double d = sdiag;
+      if (!(d > 0.0) || !isfinite(d)) {      // uniform
+        if (tid == 0) st.status = MF_COL_NOT_SPD;
+        return;
+      }
+      if (owner) {                           // publish row/column k
+#pragma unroll
+        for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+          for (int y = 0; y < kBlk; ++y) {
+            const int i = kBlk * bi + x, jj = kBlk * bj + y;
+            if (jj == k && i > k && i < B) colk[i] = A_[x][y];
+            if (i == k && jj < k) colk[jj] = A_[x][y];
+          }
+      }
+      __syncthreads();
+      const double inv = 1.0 / d;
+      if (owner) {
+#pragma unroll
+        for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+          for (int y = 0; y < kBlk; ++y) {
+            const int i = kBlk * bi + x, jj = kBlk * bj + y;
+            if (i >= B || jj > i) continue;
+            if (i == k && jj == k) A_[x][y] = -inv;
+            else if (jj == k) A_[x][y] = colk[i] * inv;
+            else if (i == k) A_[x][y] = colk[jj] * inv;
+            else A_[x][y] -= colk[i] * colk[jj] * inv;
+          }
+      }
+    }
+    // P = (C^0)^-1; rows/columns >= B zero
+#pragma unroll
+    for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+      for (int y = 0; y < kBlk; ++y) {
+        const int i = kBlk * bi + x, jj = kBlk * bj + y;
+        A_[x][y] = (owner && i < B && jj <= i) ? -A_[x][y] : 0.0;
+        if (!(owner && i < B && jj <= i)) C_[x][y] = 0.0;
+      }
+    if (owner) {
+#pragma unroll
+      for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+        for (int y = 0; y < kBlk; ++y) pinv[tid * 16 + x * kBlk + y] = A_[x][y];
+    }
+    for (int b = tid; b < kPad; b += kBlock) rbuf[b] = b < B ? tn[b] : 0.0;
+    __syncthreads();
+    block_symv<1>(A_, owner, bi, bj, tid, B, rbuf, vbuf, prow, pcol);   // v = P t
+    for (int step = 0; step < a.refine; ++step) {
+      block_symv<1>(C_, owner, bi, bj, tid, B, vbuf, colk, prow, pcol);  // C v
+      for (int b = tid; b < kPad; b += kBlock) rbuf[b] = b < B ? tn[b] - colk[b] : 0.0;
+      __syncthreads();
+      block_symv<1>(A_, owner, bi, bj, tid, B, rbuf, colk, prow, pcol);  // P r
+      for (int b = tid; b < B; b += kBlock) vbuf[b] += colk[b];
+      __syncthreads();
+    }
+  } else {
   // ---- right-looking Cholesky on the register blocks
   for (int k = 0; k < B; ++k) {
     const int kb = k >> 2, ka = k & 3;
@@ -734,6 +868,15 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
         }
       }
   }
+  // residual matrix: zero outside the lower triangle of the first B rows
+#pragma unroll
+  for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+    for (int y = 0; y < kBlk; ++y) {
+      const int i = kBlk * bi + x, jj = kBlk * bj + y;
+      if (!(owner && i < B && jj <= i)) C_[x][y] = 0.0;
+    }
+  for (int b = tid; b < kPad; b += kBlock) vbuf[b] = 0.0;
   __syncthreads();
 
   // ---- v = C^-1 t, then refinement against the assembled C
@@ -749,40 +892,8 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   }
   __syncthreads();
   for (int step = 0; step < a.refine; ++step) {
-    // residual r = t - C v from the register blocks.  Block (bi, bj) holds
-    // C[i][jj] for jj <= i; by symmetry it also feeds row jj through C[i][jj]
-    // with jj < i.  prow collects the first kind per row i, pcol the second
-    // per row jj; each row then sums its blocks in a fixed order.
-    if (owner) {
-#pragma unroll
-      for (int x = 0; x < kBlk; ++x) {
-        double sr = 0.0;
-#pragma unroll
-        for (int y = 0; y < kBlk; ++y) {
-          const int i = kBlk * bi + x, jj = kBlk * bj + y;
-          if (i < B && jj <= i) sr += C_[x][y] * vbuf[jj];
-        }
-        prow[tid * kBlk + x] = sr;
-      }
-#pragma unroll
-      for (int y = 0; y < kBlk; ++y) {
-        double s = 0.0;
-#pragma unroll
-        for (int x = 0; x < kBlk; ++x) {
-          const int i = kBlk * bi + x, jj = kBlk * bj + y;
-          if (i < B && jj < i) s += C_[x][y] * vbuf[i];
-        }
-        pcol[tid * kBlk + y] = s;
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < B; i += kBlock) {
-      const int ib = i / kBlk, ix = i % kBlk;
-      double acc = 0.0;
-      for (int c = 0; c <= ib; ++c) acc += prow[(ib * (ib + 1) / 2 + c) * kBlk + ix];
-      for (int r = ib; r < kNBlkRows; ++r) acc += pcol[(r * (r + 1) / 2 + ib) * kBlk + ix];
-      rbuf[i] = tn[i] - acc;
-    }
+    block_symv<1>(C_, owner, bi, bj, tid, B, vbuf, rbuf, prow, pcol);   // C v
+    for (int b = tid; b < B; b += kBlock) rbuf[b] = tn[b] - rbuf[b];
     __syncthreads();
     if (wid == 0) {
       double r_lo = lane < B ? rbuf[lane] : 0.0;
@@ -793,16 +904,16 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
     }
     __syncthreads();
   }
-  if (tid == 0) {
-    double q = 0.0, m2 = 0.0;
-    for (int b = 0; b < B; ++b) {
-      q += tn[b] * vbuf[b];
-      m2 += mun[b] * mun[b];
+  }
+  if (wid == 0) {
+    const double q = wave_dot(tn, vbuf, B, lane);
+    const double m2 = wave_dot(mun, mun, B, lane);
+    if (lane == 0) {
+      sc[3] = m2;
+      st.q = q;
+      if (j == 0) st.n_valid = N;
+      if (!(q > 0.0) || !isfinite(q)) st.status = MF_COL_NOT_SPD;
     }
-    sc[3] = m2;
-    st.q = q;
-    if (j == 0) st.n_valid = N;
-    if (!(q > 0.0) || !isfinite(q)) st.status = MF_COL_NOT_SPD;
   }
   __syncthreads();
   for (int b = tid; b < kPad; b += kBlock) {
@@ -814,6 +925,180 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
       st.lbar[b] = in ? mun[b] : 0.0;
       st.m0[b] = in ? mun[b] / sc[3] : 0.0;
     }
+  }
+}
+
+// Low-rank form, iterations j >= 1: C^j = C^0 + U S U^T with U = [D, t, m],
+//   D = t^{j-1} - t^j, S = [[a^2, 0, 0], [0, S2/N - a^2, -1/N], [0, -1/N, 0]],
+// (the rank-3 identity), solved with the stored P = (C^0)^-1 by Woodbury:
+//   C^-1 b = P b - X (I + S W)^-1 S U^T P b,  X = P U,  W = U^T X,
+// followed by refinement steps against C^j applied exactly.  Everything is
+// matrix-vector products on the register blocks: no sequential factorisation.
+__global__ void __launch_bounds__(kBlock) lowrank_kernel(SolveArgs a) {
+  const int col = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  ColState& st = a.state[col];
+  if (st.status != MF_COL_OK) return;
+  const ColInfo ci = a.cols[col];
+  const int B = a.B;
+  const int64_t stride = (int64_t)a.partial_stride;
+  const double* P = a.partials + (int64_t)ci.first_item * stride;
+  const double* c0 = a.c0 + (int64_t)col * (kNBlk * 16);
+  const double* pinv = a.pinv + (int64_t)col * (kNBlk * 16);
+
+  __shared__ double U3[3 * kPad];   // D, t, m
+  __shared__ double X3[3 * kPad];   // P D, P t, P m
+  __shared__ double mun[kPad], vbuf[kPad], rbuf[kPad], wbuf[kPad], zbuf[kPad];
+  __shared__ double prow[3 * kNBlk * kBlk], pcol[3 * kNBlk * kBlk];
+  __shared__ double sc[4];
+  __shared__ double G3[9], S3[9], Ginv[9];
+  __shared__ int bad;
+
+  int bi = 0, bj = 0;
+  const bool owner = tid < kNBlk;
+  if (owner) block_coords(tid, bi, bj);
+  double Cb[kBlk][kBlk], Pb[kBlk][kBlk];
+#pragma unroll
+  for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+    for (int y = 0; y < kBlk; ++y) {
+      Cb[x][y] = owner ? c0[tid * 16 + x * kBlk + y] : 0.0;
+      Pb[x][y] = owner ? pinv[tid * 16 + x * kBlk + y] : 0.0;
+    }
+  if (tid == 0) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int it = 0; it < ci.n_items; ++it) {
+      s1 += P[it * stride + kVecS1];
+      s2 += P[it * stride + kVecS2];
+    }
+    sc[0] = st.n_valid;
+    sc[1] = s1;
+    sc[2] = s2;
+    bad = 0;
+  }
+  __syncthreads();
+  const double N = sc[0], S1 = sc[1], S2 = sc[2];
+  const double abar = S1 / N;
+  for (int b = tid; b < kPad; b += kBlock) {
+    double m = 0.0, mu = 0.0, t = 0.0, d = 0.0;
+    if (b < B) {
+      for (int it = 0; it < ci.n_items; ++it) m += P[it * stride + b];
+      mu = st.lbar[b] - abar * st.t[b];          // Eq. 10
+      t = mu * (double)a.s[b];                   // Eq. 9
+      d = st.t[b] - t;
+    }
+    mun[b] = mu;
+    U3[b] = d;
+    U3[kPad + b] = t;
+    U3[2 * kPad + b] = m;
+  }
+  __syncthreads();
+  block_symv<3>(Pb, owner, bi, bj, tid, B, U3, X3, prow, pcol);    // X = P U
+  if (wid == 0) {
+    // W = U^T X, S, and (I + S W)^-1 by Gauss-Jordan with partial pivoting
+    double W[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) W[r * 3 + c] = wave_dot(U3 + r * kPad, X3 + c * kPad, B, lane);
+    if (lane == 0) {
+      const double S[9] = {abar * abar, 0.0, 0.0, 0.0, S2 / N - abar * abar, -1.0 / N,
+                           0.0, -1.0 / N, 0.0};
+      double M[9], I3[9];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          double s = (r == c) ? 1.0 : 0.0;
+          for (int k = 0; k < 3; ++k) s += S[r * 3 + k] * W[k * 3 + c];
+          M[r * 3 + c] = s;
+          I3[r * 3 + c] = (r == c) ? 1.0 : 0.0;
+          S3[r * 3 + c] = S[r * 3 + c];
+        }
+      for (int k = 0; k < 3; ++k) {
+        int piv = k;
+        for (int r = k + 1; r < 3; ++r)
+          if (fabs(M[r * 3 + k]) > fabs(M[piv * 3 + k])) piv = r;
+        if (!(fabs(M[piv * 3 + k]) > 0.0)) bad = 1;
+        for (int c = 0; c < 3; ++c) {
+          double t0 = M[k * 3 + c]; M[k * 3 + c] = M[piv * 3 + c]; M[piv * 3 + c] = t0;
+          t0 = I3[k * 3 + c]; I3[k * 3 + c] = I3[piv * 3 + c]; I3[piv * 3 + c] = t0;
+        }
+        const double inv = 1.0 / M[k * 3 + k];
+        for (int c = 0; c < 3; ++c) {
+          M[k * 3 + c] *= inv;
+          I3[k * 3 + c] *= inv;
+        }
+        for (int r = 0; r < 3; ++r) {
+          if (r == k) continue;
+          const double f = M[r * 3 + k];
+          for (int c = 0; c < 3; ++c) {
+            M[r * 3 + c] -= f * M[k * 3 + c];
+            I3[r * 3 + c] -= f * I3[k * 3 + c];
+          }
+        }
+      }
+      for (int e = 0; e < 9; ++e) Ginv[e] = I3[e];
+      (void)G3;
+    }
+  }
+  __syncthreads();
+  if (bad) {
+    if (tid == 0) st.status = MF_COL_NOT_SPD;
+    return;
+  }
+  // v = Woodbury(t): P t is X3[1]
+  // correction coefficients z = (I + S W)^-1 S U^T y  with y = P b
+  // (computed by wave 0, applied by all threads)
+  for (int step = 0; step <= a.refine; ++step) {
+    const double* y = step == 0 ? (X3 + kPad) : wbuf;     // P b
+    if (wid == 0) {
+      double u[3];
+      for (int r = 0; r < 3; ++r) u[r] = wave_dot(U3 + r * kPad, y, B, lane);
+      if (lane == 0) {
+        double su[3], z[3];
+        for (int r = 0; r < 3; ++r) su[r] = S3[r * 3] * u[0] + S3[r * 3 + 1] * u[1] + S3[r * 3 + 2] * u[2];
+        for (int r = 0; r < 3; ++r) z[r] = Ginv[r * 3] * su[0] + Ginv[r * 3 + 1] * su[1] + Ginv[r * 3 + 2] * su[2];
+        sc[3] = 0.0;
+        zbuf[0] = z[0];
+        zbuf[1] = z[1];
+        zbuf[2] = z[2];
+      }
+    }
+    __syncthreads();
+    for (int b = tid; b < kPad; b += kBlock) {
+      const double corr = b < B ? y[b] - (X3[b] * zbuf[0] + X3[kPad + b] * zbuf[1] +
+                                          X3[2 * kPad + b] * zbuf[2]) : 0.0;
+      if (step == 0) vbuf[b] = corr;
+      else if (b < B) vbuf[b] += corr;
+    }
+    __syncthreads();
+    if (step == a.refine) break;
+    // residual r = t - C^j v with C^j v = C^0 v + U S U^T v
+    block_symv<1>(Cb, owner, bi, bj, tid, B, vbuf, rbuf, prow, pcol);
+    if (wid == 0) {
+      double u[3];
+      for (int r = 0; r < 3; ++r) u[r] = wave_dot(U3 + r * kPad, vbuf, B, lane);
+      if (lane == 0)
+        for (int r = 0; r < 3; ++r)
+          zbuf[4 + r] = S3[r * 3] * u[0] + S3[r * 3 + 1] * u[1] + S3[r * 3 + 2] * u[2];
+    }
+    __syncthreads();
+    for (int b = tid; b < kPad; b += kBlock)
+      rbuf[b] = b < B ? U3[kPad + b] - rbuf[b] -
+                            (U3[b] * zbuf[4] + U3[kPad + b] * zbuf[5] + U3[2 * kPad + b] * zbuf[6])
+                      : 0.0;
+    __syncthreads();
+    block_symv<1>(Pb, owner, bi, bj, tid, B, rbuf, wbuf, prow, pcol);  // P r
+  }
+  if (wid == 0) {
+    const double q = wave_dot(U3 + kPad, vbuf, B, lane);
+    if (lane == 0) {
+      st.q = q;
+      if (!(q > 0.0) || !isfinite(q)) st.status = MF_COL_NOT_SPD;
+    }
+  }
+  for (int b = tid; b < kPad; b += kBlock) {
+    st.mu[b] = mun[b];
+    st.t[b] = U3[kPad + b];
+    st.v[b] = vbuf[b];
   }
 }
 
@@ -869,7 +1154,7 @@ struct mf_plan_s {
   int64_t n_cols = 0, n_items = 0, n_px = 0, max_px = 0;
   ColInfo* cols_d = nullptr;
   WorkItem* items_d = nullptr;
-  size_t off_state = 0, off_partials = 0, off_c0 = 0, off_alpha0 = 0, off_alpha1 = 0;
+  size_t off_state = 0, off_partials = 0, off_c0 = 0, off_pinv = 0, off_alpha0 = 0, off_alpha1 = 0;
   size_t ws_bytes = 0;
 };
 
@@ -1090,6 +1375,8 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   off = align256(off + (size_t)p->n_items * T * 256 * sizeof(double));
   p->off_c0 = off;
   if (opt->cov == MF_COV_LOWRANK) off = align256(off + (size_t)p->n_cols * kNBlk * 16 * sizeof(double));
+  p->off_pinv = off;
+  if (opt->cov == MF_COV_LOWRANK) off = align256(off + (size_t)p->n_cols * kNBlk * 16 * sizeof(double));
   p->off_alpha0 = off;
   off = align256(off + (size_t)max_px * sizeof(double));
   p->off_alpha1 = off;
@@ -1142,6 +1429,8 @@ mf_status mf_retrieve(mf_plan p, const float* radiance, const uint8_t* valid, co
   sa.state = state;
   sa.partials = partials;
   sa.c0 = (double*)(ws + p->off_c0);
+  sa.pinv = (double*)(ws + p->off_pinv);
+  sa.partial_stride = n_tiles(p->nb) * 256;
   sa.s = s;
   sa.B = B;
   sa.refine = p->opt.refine_steps;
@@ -1162,7 +1451,10 @@ mf_status mf_retrieve(mf_plan p, const float* radiance, const uint8_t* valid, co
     if (mom) {
       sa.j = j;
       LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
-      dispatch_solve(p, sa, st);
+      if (sa.lowrank && j >= 1)
+        hipLaunchKernelGGL(lowrank_kernel, dim3((unsigned)p->n_cols), dim3(kBlock), 0, st, sa);
+      else
+        dispatch_solve(p, sa, st);
     }
   }
   if (column_status) {

@@ -101,8 +101,9 @@ struct PassArgs {
   int j;
   int albedo;
   int unclamped;             // K == 0: return alpha^0 without the clamp
-  float lam;
-  float eps;
+  double lam;
+  double eps;
+  int partial_stride;        // doubles per work item in the partial buffer
 };
 
 struct SolveArgs {
@@ -466,6 +467,218 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
     for (int e = tid; e < 82; e += kBlock) {
       double sum = 0.0;
       for (int w = 0; w < 16; ++w) sum += redv[w * 82 + e];
+      out[e] = sum;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stream pass (no Gram): alpha only (PM_NONE) or alpha plus the vector moments
+// of the low-rank form (PM_VEC).  One pixel per lane: each wave copies a
+// 64-pixel chunk of its work item into its own LDS tile with fully coalesced
+// loads (the next chunk is in flight while the current one is scored), then
+// every lane scores its own pixel from LDS with the column's constants as
+// wave-uniform scalar operands.  m = sum c (L - mean L) is accumulated
+// band-per-lane from the same tile, and skipped when the chunk has no
+// nonzero c (the enhancement is sparse).
+
+constexpr int kChunk = 64;                 // pixels per wave chunk
+constexpr int kSW = 2;                     // waves per stream workgroup
+constexpr int kSBlock = 64 * kSW;
+constexpr int kCopyGroup = 10;             // 16-byte loads in flight per lane while copying
+
+// Dynamic LDS bytes of stream_kernel for B bands (about 42 KB at 74 bands).
+__host__ __device__ constexpr size_t stream_lds_bytes(int B) {
+  return (size_t)kSW * kChunk * B * sizeof(float) + kSW * kChunk * sizeof(double) +
+         kSW * (kPad + 2) * sizeof(double) + 4 * kPad * sizeof(double);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
+  const WorkItem it = a.items[blockIdx.x];
+  const ColState* __restrict__ st = a.state + it.col;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int B = a.B;
+  const int64_t begin = it.px_begin, end = begin + it.n_px;
+  extern __shared__ double dyn[];
+  double* cbuf = dyn;                                   // [kSW][kChunk]
+  double* redm = cbuf + kSW * kChunk;                   // [kSW][kPad + 2]
+  double* cst = redm + kSW * (kPad + 2);                // [kPad][4]: mu, v, m0, lbar
+  float* my = reinterpret_cast<float*>(cst + 4 * kPad) + wid * kChunk * B;   // [kChunk][B]
+
+  if (st->status != MF_COL_OK) {           // failed column: alpha = 0, no moments
+    for (int64_t px = begin + tid; px < end; px += kSBlock) {
+      if (a.alpha_out) a.alpha_out[px] = 0.0;
+      if (a.alpha_final) a.alpha_final[px] = 0.f;
+    }
+    return;
+  }
+  for (int b = tid; b < kPad; b += kSBlock) {
+    cst[4 * b + 0] = st->mu[b];
+    cst[4 * b + 1] = st->v[b];
+    cst[4 * b + 2] = st->m0[b];
+    cst[4 * b + 3] = st->lbar[b];
+  }
+  __syncthreads();
+  const double q = st->q;
+  const double lam = a.lam, eps = a.eps;
+  const int j = a.j;
+  const uintptr_t lp = reinterpret_cast<uintptr_t>(a.L);
+
+  [[maybe_unused]] double m_lo = 0.0, m_hi = 0.0, s1 = 0.0, s2 = 0.0;
+
+  // Whole chunks whose bytes start on a 16-byte boundary are streamed with
+  // 16-byte loads, one chunk ahead in registers; other chunks are copied
+  // synchronously with 8- or 4-byte loads (never past the chunk).
+  constexpr int kF4 = (kChunk * 78 / 4 + 63) / 64;     // float4 per lane per chunk (20)
+  float4 pre[kF4];
+  auto fast = [&](int64_t c) {          // a whole, 16-byte aligned chunk
+    return c + kChunk <= end && ((lp + (uintptr_t)(c * B) * 4) & 15) == 0;
+  };
+  auto prefetch = [&](int64_t c) {
+    const float4* g4 = reinterpret_cast<const float4*>(a.L + c * B);
+    const int n4 = kChunk * B / 4;
+#pragma unroll
+    for (int k = 0; k < kF4; ++k) {
+      const int e = lane + 64 * k;
+      pre[k] = e < n4 ? g4[e] : float4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  int64_t c0 = begin + (int64_t)kChunk * wid;
+  bool have = c0 < end && fast(c0);
+  if (have) prefetch(c0);
+
+  for (; c0 < end; c0 += kSW * kChunk) {
+    const int n = (int)min<int64_t>(kChunk, end - c0);
+    const int nfl = n * B;
+    const float* g = a.L + c0 * B;
+    if (have) {
+      float4* t4 = reinterpret_cast<float4*>(my);
+      const int n4 = kChunk * B / 4;
+#pragma unroll
+      for (int k = 0; k < kF4; ++k) {
+        const int e = lane + 64 * k;
+        if (e < n4) t4[e] = pre[k];
+      }
+    } else {
+      const uintptr_t ga = lp + (uintptr_t)(c0 * B) * 4;
+      if ((ga & 7) == 0 && (nfl & 1) == 0) {
+        const float2* g2 = reinterpret_cast<const float2*>(g);
+        float2* t2 = reinterpret_cast<float2*>(my);
+        const int n2 = nfl / 2;
+        for (int base = 0; base < n2; base += 64 * kCopyGroup) {
+          float2 r[kCopyGroup];
+#pragma unroll
+          for (int k = 0; k < kCopyGroup; ++k) {
+            const int e = base + lane + 64 * k;
+            r[k] = e < n2 ? g2[e] : float2{0.f, 0.f};
+          }
+#pragma unroll
+          for (int k = 0; k < kCopyGroup; ++k) {
+            const int e = base + lane + 64 * k;
+            if (e < n2) t2[e] = r[k];
+          }
+        }
+      } else {
+        for (int e = lane; e < nfl; e += 64) my[e] = g[e];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    {
+      const int64_t nx = c0 + kSW * kChunk;
+      have = nx < end && fast(nx);
+      if (have) prefetch(nx);                 // in flight while this chunk is scored
+    }
+
+    // score this lane's pixel
+    const int64_t px = c0 + lane;
+    const bool inb = lane < n;
+    bool ok = inb;
+    if (inb && a.valid) ok = a.valid[px] != 0;
+    const double ap = (inb && a.alpha_prev) ? a.alpha_prev[px] : 0.0;
+    double pp = 0.0, rr = 0.0;
+    if (ok) {
+      const float* rowp = my + lane * B;
+      int b = 0;
+      if ((B & 1) == 0) {                     // pairs of bands: 8-byte tile reads
+#pragma unroll 4
+        for (; b < B; b += 2) {
+          const float2 l2 = *reinterpret_cast<const float2*>(rowp + b);
+          const double4 c0v = *reinterpret_cast<const double4*>(cst + 4 * b);
+          const double4 c1v = *reinterpret_cast<const double4*>(cst + 4 * b + 4);
+          const double l0 = (double)l2.x, l1 = (double)l2.y;
+          pp = fma(l0 - c0v.x, c0v.y, pp);
+          rr = fma(l0, c0v.z, rr);
+          pp = fma(l1 - c1v.x, c1v.y, pp);
+          rr = fma(l1, c1v.z, rr);
+        }
+      }
+      for (; b < B; ++b) {
+        const double l = (double)rowp[b];
+        pp = fma(l - cst[4 * b], cst[4 * b + 1], pp);
+        rr = fma(l, cst[4 * b + 2], rr);
+      }
+    }
+    double c = 0.0;
+    if (j >= 1) {
+      const double r = a.albedo ? rr : 1.0;
+      const double num = (j == 1) ? pp : pp - lam / (ap + eps);
+      double al = num / (r * q);
+      const bool dark = !(r > 0.0);
+      if (!a.unclamped) al = al > 0.0 ? al : 0.0;
+      if (!ok || dark) al = 0.0;
+      if (inb) {
+        if (a.alpha_out) a.alpha_out[px] = al;
+        if (a.alpha_final) a.alpha_final[px] = (float)al;
+      }
+      c = (ok && !dark && al > 0.0) ? r * al : 0.0;
+    }
+    if constexpr (MODE == PM_VEC) {
+      s1 += c;
+      s2 = fma(c, c, s2);
+      if (__ballot(c != 0.0)) {                 // wave-uniform
+        cbuf[wid * kChunk + lane] = c;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int b0 = lane, b1 = lane + 64;
+        const double lb0 = b0 < B ? cst[4 * b0 + 3] : 0.0;
+        const double lb1 = b1 < B ? cst[4 * b1 + 3] : 0.0;
+        for (int p = 0; p < n; ++p) {
+          const double cp = cbuf[wid * kChunk + p];
+          if (cp != 0.0) {                      // wave-uniform; skips invalid pixels too
+            if (b0 < B) m_lo = fma(cp, (double)my[p * B + b0] - lb0, m_lo);
+            if (b1 < B) m_hi = fma(cp, (double)my[p * B + b1] - lb1, m_hi);
+          }
+        }
+      }
+    }
+    // the tile is rewritten by this wave only after every lane is done with it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+
+  if constexpr (MODE == PM_VEC) {
+    for (int off = 32; off >= 1; off >>= 1) {
+      s1 += __shfl_xor(s1, off, 64);
+      s2 += __shfl_xor(s2, off, 64);
+    }
+    double* rw = redm + wid * (kPad + 2);
+    if (lane < kPad) rw[lane] = lane < B ? m_lo : 0.0;
+    if (lane + 64 < kPad) rw[lane + 64] = lane + 64 < B ? m_hi : 0.0;
+    if (lane == 0) {
+      rw[kVecS1] = s1;
+      rw[kVecS2] = s2;
+    }
+    __syncthreads();
+    double* out = a.partials + (int64_t)blockIdx.x * a.partial_stride;
+    for (int e = tid; e < kPad + 2; e += kSBlock) {
+      double sum = 0.0;
+      for (int w = 0; w < kSW; ++w) sum += redm[w * (kPad + 2) + e];
       out[e] = sum;
     }
   }
@@ -1199,8 +1412,6 @@ template <int NB, bool WIDE>
 void launch_pass_nb(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t s) {
   const dim3 g((unsigned)p->n_items), b(kBlock);
   switch (mode) {
-    case PM_NONE: hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_NONE>), g, b, 0, s, a); break;
-    case PM_VEC: hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_VEC>), g, b, 0, s, a); break;
     case PM_F64: hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F64>), g, b, 0, s, a); break;
     case PM_F32: hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F32>), g, b, 0, s, a); break;
     default: hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16>), g, b, 0, s, a); break;
@@ -1208,6 +1419,13 @@ void launch_pass_nb(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t
 }
 
 void dispatch_pass(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t s) {
+  if (mode == PM_NONE || mode == PM_VEC) {
+    const dim3 g((unsigned)p->n_items), b(kSBlock);
+    const size_t lds = stream_lds_bytes(a.B);
+    if (mode == PM_NONE) hipLaunchKernelGGL(stream_kernel<PM_NONE>, g, b, lds, s, a);
+    else hipLaunchKernelGGL(stream_kernel<PM_VEC>, g, b, lds, s, a);
+    return;
+  }
   switch (p->nb) {
     case 1: launch_pass_nb<1, false>(p, a, mode, s); break;
     case 2: launch_pass_nb<2, false>(p, a, mode, s); break;
@@ -1422,8 +1640,9 @@ mf_status mf_retrieve(mf_plan p, const float* radiance, const uint8_t* valid, co
   pa.partials = partials;
   pa.B = B;
   pa.albedo = p->opt.albedo;
-  pa.lam = (float)p->opt.lambda;
-  pa.eps = (float)p->opt.epsilon;
+  pa.lam = p->opt.lambda;
+  pa.eps = p->opt.epsilon;
+  pa.partial_stride = n_tiles(p->nb) * 256;
   SolveArgs sa{};
   sa.cols = p->cols_d;
   sa.state = state;

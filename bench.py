@@ -22,8 +22,8 @@ sys.path.insert(0, ROOT)
 METRIC = "retrieved pixels/s (74 bands, 30 iters): BF16-MFMA vs FP32 plain; fwd+bwd px/s"
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes of one streaming pass per pixel: the 74-band FP32
-# spectrum, alpha^{j-2} read and alpha^{j-1} written.
-PASS_BYTES_PER_PX = 74 * 4 + 4 + 4
+# spectrum, alpha^{j-2} read and alpha^{j-1} written (FP64 working copies).
+PASS_BYTES_PER_PX = 74 * 4 + 8 + 8
 SOURCE = os.path.join(ROOT, "paper_2003_02978_amd", "csrc", "mf.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -45,6 +45,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-lines", type=int, default=8000)
     ap.add_argument("--save-alpha", default="", help="save each form's alpha as <path>_<form>.npy")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain 1 GiB device copies (known bytes) for HBM counter scaling")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: every column is an independent problem, "
@@ -56,6 +58,16 @@ def main():
     import torch
     import paper_2003_02978_amd as mf
     from synth.scenes import flightline_spec, make_scene
+
+    if args.copy_calibration:
+        n = 1 << 28                                  # 2^28 floats = 1 GiB
+        x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {4 * n} bytes (read {4 * n}, write {4 * n} each)")
+        return
 
     cfg = json.load(open(os.path.join(ROOT, "configs", "flightline.json")))
     lam, K, eps = cfg["lambda"], cfg["n_iter"], cfg["epsilon"]

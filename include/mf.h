@@ -152,6 +152,13 @@ MF_API mf_status mf_retrieve(mf_plan plan, const float* radiance, const uint8_t*
                       const float* s, float* alpha, int32_t* column_status,
                       void* workspace, void* stream);
 
+/* Graph replay.  While enabled, mf_retrieve captures its launch sequence on
+   the caller's stream into a HIP graph the first time it sees a set of
+   pointers and stream, and replays it (one graph launch) on later calls with
+   the same set; a different set is captured anew.  Not used on the NULL
+   stream or while kernel timing is on (plain launches then). */
+MF_API mf_status mf_plan_set_graph(mf_plan plan, int enable);
+
 /* Kernel timing for benchmarks.  While enabled, mf_retrieve brackets each of
    its kernel launches with HIP events on the caller's stream (a few
    microseconds of extra stream work per launch). */

@@ -21,7 +21,7 @@ COV = {"lowrank": 0, "fp64": 1, "fp32": 2, "bf16": 3}
 # Every symbol declared in include/mf.h.
 EXPORTS = ("mf_abi_version", "mf_options_default", "mf_status_str", "mf_last_error",
            "mf_plan_create", "mf_workspace_bytes", "mf_plan_columns", "mf_plan_pixels",
-           "mf_retrieve", "mf_plan_set_timing", "mf_plan_kernel_times", "mf_stream_read",
+           "mf_retrieve", "mf_plan_set_graph", "mf_plan_set_timing", "mf_plan_kernel_times", "mf_stream_read",
            "mf_plan_destroy")
 KERNEL_KINDS = ("pass_gram", "pass_vec", "pass_last", "solve", "other")
 
@@ -74,6 +74,8 @@ def load_library(path: str = LIB_PATH):
     lib.mf_retrieve.restype = ctypes.c_int
     lib.mf_retrieve.argtypes = [vp] * 8
     lib.mf_plan_destroy.argtypes = [vp]
+    lib.mf_plan_set_graph.restype = ctypes.c_int
+    lib.mf_plan_set_graph.argtypes = [vp, ctypes.c_int]
     lib.mf_plan_set_timing.restype = ctypes.c_int
     lib.mf_plan_set_timing.argtypes = [vp, ctypes.c_int]
     lib.mf_plan_kernel_times.restype = ctypes.c_int
@@ -139,6 +141,10 @@ class Plan:
         except Exception:
             pass
 
+    def set_graph(self, enable: bool):
+        """Replay the launch sequence as one HIP graph (see mf_plan_set_graph)."""
+        _check(self._lib.mf_plan_set_graph(self._h, int(bool(enable))))
+
     def set_timing(self, enable: bool):
         _check(self._lib.mf_plan_set_timing(self._h, int(bool(enable))))
 
@@ -187,6 +193,48 @@ class Plan:
             None if column_status is None else column_status.data_ptr(), ws_al,
             stream.cuda_stream))
         return alpha
+
+
+def autotune_chunk(flightlines, radiance, s, valid=None, candidates=(512, 1024, 2048, 4096),
+                   reps: int = 3, cache_path: Optional[str] = None, **plan_kwargs):
+    """Pick chunk_lines (pixels per work item) for a batch geometry by timing
+    whole retrievals with each candidate; results are cached in a JSON file
+    keyed by the geometry, options and device.  Returns (best, {chunk: ms})."""
+    import hashlib
+    import json
+    import time
+    import torch
+    fls = [tuple(int(v) for v in f) for f in flightlines]
+    key_src = json.dumps([fls, sorted(plan_kwargs.items()), list(candidates),
+                          torch.cuda.get_device_name(radiance.device)], default=str)
+    key = hashlib.sha256(key_src.encode()).hexdigest()[:20]
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            return int(cache[key]["best"]), {int(k): v for k, v in cache[key]["ms"].items()}
+    max_px = max(a + b * c for a, b, c in fls)
+    alpha = torch.empty(max_px, dtype=torch.float32, device=radiance.device)
+    times = {}
+    for ch in candidates:
+        plan = Plan(fls, chunk_lines=int(ch), **plan_kwargs)
+        ws = plan.alloc_workspace(radiance.device)
+        plan.retrieve(radiance, s, alpha, valid, None, ws)
+        torch.cuda.synchronize(radiance.device)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.retrieve(radiance, s, alpha, valid, None, ws)
+        torch.cuda.synchronize(radiance.device)
+        times[int(ch)] = 1e3 * (time.perf_counter() - t0) / reps
+        plan.close()
+        del ws
+    best = min(times, key=times.get)
+    if cache_path:
+        cache[key] = {"best": best, "ms": times}
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return best, times
 
 
 def stream_read_ms(x, n_blocks: int = 4096) -> float:

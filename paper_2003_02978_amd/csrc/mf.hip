@@ -1351,6 +1351,14 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
+struct GraphKey {
+  const void *L, *valid, *s, *alpha, *status, *ws, *stream;
+  bool operator==(const GraphKey& o) const {
+    return L == o.L && valid == o.valid && s == o.s && alpha == o.alpha && status == o.status &&
+           ws == o.ws && stream == o.stream;
+  }
+};
+
 struct TimedLaunch {
   int kind;
   hipEvent_t start, stop;
@@ -1360,6 +1368,9 @@ struct mf_plan_s {
   mf_options opt;
   bool wide = false;         // band layout of the passes (B >= 64)
   bool timing = false;
+  bool use_graph = false;
+  GraphKey graph_key{};
+  hipGraphExec_t graph_exec = nullptr;
   std::vector<TimedLaunch> pending;
   std::vector<hipEvent_t> event_pool;
   int nb = 0;
@@ -1463,6 +1474,75 @@ int pass_mode(int cov, int j, int K) {
   }
 }
 
+
+}  // namespace
+
+namespace {
+// The launch sequence of one retrieval (also what a graph captures).
+void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid, const float* s,
+                      float* alpha, int32_t* column_status, void* workspace, hipStream_t st) {
+  char* ws = (char*)workspace;
+  ColState* state = (ColState*)(ws + p->off_state);
+  double* partials = (double*)(ws + p->off_partials);
+  double* abuf[2] = {(double*)(ws + p->off_alpha0), (double*)(ws + p->off_alpha1)};
+  const int B = p->opt.n_bands;
+  const int K = p->opt.n_iter;
+
+  {
+    LaunchTimer tm(p, MF_KERNEL_OTHER, st);
+    hipLaunchKernelGGL(setup_kernel, dim3((unsigned)p->n_cols), dim3(64), 0, st, radiance, valid,
+                       p->cols_d, state, B);
+  }
+  PassArgs pa{};
+  pa.L = radiance;
+  pa.valid = valid;
+  pa.items = p->items_d;
+  pa.state = state;
+  pa.partials = partials;
+  pa.B = B;
+  pa.albedo = p->opt.albedo;
+  pa.lam = p->opt.lambda;
+  pa.eps = p->opt.epsilon;
+  pa.partial_stride = n_tiles(p->nb) * 256;
+  SolveArgs sa{};
+  sa.cols = p->cols_d;
+  sa.state = state;
+  sa.partials = partials;
+  sa.c0 = (double*)(ws + p->off_c0);
+  sa.pinv = (double*)(ws + p->off_pinv);
+  sa.partial_stride = n_tiles(p->nb) * 256;
+  sa.s = s;
+  sa.B = B;
+  sa.refine = p->opt.refine_steps;
+  sa.lowrank = p->opt.cov == MF_COV_LOWRANK;
+  for (int j = 0; j <= K + 1; ++j) {
+    pa.j = j;
+    pa.unclamped = (j == 1 && K == 0) ? 1 : 0;
+    pa.alpha_prev = j >= 2 ? abuf[(j - 2) & 1] : nullptr;
+    pa.alpha_out = (j >= 1 && j <= K) ? abuf[(j - 1) & 1] : nullptr;
+    pa.alpha_final = j == K + 1 ? alpha : nullptr;
+    const bool mom = j <= K;
+    const int mode = pass_mode(p->opt.cov, j, K);
+    {
+      LaunchTimer tm(p, mode == PM_NONE ? MF_KERNEL_PASS_LAST
+                        : mode == PM_VEC ? MF_KERNEL_PASS_VEC : MF_KERNEL_PASS_GRAM, st);
+      dispatch_pass(p, pa, mode, st);
+    }
+    if (mom) {
+      sa.j = j;
+      LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
+      if (sa.lowrank && j >= 1)
+        hipLaunchKernelGGL(lowrank_kernel, dim3((unsigned)p->n_cols), dim3(kBlock), 0, st, sa);
+      else
+        dispatch_solve(p, sa, st);
+    }
+  }
+  if (column_status) {
+    const unsigned nb = (unsigned)((p->n_cols + 255) / 256);
+    LaunchTimer tm(p, MF_KERNEL_OTHER, st);
+    hipLaunchKernelGGL(status_kernel, dim3(nb), dim3(256), 0, st, state, column_status, p->n_cols);
+  }
+}
 
 }  // namespace
 
@@ -1619,70 +1699,43 @@ mf_status mf_retrieve(mf_plan p, const float* radiance, const uint8_t* valid, co
   if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
     return fail_with(MF_E_DEVICE, "current device differs from the plan's device");
   hipStream_t st = (hipStream_t)stream;
-  char* ws = (char*)workspace;
-  ColState* state = (ColState*)(ws + p->off_state);
-  double* partials = (double*)(ws + p->off_partials);
-  double* abuf[2] = {(double*)(ws + p->off_alpha0), (double*)(ws + p->off_alpha1)};
-  const int B = p->opt.n_bands;
-  const int K = p->opt.n_iter;
-
   (void)hipGetLastError();
-  {
-    LaunchTimer tm(p, MF_KERNEL_OTHER, st);
-    hipLaunchKernelGGL(setup_kernel, dim3((unsigned)p->n_cols), dim3(64), 0, st, radiance, valid,
-                       p->cols_d, state, B);
-  }
-  PassArgs pa{};
-  pa.L = radiance;
-  pa.valid = valid;
-  pa.items = p->items_d;
-  pa.state = state;
-  pa.partials = partials;
-  pa.B = B;
-  pa.albedo = p->opt.albedo;
-  pa.lam = p->opt.lambda;
-  pa.eps = p->opt.epsilon;
-  pa.partial_stride = n_tiles(p->nb) * 256;
-  SolveArgs sa{};
-  sa.cols = p->cols_d;
-  sa.state = state;
-  sa.partials = partials;
-  sa.c0 = (double*)(ws + p->off_c0);
-  sa.pinv = (double*)(ws + p->off_pinv);
-  sa.partial_stride = n_tiles(p->nb) * 256;
-  sa.s = s;
-  sa.B = B;
-  sa.refine = p->opt.refine_steps;
-  sa.lowrank = p->opt.cov == MF_COV_LOWRANK;
-  for (int j = 0; j <= K + 1; ++j) {
-    pa.j = j;
-    pa.unclamped = (j == 1 && K == 0) ? 1 : 0;
-    pa.alpha_prev = j >= 2 ? abuf[(j - 2) & 1] : nullptr;
-    pa.alpha_out = (j >= 1 && j <= K) ? abuf[(j - 1) & 1] : nullptr;
-    pa.alpha_final = j == K + 1 ? alpha : nullptr;
-    const bool mom = j <= K;
-    const int mode = pass_mode(p->opt.cov, j, K);
-    {
-      LaunchTimer tm(p, mode == PM_NONE ? MF_KERNEL_PASS_LAST
-                        : mode == PM_VEC ? MF_KERNEL_PASS_VEC : MF_KERNEL_PASS_GRAM, st);
-      dispatch_pass(p, pa, mode, st);
+  // Graph replay: the whole launch sequence captured once per set of
+  // pointers and stream (not on the legacy default stream, not while timing).
+  if (p->use_graph && st != nullptr && !p->timing) {
+    const GraphKey key{radiance, valid, s, alpha, column_status, workspace, stream};
+    if (!(p->graph_exec && p->graph_key == key)) {
+      if (p->graph_exec) {
+        (void)hipGraphExecDestroy(p->graph_exec);
+        p->graph_exec = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail_with(MF_E_DEVICE, "hipStreamBeginCapture failed");
+      enqueue_retrieve(p, radiance, valid, s, alpha, column_status, workspace, st);
+      const hipError_t ec = hipStreamEndCapture(st, &g);
+      if (ec != hipSuccess || !g) return fail_with(MF_E_DEVICE, std::string("capture: ") + hipGetErrorString(ec));
+      const hipError_t ei = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        p->graph_exec = nullptr;
+        return fail_with(MF_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+      }
+      p->graph_key = key;
     }
-    if (mom) {
-      sa.j = j;
-      LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
-      if (sa.lowrank && j >= 1)
-        hipLaunchKernelGGL(lowrank_kernel, dim3((unsigned)p->n_cols), dim3(kBlock), 0, st, sa);
-      else
-        dispatch_solve(p, sa, st);
-    }
+    const hipError_t e = hipGraphLaunch(p->graph_exec, st);
+    if (e != hipSuccess) return fail_with(MF_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+    return MF_OK;
   }
-  if (column_status) {
-    const unsigned nb = (unsigned)((p->n_cols + 255) / 256);
-    LaunchTimer tm(p, MF_KERNEL_OTHER, st);
-    hipLaunchKernelGGL(status_kernel, dim3(nb), dim3(256), 0, st, state, column_status, p->n_cols);
-  }
+  enqueue_retrieve(p, radiance, valid, s, alpha, column_status, workspace, st);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail_with(MF_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+  return MF_OK;
+}
+
+mf_status mf_plan_set_graph(mf_plan p, int enable) {
+  if (!p) return fail_with(MF_E_ARG, "plan is NULL");
+  p->use_graph = enable != 0;
   return MF_OK;
 }
 
@@ -1749,6 +1802,7 @@ void mf_plan_destroy(mf_plan p) {
     (void)hipEventDestroy(l.stop);
   }
   for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   if (p->cols_d) (void)hipFree(p->cols_d);
   if (p->items_d) (void)hipFree(p->items_d);
   delete p;

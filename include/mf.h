@@ -96,7 +96,9 @@ typedef struct {
   double   epsilon;       /* > 0, ppm*m (Eq. 5) */
   int32_t  cov;           /* mf_cov */
   int32_t  refine_steps;  /* iterative-refinement steps of C^-1 t (0..4; 1 = default) */
-  int32_t  save_for_backward; /* reserved, must be 0 in ABI version 1 */
+  int32_t  save_for_backward; /* 1: mf_retrieve keeps alpha^0..alpha^K and the
+                             per-iteration column state for mf_backward (needs
+                             MF_COV_LOWRANK and n_iter <= 30; larger workspace) */
   int32_t  chunk_lines;   /* pixels per work item along a column (multiple of
                              128; 0 = library default) */
 } mf_options;
@@ -151,6 +153,20 @@ MF_API int64_t mf_plan_pixels(mf_plan plan);
 MF_API mf_status mf_retrieve(mf_plan plan, const float* radiance, const uint8_t* valid,
                       const float* s, float* alpha, int32_t* column_status,
                       void* workspace, void* stream);
+
+/* Adjoint of mf_retrieve (reverse mode through the K unrolled iterations of
+   Fig. 1): given grad_alpha = dJ/dalpha^K for a scalar loss J (e.g.
+   J = sum (alpha^K - alpha_true)^2 gives 2 (alpha^K - alpha_true)), writes
+     grad_radiance [max_px][B] float32 = dJ/dL  (0 on invalid pixels and on
+                   columns whose status is not MF_COL_OK; only plan pixels written)
+     grad_s        [B] float64 = dJ/ds summed over every column
+   The plan needs save_for_backward = 1, and the preceding mf_retrieve on the
+   same workspace (and the same radiance, valid and s) must be ordered before
+   it on the stream.  The derivative of max(z, 0) is 1 for z > 0, else 0.
+   Device pointers; enqueued on the stream. */
+MF_API mf_status mf_backward(mf_plan plan, const float* radiance, const uint8_t* valid,
+                             const float* s, const float* grad_alpha, float* grad_radiance,
+                             double* grad_s, void* workspace, void* stream);
 
 /* Graph replay.  While enabled, mf_retrieve captures its launch sequence on
    the caller's stream into a HIP graph the first time it sees a set of

@@ -21,7 +21,7 @@ COV = {"lowrank": 0, "fp64": 1, "fp32": 2, "bf16": 3}
 # Every symbol declared in include/mf.h.
 EXPORTS = ("mf_abi_version", "mf_options_default", "mf_status_str", "mf_last_error",
            "mf_plan_create", "mf_workspace_bytes", "mf_plan_columns", "mf_plan_pixels",
-           "mf_retrieve", "mf_plan_set_graph", "mf_plan_set_timing", "mf_plan_kernel_times", "mf_stream_read",
+           "mf_retrieve", "mf_backward", "mf_plan_set_graph", "mf_plan_set_timing", "mf_plan_kernel_times", "mf_stream_read",
            "mf_plan_destroy")
 KERNEL_KINDS = ("pass_gram", "pass_vec", "pass_last", "solve", "other")
 
@@ -74,6 +74,8 @@ def load_library(path: str = LIB_PATH):
     lib.mf_retrieve.restype = ctypes.c_int
     lib.mf_retrieve.argtypes = [vp] * 8
     lib.mf_plan_destroy.argtypes = [vp]
+    lib.mf_backward.restype = ctypes.c_int
+    lib.mf_backward.argtypes = [vp] * 9
     lib.mf_plan_set_graph.restype = ctypes.c_int
     lib.mf_plan_set_graph.argtypes = [vp, ctypes.c_int]
     lib.mf_plan_set_timing.restype = ctypes.c_int
@@ -110,12 +112,14 @@ class Plan:
 
     def __init__(self, flightlines: Iterable[Tuple[int, int, int]], n_bands: int = 74,
                  n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9, albedo: bool = True,
-                 cov: str = "lowrank", refine_steps: int = 1, chunk_lines: int = 0):
+                 cov: str = "lowrank", refine_steps: int = 1, chunk_lines: int = 0,
+                 save_for_backward: bool = False):
         lib = load_library()
         o = default_options()
         o.n_bands, o.n_iter, o.albedo = n_bands, n_iter, int(bool(albedo))
         o.lambda_, o.epsilon, o.cov = float(lam), float(eps), COV[cov]
         o.refine_steps, o.chunk_lines = refine_steps, chunk_lines
+        o.save_for_backward = int(bool(save_for_backward))
         fls = list(flightlines)
         arr = (Flightline * max(1, len(fls)))(*[Flightline(int(a), int(b), int(c)) for a, b, c in fls])
         h = ctypes.c_void_p()
@@ -247,6 +251,77 @@ def stream_read_ms(x, n_blocks: int = 4096) -> float:
                                          n_blocks, ctypes.byref(ms),
                                          torch.cuda.current_stream(x.device).cuda_stream))
     return ms.value
+
+
+def _plan_backward(plan, radiance, s, grad_alpha, valid=None, workspace=None, stream=None):
+    """Enqueue mf_backward; returns (grad_radiance float32 like radiance, grad_s float64 [B])."""
+    import torch
+    _need(radiance, torch.float32, "radiance")
+    _need(s, torch.float32, "s")
+    _need(grad_alpha, torch.float32, "grad_alpha")
+    if workspace is None:
+        raise ValueError("backward needs the forward's workspace")
+    if valid is not None:
+        _need(valid, torch.uint8, "valid")
+    grad_L = torch.zeros_like(radiance)
+    grad_s = torch.empty(plan.n_bands, dtype=torch.float64, device=radiance.device)
+    ws = workspace.data_ptr()
+    ws_al = (ws + 255) & ~255
+    if stream is None:
+        stream = torch.cuda.current_stream(radiance.device)
+    _check(plan._lib.mf_backward(plan._h, radiance.data_ptr(),
+                                 None if valid is None else valid.data_ptr(), s.data_ptr(),
+                                 grad_alpha.data_ptr(), grad_L.data_ptr(), grad_s.data_ptr(),
+                                 ws_al, stream.cuda_stream))
+    return grad_L, grad_s
+
+
+Plan.backward = _plan_backward
+
+
+def _make_autograd():
+    import torch
+
+    class RetrieveFunction(torch.autograd.Function):
+        """alpha^K of a [S, N, B] radiance cube, differentiable in radiance and s
+        through the library's hand-written adjoint (mf_backward)."""
+
+        @staticmethod
+        def forward(ctx, radiance, s, n_iter, lam, eps, albedo, valid, refine_steps, chunk_lines):
+            S, N, B = radiance.shape
+            plan = Plan([(0, S, N)], B, n_iter, lam, eps, albedo, "lowrank", refine_steps,
+                        chunk_lines, save_for_backward=True)
+            ws = plan.alloc_workspace(radiance.device)
+            L = radiance.detach().contiguous()
+            sv = s.detach().contiguous()
+            vv = None if valid is None else valid.contiguous()
+            alpha = torch.empty((S, N), dtype=torch.float32, device=radiance.device)
+            plan.retrieve(L, sv, alpha, vv, None, ws)
+            ctx.state = (plan, ws, L, sv, vv)
+            return alpha
+
+        @staticmethod
+        def backward(ctx, grad_alpha):
+            plan, ws, L, sv, vv = ctx.state
+            gL, gs = plan.backward(L, sv, grad_alpha.contiguous().float(), vv, ws)
+            ctx.state = None
+            return gL, gs.to(sv.dtype), None, None, None, None, None, None, None
+
+    return RetrieveFunction
+
+
+_RetrieveFunction = None
+
+
+def retrieve_differentiable(radiance, s, n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9,
+                            albedo: bool = True, valid=None, refine_steps: int = 1,
+                            chunk_lines: int = 0):
+    """alpha [S, N] with autograd support (radiance and s), low-rank form."""
+    global _RetrieveFunction
+    if _RetrieveFunction is None:
+        _RetrieveFunction = _make_autograd()
+    return _RetrieveFunction.apply(radiance, s, n_iter, lam, eps, albedo, valid, refine_steps,
+                                   chunk_lines)
 
 
 def _need(t, dtype, name):

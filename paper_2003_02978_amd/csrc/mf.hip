@@ -118,6 +118,8 @@ struct SolveArgs {
   int refine;
   int lowrank;
   int partial_stride;        // doubles per work item in the partial buffer
+  double* ck;                // save_for_backward: column checkpoints [K+1][n_cols][kCk]
+  int n_cols;
 };
 
 __host__ __device__ constexpr int n_tiles(int nb) { return nb * (nb + 1) / 2; }
@@ -821,6 +823,10 @@ __device__ void block_symv(const double (&M)[kBlk][kBlk], bool owner, int bi, in
   __syncthreads();
 }
 
+// Column checkpoint of iteration k (save_for_backward): mu, t, v, m, a, S2, q, N.
+constexpr int kCkMu = 0, kCkT = kPad, kCkV = 2 * kPad, kCkM = 3 * kPad, kCkScal = 4 * kPad;
+constexpr int kCk = 4 * kPad + 8;
+
 template <int NB, bool WIDE>
 __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   const int col = blockIdx.x;
@@ -1139,97 +1145,67 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
       st.m0[b] = in ? mun[b] / sc[3] : 0.0;
     }
   }
+  if (a.ck && j == 0) {                          // checkpoint of iteration 0
+    double* ck = a.ck + (int64_t)col * kCk;
+    for (int b = tid; b < kPad; b += kBlock) {
+      const bool in = b < B;
+      ck[kCkMu + b] = in ? mun[b] : 0.0;
+      ck[kCkT + b] = in ? tn[b] : 0.0;
+      ck[kCkV + b] = in ? vbuf[b] : 0.0;
+      ck[kCkM + b] = 0.0;
+    }
+    if (tid == 0) {
+      ck[kCkScal + 0] = 0.0;
+      ck[kCkScal + 1] = 0.0;
+      ck[kCkScal + 2] = st.q;
+      ck[kCkScal + 3] = N;
+    }
+  }
 }
 
-// Low-rank form, iterations j >= 1: C^j = C^0 + U S U^T with U = [D, t, m],
-//   D = t^{j-1} - t^j, S = [[a^2, 0, 0], [0, S2/N - a^2, -1/N], [0, -1/N, 0]],
-// (the rank-3 identity), solved with the stored P = (C^0)^-1 by Woodbury:
-//   C^-1 b = P b - X (I + S W)^-1 S U^T P b,  X = P U,  W = U^T X,
-// followed by refinement steps against C^j applied exactly.  Everything is
-// matrix-vector products on the register blocks: no sequential factorisation.
-__global__ void __launch_bounds__(kBlock) lowrank_kernel(SolveArgs a) {
-  const int col = blockIdx.x;
-  const int tid = threadIdx.x;
+// ---------------------------------------------------------------------------
+// Rank-3 solves.  C = C^0 + U S U^T (U = three LDS vectors, S a 3x3 matrix)
+// with P = (C^0)^-1 and C^0 held in the 4x4 register blocks.  Woodbury:
+//   C^-1 b = P b - X (I + S W)^-1 S U^T P b,   X = P U,  W = U^T X,
+// then refinement steps against C applied exactly.  Everything is
+// matrix-vector products on the register blocks (no factorisation).
+
+struct R3Smem {
+  double U3[3 * kPad];
+  double X3[3 * kPad];
+  double vbuf[kPad], rbuf[kPad], wbuf[kPad];
+  double prow[3 * kNBlk * kBlk], pcol[3 * kNBlk * kBlk];
+  double S3[9], Ginv[9], zbuf[8];
+  int bad;
+};
+
+// X = P U and Ginv = (I + S U^T X)^-1 (partial pivoting); sm.bad on failure.
+__device__ void r3_prepare(const double (&Pb)[kBlk][kBlk], bool owner, int bi, int bj, int tid,
+                           int B, R3Smem& sm) {
   const int lane = tid & 63, wid = tid >> 6;
-  ColState& st = a.state[col];
-  if (st.status != MF_COL_OK) return;
-  const ColInfo ci = a.cols[col];
-  const int B = a.B;
-  const int64_t stride = (int64_t)a.partial_stride;
-  const double* P = a.partials + (int64_t)ci.first_item * stride;
-  const double* c0 = a.c0 + (int64_t)col * (kNBlk * 16);
-  const double* pinv = a.pinv + (int64_t)col * (kNBlk * 16);
-
-  __shared__ double U3[3 * kPad];   // D, t, m
-  __shared__ double X3[3 * kPad];   // P D, P t, P m
-  __shared__ double mun[kPad], vbuf[kPad], rbuf[kPad], wbuf[kPad], zbuf[kPad];
-  __shared__ double prow[3 * kNBlk * kBlk], pcol[3 * kNBlk * kBlk];
-  __shared__ double sc[4];
-  __shared__ double G3[9], S3[9], Ginv[9];
-  __shared__ int bad;
-
-  int bi = 0, bj = 0;
-  const bool owner = tid < kNBlk;
-  if (owner) block_coords(tid, bi, bj);
-  double Cb[kBlk][kBlk], Pb[kBlk][kBlk];
-#pragma unroll
-  for (int x = 0; x < kBlk; ++x)
-#pragma unroll
-    for (int y = 0; y < kBlk; ++y) {
-      Cb[x][y] = owner ? c0[tid * 16 + x * kBlk + y] : 0.0;
-      Pb[x][y] = owner ? pinv[tid * 16 + x * kBlk + y] : 0.0;
-    }
-  if (tid == 0) {
-    double s1 = 0.0, s2 = 0.0;
-    for (int it = 0; it < ci.n_items; ++it) {
-      s1 += P[it * stride + kVecS1];
-      s2 += P[it * stride + kVecS2];
-    }
-    sc[0] = st.n_valid;
-    sc[1] = s1;
-    sc[2] = s2;
-    bad = 0;
-  }
-  __syncthreads();
-  const double N = sc[0], S1 = sc[1], S2 = sc[2];
-  const double abar = S1 / N;
-  for (int b = tid; b < kPad; b += kBlock) {
-    double m = 0.0, mu = 0.0, t = 0.0, d = 0.0;
-    if (b < B) {
-      for (int it = 0; it < ci.n_items; ++it) m += P[it * stride + b];
-      mu = st.lbar[b] - abar * st.t[b];          // Eq. 10
-      t = mu * (double)a.s[b];                   // Eq. 9
-      d = st.t[b] - t;
-    }
-    mun[b] = mu;
-    U3[b] = d;
-    U3[kPad + b] = t;
-    U3[2 * kPad + b] = m;
-  }
-  __syncthreads();
-  block_symv<3>(Pb, owner, bi, bj, tid, B, U3, X3, prow, pcol);    // X = P U
+  if (tid == 0) sm.bad = 0;
+  block_symv<3>(Pb, owner, bi, bj, tid, B, sm.U3, sm.X3, sm.prow, sm.pcol);
   if (wid == 0) {
-    // W = U^T X, S, and (I + S W)^-1 by Gauss-Jordan with partial pivoting
     double W[9];
     for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) W[r * 3 + c] = wave_dot(U3 + r * kPad, X3 + c * kPad, B, lane);
+      for (int c = 0; c < 3; ++c) W[r * 3 + c] = wave_dot(sm.U3 + r * kPad, sm.X3 + c * kPad, B, lane);
     if (lane == 0) {
-      const double S[9] = {abar * abar, 0.0, 0.0, 0.0, S2 / N - abar * abar, -1.0 / N,
-                           0.0, -1.0 / N, 0.0};
       double M[9], I3[9];
       for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) {
           double s = (r == c) ? 1.0 : 0.0;
-          for (int k = 0; k < 3; ++k) s += S[r * 3 + k] * W[k * 3 + c];
+          for (int k = 0; k < 3; ++k) s += sm.S3[r * 3 + k] * W[k * 3 + c];
           M[r * 3 + c] = s;
           I3[r * 3 + c] = (r == c) ? 1.0 : 0.0;
-          S3[r * 3 + c] = S[r * 3 + c];
         }
       for (int k = 0; k < 3; ++k) {
         int piv = k;
         for (int r = k + 1; r < 3; ++r)
           if (fabs(M[r * 3 + k]) > fabs(M[piv * 3 + k])) piv = r;
-        if (!(fabs(M[piv * 3 + k]) > 0.0)) bad = 1;
+        if (!(fabs(M[piv * 3 + k]) > 0.0)) {
+          sm.bad = 1;
+          break;
+        }
         for (int c = 0; c < 3; ++c) {
           double t0 = M[k * 3 + c]; M[k * 3 + c] = M[piv * 3 + c]; M[piv * 3 + c] = t0;
           t0 = I3[k * 3 + c]; I3[k * 3 + c] = I3[piv * 3 + c]; I3[piv * 3 + c] = t0;
@@ -1248,61 +1224,138 @@ __global__ void __launch_bounds__(kBlock) lowrank_kernel(SolveArgs a) {
           }
         }
       }
-      for (int e = 0; e < 9; ++e) Ginv[e] = I3[e];
-      (void)G3;
+      for (int e = 0; e < 9; ++e) sm.Ginv[e] = I3[e];
     }
   }
   __syncthreads();
-  if (bad) {
-    if (tid == 0) st.status = MF_COL_NOT_SPD;
-    return;
-  }
-  // v = Woodbury(t): P t is X3[1]
-  // correction coefficients z = (I + S W)^-1 S U^T y  with y = P b
-  // (computed by wave 0, applied by all threads)
-  for (int step = 0; step <= a.refine; ++step) {
-    const double* y = step == 0 ? (X3 + kPad) : wbuf;     // P b
+}
+
+// sm.vbuf = C^-1 b (b: LDS vector, zero beyond B), with `refine` refinement steps.
+__device__ void r3_solve(const double (&Pb)[kBlk][kBlk], const double (&Cb)[kBlk][kBlk], bool owner,
+                         int bi, int bj, int tid, int B, int refine, const double* b, R3Smem& sm) {
+  const int lane = tid & 63, wid = tid >> 6;
+  block_symv<1>(Pb, owner, bi, bj, tid, B, b, sm.wbuf, sm.prow, sm.pcol);   // y = P b
+  for (int step = 0; step <= refine; ++step) {
     if (wid == 0) {
       double u[3];
-      for (int r = 0; r < 3; ++r) u[r] = wave_dot(U3 + r * kPad, y, B, lane);
+      for (int r = 0; r < 3; ++r) u[r] = wave_dot(sm.U3 + r * kPad, sm.wbuf, B, lane);
       if (lane == 0) {
-        double su[3], z[3];
-        for (int r = 0; r < 3; ++r) su[r] = S3[r * 3] * u[0] + S3[r * 3 + 1] * u[1] + S3[r * 3 + 2] * u[2];
-        for (int r = 0; r < 3; ++r) z[r] = Ginv[r * 3] * su[0] + Ginv[r * 3 + 1] * su[1] + Ginv[r * 3 + 2] * su[2];
-        sc[3] = 0.0;
-        zbuf[0] = z[0];
-        zbuf[1] = z[1];
-        zbuf[2] = z[2];
+        double su[3];
+        for (int r = 0; r < 3; ++r)
+          su[r] = sm.S3[r * 3] * u[0] + sm.S3[r * 3 + 1] * u[1] + sm.S3[r * 3 + 2] * u[2];
+        for (int r = 0; r < 3; ++r)
+          sm.zbuf[r] = sm.Ginv[r * 3] * su[0] + sm.Ginv[r * 3 + 1] * su[1] + sm.Ginv[r * 3 + 2] * su[2];
       }
     }
     __syncthreads();
-    for (int b = tid; b < kPad; b += kBlock) {
-      const double corr = b < B ? y[b] - (X3[b] * zbuf[0] + X3[kPad + b] * zbuf[1] +
-                                          X3[2 * kPad + b] * zbuf[2]) : 0.0;
-      if (step == 0) vbuf[b] = corr;
-      else if (b < B) vbuf[b] += corr;
+    for (int e = tid; e < kPad; e += kBlock) {
+      const double corr = e < B ? sm.wbuf[e] - (sm.X3[e] * sm.zbuf[0] + sm.X3[kPad + e] * sm.zbuf[1] +
+                                                sm.X3[2 * kPad + e] * sm.zbuf[2]) : 0.0;
+      if (step == 0) sm.vbuf[e] = corr;
+      else if (e < B) sm.vbuf[e] += corr;
     }
     __syncthreads();
-    if (step == a.refine) break;
-    // residual r = t - C^j v with C^j v = C^0 v + U S U^T v
-    block_symv<1>(Cb, owner, bi, bj, tid, B, vbuf, rbuf, prow, pcol);
+    if (step == refine) break;
+    // residual r = b - C v, C v = C^0 v + U S U^T v
+    block_symv<1>(Cb, owner, bi, bj, tid, B, sm.vbuf, sm.rbuf, sm.prow, sm.pcol);
     if (wid == 0) {
       double u[3];
-      for (int r = 0; r < 3; ++r) u[r] = wave_dot(U3 + r * kPad, vbuf, B, lane);
+      for (int r = 0; r < 3; ++r) u[r] = wave_dot(sm.U3 + r * kPad, sm.vbuf, B, lane);
       if (lane == 0)
         for (int r = 0; r < 3; ++r)
-          zbuf[4 + r] = S3[r * 3] * u[0] + S3[r * 3 + 1] * u[1] + S3[r * 3 + 2] * u[2];
+          sm.zbuf[4 + r] = sm.S3[r * 3] * u[0] + sm.S3[r * 3 + 1] * u[1] + sm.S3[r * 3 + 2] * u[2];
     }
     __syncthreads();
-    for (int b = tid; b < kPad; b += kBlock)
-      rbuf[b] = b < B ? U3[kPad + b] - rbuf[b] -
-                            (U3[b] * zbuf[4] + U3[kPad + b] * zbuf[5] + U3[2 * kPad + b] * zbuf[6])
-                      : 0.0;
+    for (int e = tid; e < kPad; e += kBlock)
+      sm.rbuf[e] = e < B ? b[e] - sm.rbuf[e] -
+                               (sm.U3[e] * sm.zbuf[4] + sm.U3[kPad + e] * sm.zbuf[5] +
+                                sm.U3[2 * kPad + e] * sm.zbuf[6])
+                         : 0.0;
     __syncthreads();
-    block_symv<1>(Pb, owner, bi, bj, tid, B, rbuf, wbuf, prow, pcol);  // P r
+    block_symv<1>(Pb, owner, bi, bj, tid, B, sm.rbuf, sm.wbuf, sm.prow, sm.pcol);   // P r
   }
+}
+
+// Loads the register blocks of C^0 and P of one column.
+__device__ void load_blocks(const double* c0, const double* pinv, bool owner, int tid,
+                            double (&Cb)[kBlk][kBlk], double (&Pb)[kBlk][kBlk]) {
+#pragma unroll
+  for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+    for (int y = 0; y < kBlk; ++y) {
+      Cb[x][y] = owner ? c0[tid * 16 + x * kBlk + y] : 0.0;
+      Pb[x][y] = owner ? pinv[tid * 16 + x * kBlk + y] : 0.0;
+    }
+}
+
+// S of the rank-3 identity:  N C^j = N C^0 + N a^2 D D^T + (S2 - N a^2) t t^T - (m t^T + t m^T)
+// for U = [D, t, m].
+__device__ void rank3_S(double* S3, double abar, double S2, double N) {
+  S3[0] = abar * abar; S3[1] = 0.0;                     S3[2] = 0.0;
+  S3[3] = 0.0;         S3[4] = S2 / N - abar * abar;    S3[5] = -1.0 / N;
+  S3[6] = 0.0;         S3[7] = -1.0 / N;                S3[8] = 0.0;
+}
+
+
+// Low-rank form, iterations j >= 1: mu^j (Eq. 10), t^j (Eq. 9), C^j by the
+// rank-3 identity, v^j = C^j^-1 t^j by the rank-3 solve, q^j.
+__global__ void __launch_bounds__(kBlock) lowrank_kernel(SolveArgs a) {
+  const int col = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  ColState& st = a.state[col];
+  if (st.status != MF_COL_OK) return;
+  const ColInfo ci = a.cols[col];
+  const int B = a.B;
+  const int64_t stride = (int64_t)a.partial_stride;
+  const double* P = a.partials + (int64_t)ci.first_item * stride;
+
+  __shared__ R3Smem sm;
+  __shared__ double mun[kPad];
+  __shared__ double sc[4];
+
+  int bi = 0, bj = 0;
+  const bool owner = tid < kNBlk;
+  if (owner) block_coords(tid, bi, bj);
+  double Cb[kBlk][kBlk], Pb[kBlk][kBlk];
+  load_blocks(a.c0 + (int64_t)col * (kNBlk * 16), a.pinv + (int64_t)col * (kNBlk * 16), owner, tid,
+              Cb, Pb);
+  if (tid == 0) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int it = 0; it < ci.n_items; ++it) {
+      s1 += P[it * stride + kVecS1];
+      s2 += P[it * stride + kVecS2];
+    }
+    sc[0] = st.n_valid;
+    sc[1] = s1;
+    sc[2] = s2;
+    rank3_S(sm.S3, s1 / st.n_valid, s2, st.n_valid);
+  }
+  __syncthreads();
+  const double N = sc[0], S1 = sc[1], S2 = sc[2];
+  const double abar = S1 / N;
+  for (int b = tid; b < kPad; b += kBlock) {
+    double m = 0.0, mu = 0.0, t = 0.0, d = 0.0;
+    if (b < B) {
+      for (int it = 0; it < ci.n_items; ++it) m += P[it * stride + b];
+      mu = st.lbar[b] - abar * st.t[b];          // Eq. 10
+      t = mu * (double)a.s[b];                   // Eq. 9
+      d = st.t[b] - t;
+    }
+    mun[b] = mu;
+    sm.U3[b] = d;
+    sm.U3[kPad + b] = t;
+    sm.U3[2 * kPad + b] = m;
+  }
+  __syncthreads();
+  r3_prepare(Pb, owner, bi, bj, tid, B, sm);
+  if (sm.bad) {
+    if (tid == 0) st.status = MF_COL_NOT_SPD;
+    return;
+  }
+  r3_solve(Pb, Cb, owner, bi, bj, tid, B, a.refine, sm.U3 + kPad, sm);
   if (wid == 0) {
-    const double q = wave_dot(U3 + kPad, vbuf, B, lane);
+    const double q = wave_dot(sm.U3 + kPad, sm.vbuf, B, lane);
     if (lane == 0) {
       st.q = q;
       if (!(q > 0.0) || !isfinite(q)) st.status = MF_COL_NOT_SPD;
@@ -1310,9 +1363,529 @@ __global__ void __launch_bounds__(kBlock) lowrank_kernel(SolveArgs a) {
   }
   for (int b = tid; b < kPad; b += kBlock) {
     st.mu[b] = mun[b];
-    st.t[b] = U3[kPad + b];
-    st.v[b] = vbuf[b];
+    st.t[b] = sm.U3[kPad + b];
+    st.v[b] = sm.vbuf[b];
   }
+  if (a.ck) {                                    // checkpoint of iteration j
+    double* ck = a.ck + ((int64_t)a.j * a.n_cols + col) * kCk;
+    for (int b = tid; b < kPad; b += kBlock) {
+      ck[kCkMu + b] = mun[b];
+      ck[kCkT + b] = sm.U3[kPad + b];
+      ck[kCkV + b] = sm.vbuf[b];
+      ck[kCkM + b] = sm.U3[2 * kPad + b];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      ck[kCkScal + 0] = abar;
+      ck[kCkScal + 1] = S2;
+      ck[kCkScal + 2] = st.q;
+      ck[kCkScal + 3] = N;
+    }
+  }
+}
+
+// ===========================================================================
+// Adjoint: reverse mode through the K unrolled iterations (J = sum alpha^K
+// weighted by the caller's grad_alpha).  Per iteration k = K..0, with
+// abar_i the adjoint of alpha_i^k and zeta_i = abar_i [z_i > 0]:
+//  pass A  pbar = zeta / (r q);  rbar += -zeta z / r;
+//          adjoint of alpha^{k-1} through w (Eq. 5): zeta lam / (r q (a^{k-1} + eps)^2);
+//          sums  Q1 = sum zeta z,  P1 = sum pbar,  V = sum pbar (L - mu^k)
+//  col A   qbar = -Q1 / q,  vbar = V + qbar t,  u = C^-1 vbar (rank-3 solve),
+//          tbar = tbar_in + qbar v + u,  mubar = -P1 v
+//  pass B  with d_i = L_i - c_i t - mu (Eq. 11), c_i = r_i a_i^{k-1}:
+//          alpha_i = v.d_i = p - c q,  beta_i = u.d_i,  dbar_i = -(alpha_i u + beta_i v) / N;
+//          radiance-gradient coefficients  cv = pbar - beta / N (of v^k), cu = -alpha / N (of u^k);
+//          cbar = -t.dbar = (alpha t.u + beta q) / N:  abar += r cbar,  rbar += a^{k-1} cbar;
+//          sums  A0 = sum alpha, B0 = sum beta, A1 = sum c alpha, B1 = sum c beta
+//  col B   mubar += (u A0 + v B0) / N,  tbar += (u A1 + v B1) / N,
+//          mubar += tbar (.) s,  sbar += tbar (.) mu   (t = mu (.) s, Eq. 9);
+//          k >= 1 (mu^k = mean L - a_k t^{k-1}, Eq. 10): Mbar += mubar,
+//            gamma = -(mubar . t^{k-1}) / N is the uniform part of cbar, applied by the
+//            next pass A as abar += r gamma, rbar += a^{k-1} gamma;  tbar_in = -a_k mubar
+//          k = 0: Mbar += mubar + (sum rbar L) / |mu0|^2 - 2 (sum rbar r) mu0 / |mu0|^2  (Eq. 7)
+// Finally G_i = sum_k (cv_i^k v^k + cu_i^k u^k) + rbar_i mu0 / |mu0|^2 + Mbar / N.
+
+constexpr int kBwTbarIn = 0, kBwTbar = kPad, kBwMubar = 2 * kPad, kBwMbar = 3 * kPad,
+              kBwSbar = 4 * kPad, kBwScal = 5 * kPad;          // scal: gamma, t.u, mu.u
+constexpr int kBw = 5 * kPad + 8;
+constexpr int kBwQ1 = 80, kBwP1 = 81;                          // pass A partial scalars
+constexpr int kBwA0 = 80, kBwB0 = 81, kBwA1 = 82, kBwB1 = 83, kBwRR = 84;   // pass B
+
+struct BwArgs {
+  const float* L;
+  const uint8_t* valid;
+  const WorkItem* items;
+  const ColState* state;
+  const double* ck_k;        // checkpoints of iteration k, [n_cols][kCk]
+  const double* a_k;         // alpha^k (FP64 checkpoint)
+  const double* a_km1;       // alpha^{k-1}, or null for k = 0
+  const float* grad_alpha;   // adjoint of alpha^K (k = K)
+  double* abar;
+  double* rbar;
+  double* pbar;
+  double* coef_v;            // coefficient of v^k in G, per pixel
+  double* coef_u;            // coefficient of u^k in G, per pixel
+  const double* bwcol;       // per-column backward state [n_cols][kBw]
+  const double* u_k;         // u^k [n_cols][kPad]
+  double* partials;
+  int partial_stride;
+  int B, k, K;
+  double lam, eps;
+  int albedo;
+};
+
+// Synchronous copy of one chunk (contiguous in memory) into a wave's LDS tile.
+__device__ __forceinline__ void copy_chunk(const float* g, int nfl, float* my, int lane) {
+  const uintptr_t ga = reinterpret_cast<uintptr_t>(g);
+  if ((ga & 15) == 0 && (nfl & 3) == 0) {
+    const float4* g4 = reinterpret_cast<const float4*>(g);
+    float4* t4 = reinterpret_cast<float4*>(my);
+    const int n4 = nfl / 4;
+    for (int base = 0; base < n4; base += 64 * kCopyGroup) {
+      float4 r[kCopyGroup];
+#pragma unroll
+      for (int q = 0; q < kCopyGroup; ++q) {
+        const int e = base + lane + 64 * q;
+        r[q] = e < n4 ? g4[e] : float4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int q = 0; q < kCopyGroup; ++q) {
+        const int e = base + lane + 64 * q;
+        if (e < n4) t4[e] = r[q];
+      }
+    }
+  } else if ((ga & 7) == 0 && (nfl & 1) == 0) {
+    const float2* g2 = reinterpret_cast<const float2*>(g);
+    float2* t2 = reinterpret_cast<float2*>(my);
+    const int n2 = nfl / 2;
+    for (int e = lane; e < n2; e += 64) t2[e] = g2[e];
+  } else {
+    for (int e = lane; e < nfl; e += 64) my[e] = g[e];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Dynamic LDS of bwd_kernel: tiles, per-pixel weights, partial rows, constants.
+__host__ __device__ constexpr size_t bwd_lds_bytes(int B) {
+  return (size_t)kSW * kChunk * B * sizeof(float) + kSW * kChunk * sizeof(double) +
+         kSW * (kPad + 8) * sizeof(double) + 4 * kPad * sizeof(double);
+}
+
+template <int PASS>   // 0: pass A, 1: pass B
+__global__ void __launch_bounds__(kSBlock) bwd_kernel(BwArgs a) {
+  const WorkItem it = a.items[blockIdx.x];
+  const ColState* __restrict__ st = a.state + it.col;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int B = a.B, k = a.k;
+  const int64_t begin = it.px_begin, end = begin + it.n_px;
+  extern __shared__ double dyn[];
+  double* cbuf = dyn;                                   // [kSW][kChunk]
+  double* redm = cbuf + kSW * kChunk;                   // [kSW][kPad + 8]
+  double* cst = redm + kSW * (kPad + 8);                // [kPad][4]: mu, v, m0, u
+  float* my = reinterpret_cast<float*>(cst + 4 * kPad) + wid * kChunk * B;
+
+  if (st->status != MF_COL_OK) return;       // failed column: gradient 0 (assembly)
+  const double* ck = a.ck_k + (int64_t)it.col * kCk;
+  const double* bw = a.bwcol + (int64_t)it.col * kBw;
+  for (int b = tid; b < kPad; b += kSBlock) {
+    cst[4 * b + 0] = ck[kCkMu + b];
+    cst[4 * b + 1] = ck[kCkV + b];
+    cst[4 * b + 2] = st->m0[b];
+    cst[4 * b + 3] = PASS == 1 ? a.u_k[(int64_t)it.col * kPad + b] : 0.0;
+  }
+  __syncthreads();
+  const double q = ck[kCkScal + 2], N = ck[kCkScal + 3];
+  const double gamma = bw[kBwScal + 0], tu = bw[kBwScal + 1], muu = bw[kBwScal + 2];
+  const double lam = a.lam, eps = a.eps;
+  // weighted band sums: PASS A  V = sum pbar (L - mu);  PASS B (k = 0)  sum rbar L
+  const bool vec = PASS == 0 || k == 0;
+  double m_lo = 0.0, m_hi = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+
+  for (int64_t c0 = begin + (int64_t)kChunk * wid; c0 < end; c0 += kSW * kChunk) {
+    const int n = (int)min<int64_t>(kChunk, end - c0);
+    copy_chunk(a.L + c0 * B, n * B, my, lane);
+    const int64_t px = c0 + lane;
+    const bool inb = lane < n;
+    bool ok = inb;
+    if (inb && a.valid) ok = a.valid[px] != 0;
+    double pp = 0.0, rr = 0.0, lu = 0.0;
+    if (ok) {
+      const float* rowp = my + lane * B;
+      for (int b = 0; b < B; ++b) {
+        const double l = (double)rowp[b];
+        pp = fma(l - cst[4 * b], cst[4 * b + 1], pp);
+        rr = fma(l, cst[4 * b + 2], rr);
+        if (PASS == 1) lu = fma(l, cst[4 * b + 3], lu);
+      }
+    }
+    const double r = a.albedo ? rr : 1.0;
+    const bool live = ok && (r > 0.0);          // dark pixels keep alpha = 0
+    double wgt = 0.0;
+    if (PASS == 0) {
+      double ab = 0.0, rb = 0.0;
+      if (inb) {
+        if (k == a.K) {
+          ab = (double)a.grad_alpha[px];
+        } else {
+          ab = a.abar[px] + r * gamma;
+          rb = a.rbar[px] + a.a_k[px] * gamma;
+        }
+      }
+      const double am1 = (k >= 1 && inb) ? a.a_km1[px] : 0.0;
+      const double w = k >= 1 ? lam / (am1 + eps) : 0.0;
+      const double z = (pp - w) / (r * q);
+      const bool pos = (a.K == 0) || (z > 0.0);   // K = 0 returns alpha^0 unclamped
+      const double zeta = (live && pos) ? ab : 0.0;
+      const double pb = zeta != 0.0 ? zeta / (r * q) : 0.0;
+      if (zeta != 0.0) rb -= zeta * z / r;
+      const double abm1 = (k >= 1 && zeta != 0.0) ? zeta * lam / (r * q * (am1 + eps) * (am1 + eps)) : 0.0;
+      if (inb) {
+        a.abar[px] = ok ? abm1 : 0.0;
+        a.pbar[px] = ok ? pb : 0.0;
+        a.rbar[px] = ok ? rb : 0.0;
+      }
+      s0 += zeta != 0.0 ? zeta * z : 0.0;
+      s1 += pb;
+      wgt = pb;
+    } else {
+      const double am1 = (k >= 1 && live) ? a.a_km1[px] : 0.0;
+      const double c = r * am1;
+      const double al = ok ? pp - c * q : 0.0;
+      const double be = ok ? lu - c * tu - muu : 0.0;
+      const double pb = inb ? a.pbar[px] : 0.0;
+      const double cbar = (al * tu + be * q) / N;
+      if (inb) {
+        a.coef_v[px] = ok ? pb - be / N : 0.0;
+        a.coef_u[px] = ok ? -al / N : 0.0;
+        if (k >= 1 && live) {
+          a.abar[px] += r * cbar;
+          a.rbar[px] += am1 * cbar;
+        }
+      }
+      s0 += al;
+      s1 += be;
+      s2 += c * al;
+      s3 += c * be;
+      if (k == 0) {
+        const double rb = ok ? a.rbar[px] : 0.0;
+        s4 += rb * r;
+        wgt = rb;
+      }
+    }
+    if (vec && __ballot(wgt != 0.0)) {             // wave-uniform; sparse weights
+      cbuf[wid * kChunk + lane] = wgt;
+      wave_sync_lds();
+      const int b0 = lane, b1 = lane + 64;
+      const double o0 = (PASS == 0 && b0 < B) ? cst[4 * b0] : 0.0;
+      const double o1 = (PASS == 0 && b1 < B) ? cst[4 * b1] : 0.0;
+      for (int p = 0; p < n; ++p) {
+        const double cp = cbuf[wid * kChunk + p];
+        if (cp != 0.0) {
+          if (b0 < B) m_lo = fma(cp, (double)my[p * B + b0] - o0, m_lo);
+          if (b1 < B) m_hi = fma(cp, (double)my[p * B + b1] - o1, m_hi);
+        }
+      }
+    }
+    wave_sync_lds();
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    s0 += __shfl_xor(s0, off, 64);
+    s1 += __shfl_xor(s1, off, 64);
+    s2 += __shfl_xor(s2, off, 64);
+    s3 += __shfl_xor(s3, off, 64);
+    s4 += __shfl_xor(s4, off, 64);
+  }
+  double* rw = redm + wid * (kPad + 8);
+  if (lane < kPad) rw[lane] = (vec && lane < B) ? m_lo : 0.0;
+  if (lane + 64 < kPad) rw[lane + 64] = (vec && lane + 64 < B) ? m_hi : 0.0;
+  if (lane == 0) {
+    rw[80] = s0;
+    rw[81] = s1;
+    rw[82] = s2;
+    rw[83] = s3;
+    rw[84] = s4;
+  }
+  __syncthreads();
+  double* out = a.partials + (int64_t)blockIdx.x * a.partial_stride;
+  for (int e = tid; e < kPad + 5; e += kSBlock) {
+    double sum = 0.0;
+    for (int w = 0; w < kSW; ++w) sum += redm[w * (kPad + 8) + e];
+    out[e] = sum;
+  }
+}
+
+struct BwColArgs {
+  const ColInfo* cols;
+  const ColState* state;
+  const double* ck_k;        // [n_cols][kCk] of iteration k
+  const double* ck_km1;      // of iteration k - 1 (k >= 1)
+  const double* c0;
+  const double* pinv;
+  const double* partials;
+  double* bwcol;
+  double* u_k;
+  const float* s;
+  int partial_stride;
+  int B, k, refine, albedo;
+};
+
+__global__ void bwd_init_kernel(double* bwcol, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) bwcol[e] = 0.0;
+}
+
+// col A: vbar, u = C^k^-1 vbar, tbar, mubar.
+__global__ void __launch_bounds__(kBlock) bwd_colA_kernel(BwColArgs a) {
+  const int col = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const ColState& st = a.state[col];
+  if (st.status != MF_COL_OK) return;
+  const ColInfo ci = a.cols[col];
+  const int B = a.B, k = a.k;
+  const int64_t stride = a.partial_stride;
+  const double* P = a.partials + (int64_t)ci.first_item * stride;
+  const double* ck = a.ck_k + (int64_t)col * kCk;
+  double* bw = a.bwcol + (int64_t)col * kBw;
+
+  __shared__ R3Smem sm;
+  __shared__ double vbar[kPad];
+  __shared__ double sc[2];
+  int bi = 0, bj = 0;
+  const bool owner = tid < kNBlk;
+  if (owner) block_coords(tid, bi, bj);
+  double Cb[kBlk][kBlk], Pb[kBlk][kBlk];
+  load_blocks(a.c0 + (int64_t)col * (kNBlk * 16), a.pinv + (int64_t)col * (kNBlk * 16), owner, tid,
+              Cb, Pb);
+  const double q = ck[kCkScal + 2], N = ck[kCkScal + 3];
+  if (tid == 0) {
+    double q1 = 0.0, p1 = 0.0;
+    for (int it = 0; it < ci.n_items; ++it) {
+      q1 += P[it * stride + kBwQ1];
+      p1 += P[it * stride + kBwP1];
+    }
+    sc[0] = q1;
+    sc[1] = p1;
+    if (k >= 1) rank3_S(sm.S3, ck[kCkScal + 0], ck[kCkScal + 1], N);
+    else
+      for (int e = 0; e < 9; ++e) sm.S3[e] = 0.0;
+  }
+  __syncthreads();
+  const double qbar = -sc[0] / q, P1 = sc[1];
+  const double* ckm1 = k >= 1 ? a.ck_km1 + (int64_t)col * kCk : nullptr;
+  for (int b = tid; b < kPad; b += kBlock) {
+    double V = 0.0;
+    if (b < B)
+      for (int it = 0; it < ci.n_items; ++it) V += P[it * stride + b];
+    const double t = ck[kCkT + b];
+    vbar[b] = b < B ? V + qbar * t : 0.0;
+    sm.U3[b] = (k >= 1 && b < B) ? ckm1[kCkT + b] - t : 0.0;
+    sm.U3[kPad + b] = (k >= 1 && b < B) ? t : 0.0;
+    sm.U3[2 * kPad + b] = (k >= 1 && b < B) ? ck[kCkM + b] : 0.0;
+  }
+  __syncthreads();
+  r3_prepare(Pb, owner, bi, bj, tid, B, sm);
+  r3_solve(Pb, Cb, owner, bi, bj, tid, B, a.refine, vbar, sm);      // u in sm.vbuf
+  for (int b = tid; b < kPad; b += kBlock) {
+    const double u = b < B ? sm.vbuf[b] : 0.0;
+    const double v = ck[kCkV + b];
+    a.u_k[(int64_t)col * kPad + b] = u;
+    bw[kBwTbar + b] = b < B ? bw[kBwTbarIn + b] + qbar * v + u : 0.0;
+    bw[kBwMubar + b] = b < B ? -P1 * v : 0.0;
+    sm.rbuf[b] = u;
+  }
+  __syncthreads();
+  if (wid == 0) {
+    double tu = 0.0, muu = 0.0;
+    for (int b = lane; b < B; b += 64) {
+      tu += ck[kCkT + b] * sm.rbuf[b];
+      muu += ck[kCkMu + b] * sm.rbuf[b];
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      tu += __shfl_xor(tu, off, 64);
+      muu += __shfl_xor(muu, off, 64);
+    }
+    if (lane == 0) {
+      bw[kBwScal + 1] = tu;
+      bw[kBwScal + 2] = muu;
+    }
+  }
+}
+
+// col B: finish mubar and tbar of iteration k, sbar, and hand over to k - 1.
+__global__ void __launch_bounds__(128) bwd_colB_kernel(BwColArgs a) {
+  const int col = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const ColState& st = a.state[col];
+  if (st.status != MF_COL_OK) return;
+  const ColInfo ci = a.cols[col];
+  const int B = a.B, k = a.k;
+  const int64_t stride = a.partial_stride;
+  const double* P = a.partials + (int64_t)ci.first_item * stride;
+  const double* ck = a.ck_k + (int64_t)col * kCk;
+  const double* u = a.u_k + (int64_t)col * kPad;
+  double* bw = a.bwcol + (int64_t)col * kBw;
+  __shared__ double mub[kPad], sc[8];
+  if (tid == 0) {
+    double A0 = 0.0, B0 = 0.0, A1 = 0.0, B1 = 0.0, RR = 0.0;
+    for (int it = 0; it < ci.n_items; ++it) {
+      A0 += P[it * stride + kBwA0];
+      B0 += P[it * stride + kBwB0];
+      A1 += P[it * stride + kBwA1];
+      B1 += P[it * stride + kBwB1];
+      RR += P[it * stride + kBwRR];
+    }
+    sc[0] = A0; sc[1] = B0; sc[2] = A1; sc[3] = B1; sc[4] = RR;
+  }
+  __syncthreads();
+  const double N = ck[kCkScal + 3];
+  for (int b = tid; b < kPad; b += 128) {
+    double mubar = 0.0, tbar = 0.0;
+    if (b < B) {
+      const double v = ck[kCkV + b];
+      mubar = bw[kBwMubar + b] + (u[b] * sc[0] + v * sc[1]) / N;
+      tbar = bw[kBwTbar + b] + (u[b] * sc[2] + v * sc[3]) / N;
+      mubar += tbar * (double)a.s[b];                 // t = mu (.) s
+      bw[kBwSbar + b] += tbar * ck[kCkMu + b];
+    }
+    mub[b] = mubar;
+  }
+  __syncthreads();
+  if (k >= 1) {
+    const double* ckm1 = a.ck_km1 + (int64_t)col * kCk;
+    if (wid == 0) {
+      double d = 0.0;
+      for (int b = lane; b < B; b += 64) d += mub[b] * ckm1[kCkT + b];
+      for (int off = 32; off >= 1; off >>= 1) d += __shfl_xor(d, off, 64);
+      if (lane == 0) bw[kBwScal + 0] = -d / N;       // gamma for pass A(k-1)
+    }
+    const double ak = ck[kCkScal + 0];
+    for (int b = tid; b < kPad; b += 128) {
+      bw[kBwMbar + b] += mub[b];
+      bw[kBwTbarIn + b] = -ak * mub[b];
+    }
+  } else {
+    // albedo factor r_i = L_i . mu0 / |mu0|^2 (Eq. 7), mu0 = mean L
+    if (wid == 0) {
+      double m2 = 0.0;
+      for (int b = lane; b < B; b += 64) m2 += st.lbar[b] * st.lbar[b];
+      for (int off = 32; off >= 1; off >>= 1) m2 += __shfl_xor(m2, off, 64);
+      if (lane == 0) sc[5] = m2;
+    }
+    __syncthreads();
+    const double m2 = sc[5];
+    for (int b = tid; b < B; b += 128) {
+      double RL = 0.0;
+      for (int it = 0; it < ci.n_items; ++it) RL += P[it * stride + b];
+      double alb = 0.0;
+      if (a.albedo) alb = RL / m2 - 2.0 * sc[4] * st.lbar[b] / m2;
+      bw[kBwMbar + b] += mub[b] + alb;
+    }
+  }
+}
+
+// G_i = sum_k (cv_i^k v^k + cu_i^k u^k) + rbar_i mu0 / |mu0|^2 + Mbar / N.
+struct BwAsmArgs {
+  const WorkItem* items;
+  const ColState* state;
+  const uint8_t* valid;
+  const double* ck;          // [K+1][n_cols][kCk]
+  const double* u_hist;      // [K+1][n_cols][kPad]
+  const double* coef;        // [2(K+1)][max_px]
+  const double* rbar;
+  const double* bwcol;
+  float* grad_L;
+  int64_t max_px;
+  int n_cols, B, K, albedo;
+};
+
+__host__ __device__ constexpr size_t asm_lds_bytes(int B, int K) {
+  return (size_t)(2 * (K + 1) + 2) * kPad * sizeof(double) + (size_t)kChunk * B * sizeof(float);
+}
+
+__global__ void __launch_bounds__(64) bwd_assemble_kernel(BwAsmArgs a) {
+  const WorkItem it = a.items[blockIdx.x];
+  const ColState& st = a.state[it.col];
+  const int lane = threadIdx.x;
+  const int B = a.B, K = a.K, nb = 2 * (K + 1);
+  const int64_t begin = it.px_begin, end = begin + it.n_px;
+  extern __shared__ double dyn[];
+  double* basis = dyn;                                // [nb + 2][kPad]
+  float* tile = reinterpret_cast<float*>(basis + (nb + 2) * kPad);
+  const bool good = st.status == MF_COL_OK;
+  if (good) {
+    const double N = st.n_valid;
+    const double* bw = a.bwcol + (int64_t)it.col * kBw;
+    for (int e = lane; e < (nb + 2) * kPad; e += 64) {
+      const int j = e / kPad, b = e - j * kPad;
+      double v = 0.0;
+      if (b < B) {
+        if (j < nb) {
+          const int kk = j >> 1;
+          v = (j & 1) ? a.u_hist[((int64_t)kk * a.n_cols + it.col) * kPad + b]
+                      : a.ck[((int64_t)kk * a.n_cols + it.col) * kCk + kCkV + b];
+        } else if (j == nb) {
+          v = a.albedo ? st.m0[b] : 0.0;
+        } else {
+          v = bw[kBwMbar + b] / N;
+        }
+      }
+      basis[e] = v;
+    }
+  }
+  wave_sync_lds();
+  for (int64_t c0 = begin; c0 < end; c0 += kChunk) {
+    const int n = (int)min<int64_t>(kChunk, end - c0);
+    const int64_t px = c0 + lane;
+    const bool inb = lane < n;
+    bool ok = inb && good;
+    if (ok && a.valid) ok = a.valid[px] != 0;
+    double acc[kPad];
+#pragma unroll
+    for (int b = 0; b < kPad; ++b) acc[b] = 0.0;
+    if (ok) {
+      for (int j = 0; j < nb; ++j) {
+        const double cj = a.coef[(int64_t)j * a.max_px + px];
+        const double* bj = basis + j * kPad;
+#pragma unroll
+        for (int b = 0; b < kPad; ++b) acc[b] = fma(cj, bj[b], acc[b]);
+      }
+      const double rb = a.rbar[px];
+#pragma unroll
+      for (int b = 0; b < kPad; ++b) acc[b] += rb * basis[nb * kPad + b] + basis[(nb + 1) * kPad + b];
+    }
+    if (inb) {
+#pragma unroll
+      for (int b = 0; b < kPad; ++b)
+        if (b < B) tile[lane * B + b] = ok ? (float)acc[b] : 0.f;
+    }
+    wave_sync_lds();
+    float* g = a.grad_L + c0 * B;
+    for (int e = lane; e < n * B; e += 64) g[e] = tile[e];
+    wave_sync_lds();
+  }
+}
+
+__global__ void bwd_sbar_kernel(const ColState* state, const double* bwcol, int n_cols, int B,
+                                double* grad_s) {
+  const int b = threadIdx.x;
+  if (b >= B) return;
+  double s = 0.0;
+  for (int c = 0; c < n_cols; ++c)
+    if (state[c].status == MF_COL_OK) s += bwcol[(int64_t)c * kBw + kBwSbar + b];
+  grad_s[b] = s;
 }
 
 // Plain streaming read: the achievable HBM read bandwidth for this access
@@ -1379,6 +1952,8 @@ struct mf_plan_s {
   ColInfo* cols_d = nullptr;
   WorkItem* items_d = nullptr;
   size_t off_state = 0, off_partials = 0, off_c0 = 0, off_pinv = 0, off_alpha0 = 0, off_alpha1 = 0;
+  // save_for_backward: checkpoints and adjoint buffers
+  size_t off_ck_alpha = 0, off_ck_col = 0, off_bw_px = 0, off_bw_coef = 0, off_bw_u = 0, off_bw_col = 0;
   size_t ws_bytes = 0;
 };
 
@@ -1485,6 +2060,7 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   ColState* state = (ColState*)(ws + p->off_state);
   double* partials = (double*)(ws + p->off_partials);
   double* abuf[2] = {(double*)(ws + p->off_alpha0), (double*)(ws + p->off_alpha1)};
+  double* ck_alpha = p->opt.save_for_backward ? (double*)(ws + p->off_ck_alpha) : nullptr;
   const int B = p->opt.n_bands;
   const int K = p->opt.n_iter;
 
@@ -1515,11 +2091,18 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   sa.B = B;
   sa.refine = p->opt.refine_steps;
   sa.lowrank = p->opt.cov == MF_COV_LOWRANK;
+  sa.ck = p->opt.save_for_backward ? (double*)(ws + p->off_ck_col) : nullptr;
+  sa.n_cols = (int)p->n_cols;
   for (int j = 0; j <= K + 1; ++j) {
     pa.j = j;
     pa.unclamped = (j == 1 && K == 0) ? 1 : 0;
-    pa.alpha_prev = j >= 2 ? abuf[(j - 2) & 1] : nullptr;
-    pa.alpha_out = (j >= 1 && j <= K) ? abuf[(j - 1) & 1] : nullptr;
+    if (ck_alpha) {          // save_for_backward: keep alpha^0..alpha^K
+      pa.alpha_prev = j >= 2 ? ck_alpha + (int64_t)(j - 2) * p->max_px : nullptr;
+      pa.alpha_out = j >= 1 ? ck_alpha + (int64_t)(j - 1) * p->max_px : nullptr;
+    } else {
+      pa.alpha_prev = j >= 2 ? abuf[(j - 2) & 1] : nullptr;
+      pa.alpha_out = (j >= 1 && j <= K) ? abuf[(j - 1) & 1] : nullptr;
+    }
     pa.alpha_final = j == K + 1 ? alpha : nullptr;
     const bool mom = j <= K;
     const int mode = pass_mode(p->opt.cov, j, K);
@@ -1598,8 +2181,12 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
     return fail_with(MF_E_ARG, "cov must be one of MF_COV_*");
   if (opt->refine_steps < 0 || opt->refine_steps > 4)
     return fail_with(MF_E_ARG, "refine_steps must be in [0, 4]");
-  if (opt->save_for_backward != 0)
-    return fail_with(MF_E_UNSUPPORTED, "save_for_backward is not available in ABI version 1");
+  if (opt->save_for_backward != 0 && opt->save_for_backward != 1)
+    return fail_with(MF_E_ARG, "save_for_backward must be 0 or 1");
+  if (opt->save_for_backward && opt->cov != MF_COV_LOWRANK)
+    return fail_with(MF_E_UNSUPPORTED, "save_for_backward needs the low-rank covariance form");
+  if (opt->save_for_backward && opt->n_iter > 30)
+    return fail_with(MF_E_UNSUPPORTED, "save_for_backward supports n_iter <= 30");
   if (opt->chunk_lines < 0 || opt->chunk_lines % 128 != 0)
     return fail_with(MF_E_ARG, "chunk_lines must be a non-negative multiple of 128");
   if (n_fl < 1) return fail_with(MF_E_SHAPE, "need at least one flightline");
@@ -1679,6 +2266,21 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   off = align256(off + (size_t)max_px * sizeof(double));
   p->off_alpha1 = off;
   off = align256(off + (size_t)max_px * sizeof(double));
+  if (opt->save_for_backward) {
+    const size_t K1 = (size_t)opt->n_iter + 1;
+    p->off_ck_alpha = off;
+    off = align256(off + K1 * (size_t)max_px * sizeof(double));
+    p->off_ck_col = off;
+    off = align256(off + K1 * (size_t)p->n_cols * kCk * sizeof(double));
+    p->off_bw_px = off;
+    off = align256(off + 3 * (size_t)max_px * sizeof(double));
+    p->off_bw_coef = off;
+    off = align256(off + 2 * K1 * (size_t)max_px * sizeof(double));
+    p->off_bw_u = off;
+    off = align256(off + K1 * (size_t)p->n_cols * kPad * sizeof(double));
+    p->off_bw_col = off;
+    off = align256(off + (size_t)p->n_cols * kBw * sizeof(double));
+  }
   p->ws_bytes = off;
   *out = p;
   g_last_error.clear();
@@ -1730,6 +2332,123 @@ mf_status mf_retrieve(mf_plan p, const float* radiance, const uint8_t* valid, co
   enqueue_retrieve(p, radiance, valid, s, alpha, column_status, workspace, st);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail_with(MF_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+  return MF_OK;
+}
+
+mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, const float* s,
+                      const float* grad_alpha, float* grad_radiance, double* grad_s,
+                      void* workspace, void* stream) {
+  if (!p) return fail_with(MF_E_ARG, "plan is NULL");
+  if (!p->opt.save_for_backward)
+    return fail_with(MF_E_STATE, "the plan was created without save_for_backward");
+  if (!radiance || !s || !grad_alpha || !grad_radiance || !grad_s || !workspace)
+    return fail_with(MF_E_ARG, "radiance, s, grad_alpha, grad_radiance, grad_s and workspace must be non-NULL");
+  if (((uintptr_t)workspace & 255) != 0) return fail_with(MF_E_ARG, "workspace must be 256-byte aligned");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail_with(MF_E_DEVICE, "current device differs from the plan's device");
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const int B = p->opt.n_bands, K = p->opt.n_iter;
+  const int64_t mp = p->max_px;
+  ColState* state = (ColState*)(ws + p->off_state);
+  double* partials = (double*)(ws + p->off_partials);
+  double* ck_alpha = (double*)(ws + p->off_ck_alpha);
+  double* ck_col = (double*)(ws + p->off_ck_col);
+  double* bwpx = (double*)(ws + p->off_bw_px);
+  double* coef = (double*)(ws + p->off_bw_coef);
+  double* u_hist = (double*)(ws + p->off_bw_u);
+  double* bwcol = (double*)(ws + p->off_bw_col);
+  const int pstride = n_tiles(p->nb) * 256;
+  (void)hipGetLastError();
+  {
+    const int64_t n = p->n_cols * kBw;
+    LaunchTimer tm(p, MF_KERNEL_OTHER, st);
+    hipLaunchKernelGGL(bwd_init_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, bwcol, n);
+  }
+  BwArgs ba{};
+  ba.L = radiance;
+  ba.valid = valid;
+  ba.items = p->items_d;
+  ba.state = state;
+  ba.grad_alpha = grad_alpha;
+  ba.abar = bwpx;
+  ba.rbar = bwpx + mp;
+  ba.pbar = bwpx + 2 * mp;
+  ba.bwcol = bwcol;
+  ba.partials = partials;
+  ba.partial_stride = pstride;
+  ba.B = B;
+  ba.K = K;
+  ba.lam = p->opt.lambda;
+  ba.eps = p->opt.epsilon;
+  ba.albedo = p->opt.albedo;
+  BwColArgs ca{};
+  ca.cols = p->cols_d;
+  ca.state = state;
+  ca.c0 = (double*)(ws + p->off_c0);
+  ca.pinv = (double*)(ws + p->off_pinv);
+  ca.partials = partials;
+  ca.bwcol = bwcol;
+  ca.s = s;
+  ca.partial_stride = pstride;
+  ca.B = B;
+  ca.refine = p->opt.refine_steps;
+  ca.albedo = p->opt.albedo;
+  const size_t lds = bwd_lds_bytes(B);
+  for (int k = K; k >= 0; --k) {
+    ba.k = ca.k = k;
+    ba.ck_k = ca.ck_k = ck_col + (int64_t)k * p->n_cols * kCk;
+    ca.ck_km1 = k >= 1 ? ck_col + (int64_t)(k - 1) * p->n_cols * kCk : nullptr;
+    ba.a_k = ck_alpha + (int64_t)k * mp;
+    ba.a_km1 = k >= 1 ? ck_alpha + (int64_t)(k - 1) * mp : nullptr;
+    ba.coef_v = coef + (int64_t)(2 * k) * mp;
+    ba.coef_u = coef + (int64_t)(2 * k + 1) * mp;
+    ba.u_k = ca.u_k = u_hist + (int64_t)k * p->n_cols * kPad;
+    {
+      LaunchTimer tm(p, MF_KERNEL_PASS_VEC, st);
+      hipLaunchKernelGGL(bwd_kernel<0>, dim3((unsigned)p->n_items), dim3(kSBlock), lds, st, ba);
+    }
+    {
+      LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
+      hipLaunchKernelGGL(bwd_colA_kernel, dim3((unsigned)p->n_cols), dim3(kBlock), 0, st, ca);
+    }
+    {
+      LaunchTimer tm(p, MF_KERNEL_PASS_VEC, st);
+      hipLaunchKernelGGL(bwd_kernel<1>, dim3((unsigned)p->n_items), dim3(kSBlock), lds, st, ba);
+    }
+    {
+      LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
+      hipLaunchKernelGGL(bwd_colB_kernel, dim3((unsigned)p->n_cols), dim3(128), 0, st, ca);
+    }
+  }
+  BwAsmArgs aa{};
+  aa.items = p->items_d;
+  aa.state = state;
+  aa.valid = valid;
+  aa.ck = ck_col;
+  aa.u_hist = u_hist;
+  aa.coef = coef;
+  aa.rbar = bwpx + mp;
+  aa.bwcol = bwcol;
+  aa.grad_L = grad_radiance;
+  aa.max_px = mp;
+  aa.n_cols = (int)p->n_cols;
+  aa.B = B;
+  aa.K = K;
+  aa.albedo = p->opt.albedo;
+  {
+    LaunchTimer tm(p, MF_KERNEL_PASS_LAST, st);
+    hipLaunchKernelGGL(bwd_assemble_kernel, dim3((unsigned)p->n_items), dim3(64), asm_lds_bytes(B, K),
+                       st, aa);
+  }
+  {
+    LaunchTimer tm(p, MF_KERNEL_OTHER, st);
+    hipLaunchKernelGGL(bwd_sbar_kernel, dim3(1), dim3(128), 0, st, state, bwcol, (int)p->n_cols, B,
+                       grad_s);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail_with(MF_E_DEVICE, std::string("backward launch: ") + hipGetErrorString(e));
   return MF_OK;
 }
 

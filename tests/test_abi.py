@@ -58,11 +58,20 @@ def _create(**kw):
     ("cov", -1, mf.MF_E_ARG),
     ("refine_steps", 9, mf.MF_E_ARG),
     ("chunk_lines", 100, mf.MF_E_ARG),
-    ("save_for_backward", 1, mf.MF_E_UNSUPPORTED),
+    ("save_for_backward", 2, mf.MF_E_ARG),
 ])
 def test_bad_options_rejected_on_host(field, value, code):
     rc, h, msg = _create(**{field: value})
     assert rc == code and not h.value and msg
+
+
+def test_backward_needs_low_rank_form_and_k_le_30():
+    rc, h, msg = _create(save_for_backward=1, cov=1)
+    assert rc == mf.MF_E_UNSUPPORTED and "low-rank" in msg
+    rc, h, msg = _create(save_for_backward=1, n_iter=31)
+    assert rc == mf.MF_E_UNSUPPORTED
+    lib = mf.load_library()
+    assert lib.mf_backward(None, None, None, None, None, None, None, None, None) == mf.MF_E_ARG
 
 
 def test_bad_geometry_rejected_on_host():

@@ -45,6 +45,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-lines", type=int, default=8000)
     ap.add_argument("--save-alpha", default="", help="save each form's alpha as <path>_<form>.npy")
+    ap.add_argument("--no-fwd-bwd", action="store_true",
+                    help="skip the forward+backward leg on the 598x4000 differentiation scene")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 1 GiB device copies (known bytes) for HBM counter scaling")
     args = ap.parse_args()
@@ -148,6 +150,55 @@ def main():
         plan.close()
         del ws
 
+    # forward + backward (hand-written adjoint) on the differentiation scene:
+    # 598 x 4000 x 74, 30 iterations, J = sum (alpha - alpha_true)^2
+    fwdbwd = None
+    if not args.no_fwd_bwd:
+        from synth.scenes import diff_spec
+        dcfg = json.load(open(os.path.join(ROOT, "configs", "diff.json")))
+        dsc = make_scene(diff_spec())
+        dS, dN, _ = dsc.radiance.shape
+        dL = torch.from_numpy(dsc.radiance).to(dev)
+        ds_ = torch.from_numpy(dsc.s).to(dev)
+        dtrue = torch.from_numpy(dsc.alpha_true.astype(np.float32)).to(dev)
+        plan = mf.Plan([(0, dS, dN)], B, K, dcfg["lambda"], eps, True, "lowrank", save_for_backward=True)
+        ws = plan.alloc_workspace(dev)
+        da = torch.empty((dS, dN), dtype=torch.float32, device=dev)
+        steps = max(3, args.steps // 4)
+
+        def fb():
+            plan.retrieve(dL, ds_, da, None, None, ws)
+            g = 2.0 * (da - dtrue)
+            return plan.backward(dL, ds_, g, None, ws)
+
+        for _ in range(max(1, args.warmup)):
+            fb()
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        for _ in range(steps):
+            fb()
+        torch.cuda.synchronize()
+        dtfb = (time.perf_counter() - t4) / steps
+        t5 = time.perf_counter()
+        for _ in range(steps):
+            plan.retrieve(dL, ds_, da, None, None, ws)
+        torch.cuda.synchronize()
+        dtf = (time.perf_counter() - t5) / steps
+        plan.set_timing(True)
+        plan.kernel_times()
+        fb()
+        kt = plan.kernel_times()
+        plan.set_timing(False)
+        fwdbwd = {"workload": f"differentiation scene {dS}x{dN}x{B}, {K} iterations, lambda "
+                              f"{dcfg['lambda']:.4g}, loss sum (alpha - alpha_true)^2",
+                  "px_per_s": round(dS * dN / dtfb, 1), "ms_per_step": round(1e3 * dtfb, 3),
+                  "forward_ms": round(1e3 * dtf, 3), "backward_ms": round(1e3 * (dtfb - dtf), 3),
+                  "kernels_ms_fwd_plus_bwd": {k: round(v[0], 4) for k, v in kt.items()}}
+        log(f"fwd+bwd: {fwdbwd['px_per_s'] / 1e6:.1f} Mpx/s, {fwdbwd['ms_per_step']:.2f} ms "
+            f"(forward {fwdbwd['forward_ms']:.2f} ms)")
+        plan.close()
+        del ws, dL
+
     # CPU baseline: the FP64 oracle on the host cores; its output is also the
     # reference for every form's error report.
     cpu = None
@@ -217,6 +268,7 @@ def main():
                       "dominant_GBps": round(r["dominant_GBps"], 1),
                       "error_vs_fp64": errors.get(f)} for f, r in results.items()},
     }
+    out["fwd_bwd"] = fwdbwd
     if "bf16" in results and "fp32" in results:
         out["bf16_vs_fp32_gram_speedup"] = round(results["bf16"]["px_per_s"] / results["fp32"]["px_per_s"], 3)
     print(json.dumps(out), flush=True)

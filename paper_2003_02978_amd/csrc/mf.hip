@@ -1512,9 +1512,45 @@ __global__ void __launch_bounds__(kSBlock) bwd_kernel(BwArgs a) {
   double m_lo = 0.0, m_hi = 0.0;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
 
-  for (int64_t c0 = begin + (int64_t)kChunk * wid; c0 < end; c0 += kSW * kChunk) {
+  // chunk pipeline as in stream_kernel: whole 16-byte aligned chunks are
+  // prefetched one chunk ahead in registers, other chunks copied in place
+  const uintptr_t lp = reinterpret_cast<uintptr_t>(a.L);
+  constexpr int kF4 = (kChunk * 78 / 4 + 63) / 64;
+  float4 pre[kF4];
+  auto fast = [&](int64_t c) {
+    return c + kChunk <= end && ((lp + (uintptr_t)(c * B) * 4) & 15) == 0;
+  };
+  auto prefetch = [&](int64_t c) {
+    const float4* g4 = reinterpret_cast<const float4*>(a.L + c * B);
+    const int n4 = kChunk * B / 4;
+#pragma unroll
+    for (int q = 0; q < kF4; ++q) {
+      const int e = lane + 64 * q;
+      pre[q] = e < n4 ? g4[e] : float4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  int64_t c0 = begin + (int64_t)kChunk * wid;
+  bool have = c0 < end && fast(c0);
+  if (have) prefetch(c0);
+  for (; c0 < end; c0 += kSW * kChunk) {
     const int n = (int)min<int64_t>(kChunk, end - c0);
-    copy_chunk(a.L + c0 * B, n * B, my, lane);
+    if (have) {
+      float4* t4 = reinterpret_cast<float4*>(my);
+      const int n4 = kChunk * B / 4;
+#pragma unroll
+      for (int q = 0; q < kF4; ++q) {
+        const int e = lane + 64 * q;
+        if (e < n4) t4[e] = pre[q];
+      }
+      wave_sync_lds();
+    } else {
+      copy_chunk(a.L + c0 * B, n * B, my, lane);
+    }
+    {
+      const int64_t nx = c0 + kSW * kChunk;
+      have = nx < end && fast(nx);
+      if (have) prefetch(nx);
+    }
     const int64_t px = c0 + lane;
     const bool inb = lane < n;
     bool ok = inb;
@@ -1522,7 +1558,25 @@ __global__ void __launch_bounds__(kSBlock) bwd_kernel(BwArgs a) {
     double pp = 0.0, rr = 0.0, lu = 0.0;
     if (ok) {
       const float* rowp = my + lane * B;
-      for (int b = 0; b < B; ++b) {
+      int b = 0;
+      if ((B & 1) == 0) {
+#pragma unroll 4
+        for (; b < B; b += 2) {
+          const float2 l2 = *reinterpret_cast<const float2*>(rowp + b);
+          const double4 c0v = *reinterpret_cast<const double4*>(cst + 4 * b);
+          const double4 c1v = *reinterpret_cast<const double4*>(cst + 4 * b + 4);
+          const double l0 = (double)l2.x, l1 = (double)l2.y;
+          pp = fma(l0 - c0v.x, c0v.y, pp);
+          rr = fma(l0, c0v.z, rr);
+          pp = fma(l1 - c1v.x, c1v.y, pp);
+          rr = fma(l1, c1v.z, rr);
+          if (PASS == 1) {
+            lu = fma(l0, c0v.w, lu);
+            lu = fma(l1, c1v.w, lu);
+          }
+        }
+      }
+      for (; b < B; ++b) {
         const double l = (double)rowp[b];
         pp = fma(l - cst[4 * b], cst[4 * b + 1], pp);
         rr = fma(l, cst[4 * b + 2], rr);
@@ -1812,23 +1866,28 @@ struct BwAsmArgs {
 };
 
 __host__ __device__ constexpr size_t asm_lds_bytes(int B, int K) {
-  return (size_t)(2 * (K + 1) + 2) * kPad * sizeof(double) + (size_t)kChunk * B * sizeof(float);
+  return (size_t)(2 * (K + 1) + 2) * kPad * sizeof(double);
 }
 
-__global__ void __launch_bounds__(64) bwd_assemble_kernel(BwAsmArgs a) {
+constexpr int kMaxCoef = 62;        // 2 (K + 1) for K <= 30
+constexpr int kHalf = kPad / 2;     // bands accumulated per sweep
+
+// Four waves share the column's basis in LDS; each lane holds one pixel's
+// coefficients in registers and accumulates the bands in two halves.
+__global__ void __launch_bounds__(256) bwd_assemble_kernel(BwAsmArgs a) {
   const WorkItem it = a.items[blockIdx.x];
   const ColState& st = a.state[it.col];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
   const int B = a.B, K = a.K, nb = 2 * (K + 1);
   const int64_t begin = it.px_begin, end = begin + it.n_px;
   extern __shared__ double dyn[];
   double* basis = dyn;                                // [nb + 2][kPad]
-  float* tile = reinterpret_cast<float*>(basis + (nb + 2) * kPad);
   const bool good = st.status == MF_COL_OK;
   if (good) {
     const double N = st.n_valid;
     const double* bw = a.bwcol + (int64_t)it.col * kBw;
-    for (int e = lane; e < (nb + 2) * kPad; e += 64) {
+    for (int e = tid; e < (nb + 2) * kPad; e += 256) {
       const int j = e / kPad, b = e - j * kPad;
       double v = 0.0;
       if (b < B) {
@@ -1845,36 +1904,36 @@ __global__ void __launch_bounds__(64) bwd_assemble_kernel(BwAsmArgs a) {
       basis[e] = v;
     }
   }
-  wave_sync_lds();
-  for (int64_t c0 = begin; c0 < end; c0 += kChunk) {
-    const int n = (int)min<int64_t>(kChunk, end - c0);
+  __syncthreads();
+  for (int64_t c0 = begin + (int64_t)kChunk * wid; c0 < end; c0 += 4 * kChunk) {
     const int64_t px = c0 + lane;
-    const bool inb = lane < n;
+    const bool inb = px < end;
     bool ok = inb && good;
     if (ok && a.valid) ok = a.valid[px] != 0;
-    double acc[kPad];
+    double cf[kMaxCoef];
 #pragma unroll
-    for (int b = 0; b < kPad; ++b) acc[b] = 0.0;
-    if (ok) {
-      for (int j = 0; j < nb; ++j) {
-        const double cj = a.coef[(int64_t)j * a.max_px + px];
-        const double* bj = basis + j * kPad;
+    for (int j = 0; j < kMaxCoef; ++j) cf[j] = (ok && j < nb) ? a.coef[(int64_t)j * a.max_px + px] : 0.0;
+    const double rb = ok ? a.rbar[px] : 0.0;
+    float* g = a.grad_L + px * B;
 #pragma unroll
-        for (int b = 0; b < kPad; ++b) acc[b] = fma(cj, bj[b], acc[b]);
+    for (int h = 0; h < 2; ++h) {
+      double acc[kHalf];
+#pragma unroll
+      for (int b = 0; b < kHalf; ++b)
+        acc[b] = rb * basis[nb * kPad + kHalf * h + b] + basis[(nb + 1) * kPad + kHalf * h + b];
+#pragma unroll
+      for (int j = 0; j < kMaxCoef; ++j) {
+        if (j >= nb) break;
+        const double* bj = basis + j * kPad + kHalf * h;
+#pragma unroll
+        for (int b = 0; b < kHalf; ++b) acc[b] = fma(cf[j], bj[b], acc[b]);
       }
-      const double rb = a.rbar[px];
+      if (inb) {
 #pragma unroll
-      for (int b = 0; b < kPad; ++b) acc[b] += rb * basis[nb * kPad + b] + basis[(nb + 1) * kPad + b];
+        for (int b = 0; b < kHalf; ++b)
+          if (kHalf * h + b < B) g[kHalf * h + b] = ok ? (float)acc[b] : 0.f;
+      }
     }
-    if (inb) {
-#pragma unroll
-      for (int b = 0; b < kPad; ++b)
-        if (b < B) tile[lane * B + b] = ok ? (float)acc[b] : 0.f;
-    }
-    wave_sync_lds();
-    float* g = a.grad_L + c0 * B;
-    for (int e = lane; e < n * B; e += 64) g[e] = tile[e];
-    wave_sync_lds();
   }
 }
 
@@ -2439,7 +2498,7 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
   aa.albedo = p->opt.albedo;
   {
     LaunchTimer tm(p, MF_KERNEL_PASS_LAST, st);
-    hipLaunchKernelGGL(bwd_assemble_kernel, dim3((unsigned)p->n_items), dim3(64), asm_lds_bytes(B, K),
+    hipLaunchKernelGGL(bwd_assemble_kernel, dim3((unsigned)p->n_items), dim3(256), asm_lds_bytes(B, K),
                        st, aa);
   }
   {

@@ -1865,73 +1865,88 @@ struct BwAsmArgs {
   int n_cols, B, K, albedo;
 };
 
+// Gradient assembly as one FP64 product per column: the pixel's coefficient
+// row (2 (K+1) slots, then rbar and 1) times the column's basis (v^k and u^k
+// rows, then m0 and Mbar / N), both padded to 64 rows.
+constexpr int kAsmRows = 64;
+constexpr int kAsmTiles = kPad / 16;
+
 __host__ __device__ constexpr size_t asm_lds_bytes(int B, int K) {
-  return (size_t)(2 * (K + 1) + 2) * kPad * sizeof(double);
+  return (size_t)kAsmRows * kPad * sizeof(double);
 }
 
-constexpr int kMaxCoef = 62;        // 2 (K + 1) for K <= 30
-constexpr int kHalf = kPad / 2;     // bands accumulated per sweep
-
-// Four waves share the column's basis in LDS; each lane holds one pixel's
-// coefficients in registers and accumulates the bands in two halves.
+// Four waves share the column's basis in LDS; each wave takes 16 pixels at a
+// time on v_mfma_f64_16x16x4f64 (A: pixels x coefficient slots from global,
+// B: slots x bands from LDS), 16 slot steps x 5 band tiles.
 __global__ void __launch_bounds__(256) bwd_assemble_kernel(BwAsmArgs a) {
   const WorkItem it = a.items[blockIdx.x];
   const ColState& st = a.state[it.col];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
-  const int B = a.B, K = a.K, nb = 2 * (K + 1);
+  const int row = lane & 15, kq = lane >> 4;
+  const int B = a.B, nb = 2 * (a.K + 1);
   const int64_t begin = it.px_begin, end = begin + it.n_px;
   extern __shared__ double dyn[];
-  double* basis = dyn;                                // [nb + 2][kPad]
+  double* basis = dyn;                                // [kAsmRows][kPad]
   const bool good = st.status == MF_COL_OK;
-  if (good) {
-    const double N = st.n_valid;
-    const double* bw = a.bwcol + (int64_t)it.col * kBw;
-    for (int e = tid; e < (nb + 2) * kPad; e += 256) {
-      const int j = e / kPad, b = e - j * kPad;
-      double v = 0.0;
-      if (b < B) {
-        if (j < nb) {
-          const int kk = j >> 1;
-          v = (j & 1) ? a.u_hist[((int64_t)kk * a.n_cols + it.col) * kPad + b]
-                      : a.ck[((int64_t)kk * a.n_cols + it.col) * kCk + kCkV + b];
-        } else if (j == nb) {
-          v = a.albedo ? st.m0[b] : 0.0;
-        } else {
-          v = bw[kBwMbar + b] / N;
-        }
+  const double N = good ? (double)st.n_valid : 1.0;
+  const double* bw = a.bwcol + (int64_t)it.col * kBw;
+  for (int e = tid; e < kAsmRows * kPad; e += 256) {
+    const int j = e / kPad, b = e - j * kPad;
+    double v = 0.0;
+    if (good && b < B) {
+      if (j < nb) {
+        const int kk = j >> 1;
+        v = (j & 1) ? a.u_hist[((int64_t)kk * a.n_cols + it.col) * kPad + b]
+                    : a.ck[((int64_t)kk * a.n_cols + it.col) * kCk + kCkV + b];
+      } else if (j == kAsmRows - 2) {
+        v = a.albedo ? st.m0[b] : 0.0;
+      } else if (j == kAsmRows - 1) {
+        v = bw[kBwMbar + b] / N;
       }
-      basis[e] = v;
     }
+    basis[e] = v;
   }
   __syncthreads();
-  for (int64_t c0 = begin + (int64_t)kChunk * wid; c0 < end; c0 += 4 * kChunk) {
-    const int64_t px = c0 + lane;
-    const bool inb = px < end;
-    bool ok = inb && good;
+  for (int64_t p0 = begin + 16 * wid; p0 < end; p0 += 64) {
+    const int64_t px = p0 + row;                       // A row of this lane
+    bool ok = good && px < end;
     if (ok && a.valid) ok = a.valid[px] != 0;
-    double cf[kMaxCoef];
+    double cf[kAsmRows / 4];
 #pragma unroll
-    for (int j = 0; j < kMaxCoef; ++j) cf[j] = (ok && j < nb) ? a.coef[(int64_t)j * a.max_px + px] : 0.0;
-    const double rb = ok ? a.rbar[px] : 0.0;
-    float* g = a.grad_L + px * B;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      double acc[kHalf];
-#pragma unroll
-      for (int b = 0; b < kHalf; ++b)
-        acc[b] = rb * basis[nb * kPad + kHalf * h + b] + basis[(nb + 1) * kPad + kHalf * h + b];
-#pragma unroll
-      for (int j = 0; j < kMaxCoef; ++j) {
-        if (j >= nb) break;
-        const double* bj = basis + j * kPad + kHalf * h;
-#pragma unroll
-        for (int b = 0; b < kHalf; ++b) acc[b] = fma(cf[j], bj[b], acc[b]);
+    for (int s = 0; s < kAsmRows / 4; ++s) {
+      const int j = 4 * s + kq;
+      double v = 0.0;
+      if (ok) {
+        if (j < nb) v = a.coef[(int64_t)j * a.max_px + px];
+        else if (j == kAsmRows - 2) v = a.rbar[px];
+        else if (j == kAsmRows - 1) v = 1.0;
       }
-      if (inb) {
+      cf[s] = v;
+    }
+    doublex4 acc[kAsmTiles];
 #pragma unroll
-        for (int b = 0; b < kHalf; ++b)
-          if (kHalf * h + b < B) g[kHalf * h + b] = ok ? (float)acc[b] : 0.f;
+    for (int t = 0; t < kAsmTiles; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+    // an opaque zero keeps the basis reads inside the loop (hoisted out of
+    // it they would hold 160 registers per lane)
+    int off = (kq * kPad + row);
+    asm volatile("" : "+v"(off));
+#pragma unroll
+    for (int s = 0; s < kAsmRows / 4; ++s) {
+      const double* brow = basis + 4 * s * kPad + off;
+#pragma unroll
+      for (int t = 0; t < kAsmTiles; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[s], brow[16 * t], acc[t], 0, 0, 0);
+    }
+    // D layout: register i of this lane holds pixel p0 + 4 i + kq, band 16 t + row
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t q = p0 + 4 * i + kq;
+      if (q < end) {
+        float* g = a.grad_L + q * B;
+#pragma unroll
+        for (int t = 0; t < kAsmTiles; ++t)
+          if (16 * t + row < B) g[16 * t + row] = (float)acc[t][i];
       }
     }
   }

@@ -97,6 +97,8 @@ struct PassArgs {
   double* alpha_out;         // alpha^{j-1} (1 <= j <= K), FP64 workspace copy
   float* alpha_final;        // alpha^K (j = K + 1), the caller's FP32 output
   double* partials;          // [item][T][16][16] FP64
+  double* p_save;            // save_for_backward: p^{j-1} = (L - mu) . v per pixel (j >= 1)
+  double* r_save;            // save_for_backward: r per pixel (j = 1)
   int B;
   int j;
   int albedo;
@@ -635,6 +637,8 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
       if (inb) {
         if (a.alpha_out) a.alpha_out[px] = al;
         if (a.alpha_final) a.alpha_final[px] = (float)al;
+        if (a.p_save) a.p_save[px] = ok ? pp : 0.0;
+        if (a.r_save) a.r_save[px] = ok ? r : 0.0;
       }
       c = (ok && !dark && al > 0.0) ? r * al : 0.0;
     }
@@ -1420,6 +1424,8 @@ struct BwArgs {
   const double* ck_k;        // checkpoints of iteration k, [n_cols][kCk]
   const double* a_k;         // alpha^k (FP64 checkpoint)
   const double* a_km1;       // alpha^{k-1}, or null for k = 0
+  const double* p_k;         // p^k = (L - mu^k) . v^k per pixel (forward pass)
+  const double* r_px;        // r per pixel (forward pass), 0 off valid pixels
   const float* grad_alpha;   // adjoint of alpha^K (k = K)
   double* abar;
   double* rbar;
@@ -1474,14 +1480,118 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Dynamic LDS of bwd_kernel: tiles, per-pixel weights, partial rows, constants.
+// Dynamic LDS of bwd_passA_kernel: per-pixel weights, partial rows, mu^k, tiles.
+__host__ __device__ constexpr size_t bwdA_lds_bytes(int B) {
+  return (size_t)kSW * kChunk * sizeof(double) + kSW * (kPad + 8) * sizeof(double) +
+         kPad * sizeof(double) + (size_t)kSW * kChunk * B * sizeof(float);
+}
+
+// Reverse pass A of iteration k.  p^k = (L - mu^k) . v^k and r per pixel come
+// from the forward pass, so the radiance is read only for chunks in which a
+// pixel carries a nonzero pbar (alpha^k > 0), for V = sum pbar (L - mu^k).
+__global__ void __launch_bounds__(kSBlock) bwd_passA_kernel(BwArgs a) {
+  const WorkItem it = a.items[blockIdx.x];
+  const ColState* __restrict__ st = a.state + it.col;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int B = a.B, k = a.k;
+  const int64_t begin = it.px_begin, end = begin + it.n_px;
+  extern __shared__ double dyn[];
+  double* cbuf = dyn;                                   // [kSW][kChunk]
+  double* redm = cbuf + kSW * kChunk;                   // [kSW][kPad + 8]
+  double* mu = redm + kSW * (kPad + 8);                 // [kPad]
+  float* my = reinterpret_cast<float*>(mu + kPad) + wid * kChunk * B;
+
+  if (st->status != MF_COL_OK) return;       // failed column: gradient 0 (assembly)
+  const double* ck = a.ck_k + (int64_t)it.col * kCk;
+  const double* bw = a.bwcol + (int64_t)it.col * kBw;
+  for (int b = tid; b < kPad; b += kSBlock) mu[b] = ck[kCkMu + b];
+  __syncthreads();
+  const double q = ck[kCkScal + 2];
+  const double gamma = bw[kBwScal + 0];
+  const double lam = a.lam, eps = a.eps;
+  double m_lo = 0.0, m_hi = 0.0, s0 = 0.0, s1 = 0.0;
+  for (int64_t c0 = begin + (int64_t)kChunk * wid; c0 < end; c0 += kSW * kChunk) {
+    const int n = (int)min<int64_t>(kChunk, end - c0);
+    const int64_t px = c0 + lane;
+    const bool inb = lane < n;
+    bool ok = inb;
+    if (inb && a.valid) ok = a.valid[px] != 0;
+    const double pp = ok ? a.p_k[px] : 0.0;
+    const double r = ok ? a.r_px[px] : 0.0;     // 0 off valid pixels
+    const bool live = ok && (r > 0.0);          // dark pixels keep alpha = 0
+    double ab = 0.0, rb = 0.0;
+    if (inb) {
+      if (k == a.K) {
+        ab = (double)a.grad_alpha[px];
+      } else {
+        ab = a.abar[px] + r * gamma;
+        rb = a.rbar[px] + a.a_k[px] * gamma;
+      }
+    }
+    const double am1 = (k >= 1 && inb) ? a.a_km1[px] : 0.0;
+    const double w = k >= 1 ? lam / (am1 + eps) : 0.0;
+    const double z = live ? (pp - w) / (r * q) : 0.0;
+    const bool pos = (a.K == 0) || (z > 0.0);   // K = 0 returns alpha^0 unclamped
+    const double zeta = (live && pos) ? ab : 0.0;
+    const double pb = zeta != 0.0 ? zeta / (r * q) : 0.0;
+    if (zeta != 0.0) rb -= zeta * z / r;
+    const double abm1 = (k >= 1 && zeta != 0.0) ? zeta * lam / (r * q * (am1 + eps) * (am1 + eps)) : 0.0;
+    if (inb) {
+      a.abar[px] = ok ? abm1 : 0.0;
+      a.pbar[px] = ok ? pb : 0.0;
+      a.rbar[px] = ok ? rb : 0.0;
+    }
+    s0 += zeta != 0.0 ? zeta * z : 0.0;
+    s1 += pb;
+    if (__ballot(pb != 0.0)) {                  // wave-uniform; sparse weights
+      copy_chunk(a.L + c0 * B, n * B, my, lane);
+      cbuf[wid * kChunk + lane] = pb;
+      wave_sync_lds();
+      const int b0 = lane, b1 = lane + 64;
+      const double o0 = b0 < B ? mu[b0] : 0.0;
+      const double o1 = b1 < B ? mu[b1] : 0.0;
+      for (int p = 0; p < n; ++p) {
+        const double cp = cbuf[wid * kChunk + p];
+        if (cp != 0.0) {
+          if (b0 < B) m_lo = fma(cp, (double)my[p * B + b0] - o0, m_lo);
+          if (b1 < B) m_hi = fma(cp, (double)my[p * B + b1] - o1, m_hi);
+        }
+      }
+      wave_sync_lds();
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    s0 += __shfl_xor(s0, off, 64);
+    s1 += __shfl_xor(s1, off, 64);
+  }
+  double* rw = redm + wid * (kPad + 8);
+  if (lane < kPad) rw[lane] = lane < B ? m_lo : 0.0;
+  if (lane + 64 < kPad) rw[lane + 64] = lane + 64 < B ? m_hi : 0.0;
+  if (lane == 0) {
+    rw[80] = s0;
+    rw[81] = s1;
+    rw[82] = 0.0;
+    rw[83] = 0.0;
+    rw[84] = 0.0;
+  }
+  __syncthreads();
+  double* out = a.partials + (int64_t)blockIdx.x * a.partial_stride;
+  for (int e = tid; e < kPad + 5; e += kSBlock) {
+    double sum = 0.0;
+    for (int w = 0; w < kSW; ++w) sum += redm[w * (kPad + 8) + e];
+    out[e] = sum;
+  }
+}
+
+// Dynamic LDS of bwd_passB_kernel: tiles, per-pixel weights, partial rows, constants.
 __host__ __device__ constexpr size_t bwd_lds_bytes(int B) {
   return (size_t)kSW * kChunk * B * sizeof(float) + kSW * kChunk * sizeof(double) +
          kSW * (kPad + 8) * sizeof(double) + 4 * kPad * sizeof(double);
 }
 
-template <int PASS>   // 0: pass A, 1: pass B
-__global__ void __launch_bounds__(kSBlock) bwd_kernel(BwArgs a) {
+// Reverse pass B of iteration k (streams the radiance for beta = u^k . d).
+__global__ void __launch_bounds__(kSBlock) bwd_passB_kernel(BwArgs a) {
   const WorkItem it = a.items[blockIdx.x];
   const ColState* __restrict__ st = a.state + it.col;
   const int tid = threadIdx.x;
@@ -1501,14 +1611,14 @@ __global__ void __launch_bounds__(kSBlock) bwd_kernel(BwArgs a) {
     cst[4 * b + 0] = ck[kCkMu + b];
     cst[4 * b + 1] = ck[kCkV + b];
     cst[4 * b + 2] = st->m0[b];
-    cst[4 * b + 3] = PASS == 1 ? a.u_k[(int64_t)it.col * kPad + b] : 0.0;
+    cst[4 * b + 3] = a.u_k[(int64_t)it.col * kPad + b];
   }
   __syncthreads();
   const double q = ck[kCkScal + 2], N = ck[kCkScal + 3];
   const double gamma = bw[kBwScal + 0], tu = bw[kBwScal + 1], muu = bw[kBwScal + 2];
   const double lam = a.lam, eps = a.eps;
-  // weighted band sums: PASS A  V = sum pbar (L - mu);  PASS B (k = 0)  sum rbar L
-  const bool vec = PASS == 0 || k == 0;
+  // weighted band sum (k = 0 only): sum rbar L
+  const bool vec = k == 0;
   double m_lo = 0.0, m_hi = 0.0;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
 
@@ -1570,49 +1680,21 @@ __global__ void __launch_bounds__(kSBlock) bwd_kernel(BwArgs a) {
           rr = fma(l0, c0v.z, rr);
           pp = fma(l1 - c1v.x, c1v.y, pp);
           rr = fma(l1, c1v.z, rr);
-          if (PASS == 1) {
-            lu = fma(l0, c0v.w, lu);
-            lu = fma(l1, c1v.w, lu);
-          }
+          lu = fma(l0, c0v.w, lu);
+          lu = fma(l1, c1v.w, lu);
         }
       }
       for (; b < B; ++b) {
         const double l = (double)rowp[b];
         pp = fma(l - cst[4 * b], cst[4 * b + 1], pp);
         rr = fma(l, cst[4 * b + 2], rr);
-        if (PASS == 1) lu = fma(l, cst[4 * b + 3], lu);
+        lu = fma(l, cst[4 * b + 3], lu);
       }
     }
     const double r = a.albedo ? rr : 1.0;
     const bool live = ok && (r > 0.0);          // dark pixels keep alpha = 0
     double wgt = 0.0;
-    if (PASS == 0) {
-      double ab = 0.0, rb = 0.0;
-      if (inb) {
-        if (k == a.K) {
-          ab = (double)a.grad_alpha[px];
-        } else {
-          ab = a.abar[px] + r * gamma;
-          rb = a.rbar[px] + a.a_k[px] * gamma;
-        }
-      }
-      const double am1 = (k >= 1 && inb) ? a.a_km1[px] : 0.0;
-      const double w = k >= 1 ? lam / (am1 + eps) : 0.0;
-      const double z = (pp - w) / (r * q);
-      const bool pos = (a.K == 0) || (z > 0.0);   // K = 0 returns alpha^0 unclamped
-      const double zeta = (live && pos) ? ab : 0.0;
-      const double pb = zeta != 0.0 ? zeta / (r * q) : 0.0;
-      if (zeta != 0.0) rb -= zeta * z / r;
-      const double abm1 = (k >= 1 && zeta != 0.0) ? zeta * lam / (r * q * (am1 + eps) * (am1 + eps)) : 0.0;
-      if (inb) {
-        a.abar[px] = ok ? abm1 : 0.0;
-        a.pbar[px] = ok ? pb : 0.0;
-        a.rbar[px] = ok ? rb : 0.0;
-      }
-      s0 += zeta != 0.0 ? zeta * z : 0.0;
-      s1 += pb;
-      wgt = pb;
-    } else {
+    {
       const double am1 = (k >= 1 && live) ? a.a_km1[px] : 0.0;
       const double c = r * am1;
       const double al = ok ? pp - c * q : 0.0;
@@ -1641,13 +1723,11 @@ __global__ void __launch_bounds__(kSBlock) bwd_kernel(BwArgs a) {
       cbuf[wid * kChunk + lane] = wgt;
       wave_sync_lds();
       const int b0 = lane, b1 = lane + 64;
-      const double o0 = (PASS == 0 && b0 < B) ? cst[4 * b0] : 0.0;
-      const double o1 = (PASS == 0 && b1 < B) ? cst[4 * b1] : 0.0;
       for (int p = 0; p < n; ++p) {
         const double cp = cbuf[wid * kChunk + p];
         if (cp != 0.0) {
-          if (b0 < B) m_lo = fma(cp, (double)my[p * B + b0] - o0, m_lo);
-          if (b1 < B) m_hi = fma(cp, (double)my[p * B + b1] - o1, m_hi);
+          if (b0 < B) m_lo = fma(cp, (double)my[p * B + b0], m_lo);
+          if (b1 < B) m_hi = fma(cp, (double)my[p * B + b1], m_hi);
         }
       }
     }
@@ -2027,7 +2107,8 @@ struct mf_plan_s {
   WorkItem* items_d = nullptr;
   size_t off_state = 0, off_partials = 0, off_c0 = 0, off_pinv = 0, off_alpha0 = 0, off_alpha1 = 0;
   // save_for_backward: checkpoints and adjoint buffers
-  size_t off_ck_alpha = 0, off_ck_col = 0, off_bw_px = 0, off_bw_coef = 0, off_bw_u = 0, off_bw_col = 0;
+  size_t off_ck_alpha = 0, off_ck_col = 0, off_ck_p = 0, off_bw_px = 0, off_bw_coef = 0, off_bw_u = 0,
+         off_bw_col = 0;
   size_t ws_bytes = 0;
 };
 
@@ -2135,6 +2216,7 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   double* partials = (double*)(ws + p->off_partials);
   double* abuf[2] = {(double*)(ws + p->off_alpha0), (double*)(ws + p->off_alpha1)};
   double* ck_alpha = p->opt.save_for_backward ? (double*)(ws + p->off_ck_alpha) : nullptr;
+  double* ck_p = p->opt.save_for_backward ? (double*)(ws + p->off_ck_p) : nullptr;
   const int B = p->opt.n_bands;
   const int K = p->opt.n_iter;
 
@@ -2178,6 +2260,8 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
       pa.alpha_out = (j >= 1 && j <= K) ? abuf[(j - 1) & 1] : nullptr;
     }
     pa.alpha_final = j == K + 1 ? alpha : nullptr;
+    pa.p_save = (ck_p && j >= 1) ? ck_p + (int64_t)(j - 1) * p->max_px : nullptr;
+    pa.r_save = (ck_p && j == 1) ? ck_p + (int64_t)(K + 1) * p->max_px : nullptr;
     const bool mom = j <= K;
     const int mode = pass_mode(p->opt.cov, j, K);
     {
@@ -2346,6 +2430,8 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
     off = align256(off + K1 * (size_t)max_px * sizeof(double));
     p->off_ck_col = off;
     off = align256(off + K1 * (size_t)p->n_cols * kCk * sizeof(double));
+    p->off_ck_p = off;                       // p^0..p^K, then r
+    off = align256(off + (K1 + 1) * (size_t)max_px * sizeof(double));
     p->off_bw_px = off;
     off = align256(off + 3 * (size_t)max_px * sizeof(double));
     p->off_bw_coef = off;
@@ -2429,6 +2515,7 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
   double* partials = (double*)(ws + p->off_partials);
   double* ck_alpha = (double*)(ws + p->off_ck_alpha);
   double* ck_col = (double*)(ws + p->off_ck_col);
+  double* ck_p = (double*)(ws + p->off_ck_p);
   double* bwpx = (double*)(ws + p->off_bw_px);
   double* coef = (double*)(ws + p->off_bw_coef);
   double* u_hist = (double*)(ws + p->off_bw_u);
@@ -2446,6 +2533,7 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
   ba.items = p->items_d;
   ba.state = state;
   ba.grad_alpha = grad_alpha;
+  ba.r_px = ck_p + (int64_t)(K + 1) * mp;
   ba.abar = bwpx;
   ba.rbar = bwpx + mp;
   ba.pbar = bwpx + 2 * mp;
@@ -2469,19 +2557,20 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
   ca.B = B;
   ca.refine = p->opt.refine_steps;
   ca.albedo = p->opt.albedo;
-  const size_t lds = bwd_lds_bytes(B);
+  const size_t lds = bwd_lds_bytes(B), ldsA = bwdA_lds_bytes(B);
   for (int k = K; k >= 0; --k) {
     ba.k = ca.k = k;
     ba.ck_k = ca.ck_k = ck_col + (int64_t)k * p->n_cols * kCk;
     ca.ck_km1 = k >= 1 ? ck_col + (int64_t)(k - 1) * p->n_cols * kCk : nullptr;
     ba.a_k = ck_alpha + (int64_t)k * mp;
     ba.a_km1 = k >= 1 ? ck_alpha + (int64_t)(k - 1) * mp : nullptr;
+    ba.p_k = ck_p + (int64_t)k * mp;
     ba.coef_v = coef + (int64_t)(2 * k) * mp;
     ba.coef_u = coef + (int64_t)(2 * k + 1) * mp;
     ba.u_k = ca.u_k = u_hist + (int64_t)k * p->n_cols * kPad;
     {
       LaunchTimer tm(p, MF_KERNEL_PASS_VEC, st);
-      hipLaunchKernelGGL(bwd_kernel<0>, dim3((unsigned)p->n_items), dim3(kSBlock), lds, st, ba);
+      hipLaunchKernelGGL(bwd_passA_kernel, dim3((unsigned)p->n_items), dim3(kSBlock), ldsA, st, ba);
     }
     {
       LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
@@ -2489,7 +2578,7 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
     }
     {
       LaunchTimer tm(p, MF_KERNEL_PASS_VEC, st);
-      hipLaunchKernelGGL(bwd_kernel<1>, dim3((unsigned)p->n_items), dim3(kSBlock), lds, st, ba);
+      hipLaunchKernelGGL(bwd_passB_kernel, dim3((unsigned)p->n_items), dim3(kSBlock), lds, st, ba);
     }
     {
       LaunchTimer tm(p, MF_KERNEL_SOLVE, st);

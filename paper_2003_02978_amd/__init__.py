@@ -263,7 +263,9 @@ def _plan_backward(plan, radiance, s, grad_alpha, valid=None, workspace=None, st
         raise ValueError("backward needs the forward's workspace")
     if valid is not None:
         _need(valid, torch.uint8, "valid")
-    grad_L = torch.zeros_like(radiance)
+    # the library writes every plan pixel; rows outside the plan stay zero
+    full = plan.n_pixels * plan.n_bands == radiance.numel()
+    grad_L = torch.empty_like(radiance) if full else torch.zeros_like(radiance)
     grad_s = torch.empty(plan.n_bands, dtype=torch.float64, device=radiance.device)
     ws = workspace.data_ptr()
     ws_al = (ws + 255) & ~255

@@ -45,7 +45,7 @@ namespace {
 constexpr int kBlock = 256;      // 4 waves of 64
 constexpr int kPad = 80;         // bands of the per-column state (5 x 16)
 constexpr int kMaxTri = 80 * 81 / 2;
-constexpr int kDefaultChunk = 2048;
+constexpr int kDefaultChunk = 1024;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
@@ -1480,16 +1480,20 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Dynamic LDS of bwd_passA_kernel: per-pixel weights, partial rows, mu^k, tiles.
+// Pass A is light per pixel: eight waves per work item keep enough loads in flight.
+constexpr int kAW = 8;
+constexpr int kABlock = 64 * kAW;
+
+// Dynamic LDS of bwd_passA_kernel: per-pixel weights, partial rows, mu^k.
 __host__ __device__ constexpr size_t bwdA_lds_bytes(int B) {
-  return (size_t)kSW * kChunk * sizeof(double) + kSW * (kPad + 8) * sizeof(double) +
-         kPad * sizeof(double) + (size_t)kSW * kChunk * B * sizeof(float);
+  return (size_t)kAW * kChunk * sizeof(double) + kAW * (kPad + 8) * sizeof(double) +
+         kPad * sizeof(double);
 }
 
 // Reverse pass A of iteration k.  p^k = (L - mu^k) . v^k and r per pixel come
-// from the forward pass, so the radiance is read only for chunks in which a
-// pixel carries a nonzero pbar (alpha^k > 0), for V = sum pbar (L - mu^k).
-__global__ void __launch_bounds__(kSBlock) bwd_passA_kernel(BwArgs a) {
+// from the forward pass, so the radiance is read only for the pixels that
+// carry a nonzero pbar (alpha^k > 0), row by row, for V = sum pbar (L - mu^k).
+__global__ void __launch_bounds__(kABlock) bwd_passA_kernel(BwArgs a) {
   const WorkItem it = a.items[blockIdx.x];
   const ColState* __restrict__ st = a.state + it.col;
   const int tid = threadIdx.x;
@@ -1497,21 +1501,20 @@ __global__ void __launch_bounds__(kSBlock) bwd_passA_kernel(BwArgs a) {
   const int B = a.B, k = a.k;
   const int64_t begin = it.px_begin, end = begin + it.n_px;
   extern __shared__ double dyn[];
-  double* cbuf = dyn;                                   // [kSW][kChunk]
-  double* redm = cbuf + kSW * kChunk;                   // [kSW][kPad + 8]
-  double* mu = redm + kSW * (kPad + 8);                 // [kPad]
-  float* my = reinterpret_cast<float*>(mu + kPad) + wid * kChunk * B;
+  double* cbuf = dyn;                                   // [kAW][kChunk]
+  double* redm = cbuf + kAW * kChunk;                   // [kAW][kPad + 8]
+  double* mu = redm + kAW * (kPad + 8);                 // [kPad]
 
   if (st->status != MF_COL_OK) return;       // failed column: gradient 0 (assembly)
   const double* ck = a.ck_k + (int64_t)it.col * kCk;
   const double* bw = a.bwcol + (int64_t)it.col * kBw;
-  for (int b = tid; b < kPad; b += kSBlock) mu[b] = ck[kCkMu + b];
+  for (int b = tid; b < kPad; b += kABlock) mu[b] = ck[kCkMu + b];
   __syncthreads();
   const double q = ck[kCkScal + 2];
   const double gamma = bw[kBwScal + 0];
   const double lam = a.lam, eps = a.eps;
   double m_lo = 0.0, m_hi = 0.0, s0 = 0.0, s1 = 0.0;
-  for (int64_t c0 = begin + (int64_t)kChunk * wid; c0 < end; c0 += kSW * kChunk) {
+  for (int64_t c0 = begin + (int64_t)kChunk * wid; c0 < end; c0 += kAW * kChunk) {
     const int n = (int)min<int64_t>(kChunk, end - c0);
     const int64_t px = c0 + lane;
     const bool inb = lane < n;
@@ -1544,18 +1547,35 @@ __global__ void __launch_bounds__(kSBlock) bwd_passA_kernel(BwArgs a) {
     }
     s0 += zeta != 0.0 ? zeta * z : 0.0;
     s1 += pb;
-    if (__ballot(pb != 0.0)) {                  // wave-uniform; sparse weights
-      copy_chunk(a.L + c0 * B, n * B, my, lane);
+    uint64_t mask = __ballot(pb != 0.0);        // wave-uniform; sparse weights
+    if (mask) {
       cbuf[wid * kChunk + lane] = pb;
       wave_sync_lds();
+      const float* Lc = a.L + c0 * B;
       const int b0 = lane, b1 = lane + 64;
       const double o0 = b0 < B ? mu[b0] : 0.0;
       const double o1 = b1 < B ? mu[b1] : 0.0;
-      for (int p = 0; p < n; ++p) {
-        const double cp = cbuf[wid * kChunk + p];
-        if (cp != 0.0) {
-          if (b0 < B) m_lo = fma(cp, (double)my[p * B + b0] - o0, m_lo);
-          if (b1 < B) m_hi = fma(cp, (double)my[p * B + b1] - o1, m_hi);
+      while (mask) {                            // rows of four pixels in flight
+        int pi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          pi[u] = mask ? (int)__builtin_ctzll(mask) : -1;
+          mask &= mask - 1;
+        }
+        float l0[4], l1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool h = pi[u] >= 0;
+          l0[u] = (h && b0 < B) ? Lc[(int64_t)pi[u] * B + b0] : 0.f;
+          l1[u] = (h && b1 < B) ? Lc[(int64_t)pi[u] * B + b1] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (pi[u] >= 0) {
+            const double cp = cbuf[wid * kChunk + pi[u]];
+            m_lo = fma(cp, (double)l0[u] - o0, m_lo);
+            m_hi = fma(cp, (double)l1[u] - o1, m_hi);
+          }
         }
       }
       wave_sync_lds();
@@ -1577,9 +1597,9 @@ __global__ void __launch_bounds__(kSBlock) bwd_passA_kernel(BwArgs a) {
   }
   __syncthreads();
   double* out = a.partials + (int64_t)blockIdx.x * a.partial_stride;
-  for (int e = tid; e < kPad + 5; e += kSBlock) {
+  for (int e = tid; e < kPad + 5; e += kABlock) {
     double sum = 0.0;
-    for (int w = 0; w < kSW; ++w) sum += redm[w * (kPad + 8) + e];
+    for (int w = 0; w < kAW; ++w) sum += redm[w * (kPad + 8) + e];
     out[e] = sum;
   }
 }
@@ -2032,14 +2052,19 @@ __global__ void __launch_bounds__(256) bwd_assemble_kernel(BwAsmArgs a) {
   }
 }
 
-__global__ void bwd_sbar_kernel(const ColState* state, const double* bwcol, int n_cols, int B,
-                                double* grad_s) {
-  const int b = threadIdx.x;
-  if (b >= B) return;
+// grad_s[b] = sum over healthy columns of sbar (one workgroup per band).
+__global__ void __launch_bounds__(256) bwd_sbar_kernel(const ColState* state, const double* bwcol,
+                                                       int n_cols, double* grad_s) {
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  __shared__ double red[4];
   double s = 0.0;
-  for (int c = 0; c < n_cols; ++c)
+  for (int c = tid; c < n_cols; c += 256)
     if (state[c].status == MF_COL_OK) s += bwcol[(int64_t)c * kBw + kBwSbar + b];
-  grad_s[b] = s;
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) grad_s[b] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // Plain streaming read: the achievable HBM read bandwidth for this access
@@ -2570,7 +2595,7 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
     ba.u_k = ca.u_k = u_hist + (int64_t)k * p->n_cols * kPad;
     {
       LaunchTimer tm(p, MF_KERNEL_PASS_VEC, st);
-      hipLaunchKernelGGL(bwd_passA_kernel, dim3((unsigned)p->n_items), dim3(kSBlock), ldsA, st, ba);
+      hipLaunchKernelGGL(bwd_passA_kernel, dim3((unsigned)p->n_items), dim3(kABlock), ldsA, st, ba);
     }
     {
       LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
@@ -2607,8 +2632,8 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
   }
   {
     LaunchTimer tm(p, MF_KERNEL_OTHER, st);
-    hipLaunchKernelGGL(bwd_sbar_kernel, dim3(1), dim3(128), 0, st, state, bwcol, (int)p->n_cols, B,
-                       grad_s);
+    hipLaunchKernelGGL(bwd_sbar_kernel, dim3((unsigned)B), dim3(256), 0, st, state, bwcol,
+                       (int)p->n_cols, grad_s);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail_with(MF_E_DEVICE, std::string("backward launch: ") + hipGetErrorString(e));

@@ -98,7 +98,8 @@ struct PassArgs {
   float* alpha_final;        // alpha^K (j = K + 1), the caller's FP32 output
   double* partials;          // [item][T][16][16] FP64
   double* p_save;            // save_for_backward: p^{j-1} = (L - mu) . v per pixel (j >= 1)
-  double* r_save;            // save_for_backward: r per pixel (j = 1)
+  double* r_out;             // r per pixel written by this pass (low-rank form, j = 1)
+  const double* r_in;        // r per pixel from pass 1, or null: computed here
   int B;
   int j;
   int albedo;
@@ -491,10 +492,54 @@ constexpr int kSW = 2;                     // waves per stream workgroup
 constexpr int kSBlock = 64 * kSW;
 constexpr int kCopyGroup = 10;             // 16-byte loads in flight per lane while copying
 
-// Dynamic LDS bytes of stream_kernel for B bands (about 42 KB at 74 bands).
+// Synchronous copy of one chunk (contiguous in memory) into a wave's LDS tile.
+__device__ __forceinline__ void copy_chunk(const float* g, int nfl, float* my, int lane) {
+  const uintptr_t ga = reinterpret_cast<uintptr_t>(g);
+  if ((ga & 15) == 0 && (nfl & 3) == 0) {
+    const float4* g4 = reinterpret_cast<const float4*>(g);
+    float4* t4 = reinterpret_cast<float4*>(my);
+    const int n4 = nfl / 4;
+    for (int base = 0; base < n4; base += 64 * kCopyGroup) {
+      float4 r[kCopyGroup];
+#pragma unroll
+      for (int q = 0; q < kCopyGroup; ++q) {
+        const int e = base + lane + 64 * q;
+        r[q] = e < n4 ? g4[e] : float4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int q = 0; q < kCopyGroup; ++q) {
+        const int e = base + lane + 64 * q;
+        if (e < n4) t4[e] = r[q];
+      }
+    }
+  } else if ((ga & 7) == 0 && (nfl & 1) == 0) {
+    const float2* g2 = reinterpret_cast<const float2*>(g);
+    float2* t2 = reinterpret_cast<float2*>(my);
+    const int n2 = nfl / 2;
+    for (int e = lane; e < n2; e += 64) t2[e] = g2[e];
+  } else {
+    for (int e = lane; e < nfl; e += 64) my[e] = g[e];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A wave's radiance tile: kF4 16-byte groups per lane (a whole chunk of up to
+// 80 bands), so the fast path writes it without bounds tests.
+constexpr int kF4 = (kChunk * 80 / 4 + 63) / 64;     // 20
+constexpr int kTileF = kF4 * 64 * 4;                  // floats per wave tile
+
+// Dynamic LDS bytes of stream_kernel (about 45 KB).
 __host__ __device__ constexpr size_t stream_lds_bytes(int B) {
-  return (size_t)kSW * kChunk * B * sizeof(float) + kSW * kChunk * sizeof(double) +
-         kSW * (kPad + 2) * sizeof(double) + 4 * kPad * sizeof(double);
+  return (size_t)kSW * kChunk * sizeof(double) + kSW * (kPad + 2) * sizeof(double) +
+         4 * kPad * sizeof(double) + (size_t)kSW * kTileF * sizeof(float);
 }
 
 template <int MODE>
@@ -508,8 +553,30 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
   extern __shared__ double dyn[];
   double* cbuf = dyn;                                   // [kSW][kChunk]
   double* redm = cbuf + kSW * kChunk;                   // [kSW][kPad + 2]
-  double* cst = redm + kSW * (kPad + 2);                // [kPad][4]: mu, v, m0, lbar
-  float* my = reinterpret_cast<float*>(cst + 4 * kPad) + wid * kChunk * B;   // [kChunk][B]
+  double* cst = redm + kSW * (kPad + 2);                // [kPad] v, m0, lbar; mu . v
+  float* my = reinterpret_cast<float*>(cst + 4 * kPad) + wid * kTileF;   // [kChunk][B]
+
+  const int64_t step = (int64_t)kSW * kChunk;
+  int64_t c0 = begin + (int64_t)kChunk * wid;
+  const uintptr_t lp = reinterpret_cast<uintptr_t>(a.L);
+  const bool aligned = ((lp + (uintptr_t)(begin * B) * 4) & 15) == 0;
+  const bool fast = aligned && c0 + kChunk <= end;
+  const int n4 = kChunk * B / 4;
+
+  // The first chunk is requested before the column state: its loads do not
+  // depend on it, and the two latencies overlap.
+  float4 pre[kF4];
+  uint32_t vld_n = 1;
+  double ap_n = 0.0, rp_n = 0.0;
+  if (fast) {
+    vld_n = a.valid ? (uint32_t)a.valid[c0 + lane] : 1u;
+    ap_n = a.alpha_prev ? a.alpha_prev[c0 + lane] : 0.0;
+    rp_n = a.r_in ? a.r_in[c0 + lane] : 0.0;
+    const float4* g4 = reinterpret_cast<const float4*>(a.L + c0 * B);
+#pragma unroll
+    for (int k = 0; k < kF4; ++k)
+      pre[k] = (lane + 64 * k < n4) ? g4[lane + 64 * k] : float4{0.f, 0.f, 0.f, 0.f};
+  }
 
   if (st->status != MF_COL_OK) {           // failed column: alpha = 0, no moments
     for (int64_t px = begin + tid; px < end; px += kSBlock) {
@@ -519,116 +586,81 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
     return;
   }
   for (int b = tid; b < kPad; b += kSBlock) {
-    cst[4 * b + 0] = st->mu[b];
-    cst[4 * b + 1] = st->v[b];
-    cst[4 * b + 2] = st->m0[b];
-    cst[4 * b + 3] = st->lbar[b];
+    cst[b] = st->v[b];
+    cst[kPad + b] = st->m0[b];
+    cst[2 * kPad + b] = st->lbar[b];
+  }
+  if (wid == 0) {          // mu . v (fixed summation order); p = L . v - mu . v
+    double d = 0.0;
+    if (lane < B) d = st->mu[lane] * st->v[lane];
+    if (lane + 64 < B) d = fma(st->mu[lane + 64], st->v[lane + 64], d);
+    for (int off = 32; off >= 1; off >>= 1) d += __shfl_xor(d, off, 64);
+    if (lane == 0) cst[3 * kPad] = d;
   }
   __syncthreads();
+  const double muv = cst[3 * kPad];
   const double q = st->q;
   const double lam = a.lam, eps = a.eps;
   const int j = a.j;
-  const uintptr_t lp = reinterpret_cast<uintptr_t>(a.L);
 
   [[maybe_unused]] double m_lo = 0.0, m_hi = 0.0, s1 = 0.0, s2 = 0.0;
 
-  // Whole chunks whose bytes start on a 16-byte boundary are streamed with
-  // 16-byte loads, one chunk ahead in registers; other chunks are copied
-  // synchronously with 8- or 4-byte loads (never past the chunk).
-  constexpr int kF4 = (kChunk * 78 / 4 + 63) / 64;     // float4 per lane per chunk (20)
-  float4 pre[kF4];
-  auto fast = [&](int64_t c) {          // a whole, 16-byte aligned chunk
-    return c + kChunk <= end && ((lp + (uintptr_t)(c * B) * 4) & 15) == 0;
-  };
-  auto prefetch = [&](int64_t c) {
-    const float4* g4 = reinterpret_cast<const float4*>(a.L + c * B);
-    const int n4 = kChunk * B / 4;
-#pragma unroll
-    for (int k = 0; k < kF4; ++k) {
-      const int e = lane + 64 * k;
-      pre[k] = e < n4 ? g4[e] : float4{0.f, 0.f, 0.f, 0.f};
-    }
-  };
-  int64_t c0 = begin + (int64_t)kChunk * wid;
-  bool have = c0 < end && fast(c0);
-  if (have) prefetch(c0);
-
-  for (; c0 < end; c0 += kSW * kChunk) {
-    const int n = (int)min<int64_t>(kChunk, end - c0);
-    const int nfl = n * B;
-    const float* g = a.L + c0 * B;
-    if (have) {
-      float4* t4 = reinterpret_cast<float4*>(my);
-      const int n4 = kChunk * B / 4;
-#pragma unroll
-      for (int k = 0; k < kF4; ++k) {
-        const int e = lane + 64 * k;
-        if (e < n4) t4[e] = pre[k];
-      }
-    } else {
-      const uintptr_t ga = lp + (uintptr_t)(c0 * B) * 4;
-      if ((ga & 7) == 0 && (nfl & 1) == 0) {
-        const float2* g2 = reinterpret_cast<const float2*>(g);
-        float2* t2 = reinterpret_cast<float2*>(my);
-        const int n2 = nfl / 2;
-        for (int base = 0; base < n2; base += 64 * kCopyGroup) {
-          float2 r[kCopyGroup];
-#pragma unroll
-          for (int k = 0; k < kCopyGroup; ++k) {
-            const int e = base + lane + 64 * k;
-            r[k] = e < n2 ? g2[e] : float2{0.f, 0.f};
-          }
-#pragma unroll
-          for (int k = 0; k < kCopyGroup; ++k) {
-            const int e = base + lane + 64 * k;
-            if (e < n2) t2[e] = r[k];
-          }
-        }
-      } else {
-        for (int e = lane; e < nfl; e += 64) my[e] = g[e];
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    {
-      const int64_t nx = c0 + kSW * kChunk;
-      have = nx < end && fast(nx);
-      if (have) prefetch(nx);                 // in flight while this chunk is scored
-    }
-
-    // score this lane's pixel
+  // Scores the chunk at c0 (n pixels, tile in LDS): alpha^{j-1}, and for the
+  // low-rank form the moment contributions of the pixels with c != 0.
+  // r = L . m0 does not change between iterations: the low-rank form computes
+  // it in pass 1 and later passes read it (r_in), so their band loop reads
+  // only v.  p = L . v - mu . v, with even and odd bands on two FMA chains.
+  const bool own_r = a.r_in == nullptr;
+  auto score = [&](int64_t c0, int n, uint32_t vld, double ap, double rp) {
     const int64_t px = c0 + lane;
     const bool inb = lane < n;
-    bool ok = inb;
-    if (inb && a.valid) ok = a.valid[px] != 0;
-    const double ap = (inb && a.alpha_prev) ? a.alpha_prev[px] : 0.0;
+    const bool ok = inb && vld != 0;
     double pp = 0.0, rr = 0.0;
     if (ok) {
       const float* rowp = my + lane * B;
+      const double2* v2 = reinterpret_cast<const double2*>(cst);
+      const double2* m2 = reinterpret_cast<const double2*>(cst + kPad);
+      double pe = 0.0, po = 0.0;
       int b = 0;
-      if ((B & 1) == 0) {                     // pairs of bands: 8-byte tile reads
+      if (own_r) {
+        double re = 0.0, ro = 0.0;
+        if ((B & 1) == 0) {                   // pairs of bands: 8-byte tile reads
 #pragma unroll 4
-        for (; b < B; b += 2) {
-          const float2 l2 = *reinterpret_cast<const float2*>(rowp + b);
-          const double4 c0v = *reinterpret_cast<const double4*>(cst + 4 * b);
-          const double4 c1v = *reinterpret_cast<const double4*>(cst + 4 * b + 4);
-          const double l0 = (double)l2.x, l1 = (double)l2.y;
-          pp = fma(l0 - c0v.x, c0v.y, pp);
-          rr = fma(l0, c0v.z, rr);
-          pp = fma(l1 - c1v.x, c1v.y, pp);
-          rr = fma(l1, c1v.z, rr);
+          for (; b < B; b += 2) {
+            const float2 l2 = *reinterpret_cast<const float2*>(rowp + b);
+            const double2 cv = v2[b >> 1], cm = m2[b >> 1];
+            const double l0 = (double)l2.x, l1 = (double)l2.y;
+            pe = fma(l0, cv.x, pe);
+            re = fma(l0, cm.x, re);
+            po = fma(l1, cv.y, po);
+            ro = fma(l1, cm.y, ro);
+          }
         }
+        for (; b < B; ++b) {
+          const double l = (double)rowp[b];
+          pe = fma(l, cst[b], pe);
+          re = fma(l, cst[kPad + b], re);
+        }
+        rr = re + ro;
+      } else {
+        if ((B & 1) == 0) {
+          double2 cv = v2[0];
+#pragma unroll 4
+          for (; b < B; b += 2) {
+            const double2 nv = v2[(b >> 1) + 1];   // next pair, in flight (kPad > B)
+            const float2 l2 = *reinterpret_cast<const float2*>(rowp + b);
+            pe = fma((double)l2.x, cv.x, pe);
+            po = fma((double)l2.y, cv.y, po);
+            cv = nv;
+          }
+        }
+        for (; b < B; ++b) pe = fma((double)rowp[b], cst[b], pe);
       }
-      for (; b < B; ++b) {
-        const double l = (double)rowp[b];
-        pp = fma(l - cst[4 * b], cst[4 * b + 1], pp);
-        rr = fma(l, cst[4 * b + 2], rr);
-      }
+      pp = (pe + po) - muv;
     }
     double c = 0.0;
     if (j >= 1) {
-      const double r = a.albedo ? rr : 1.0;
+      const double r = own_r ? (a.albedo ? rr : 1.0) : rp;
       const double num = (j == 1) ? pp : pp - lam / (ap + eps);
       double al = num / (r * q);
       const bool dark = !(r > 0.0);
@@ -638,7 +670,7 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
         if (a.alpha_out) a.alpha_out[px] = al;
         if (a.alpha_final) a.alpha_final[px] = (float)al;
         if (a.p_save) a.p_save[px] = ok ? pp : 0.0;
-        if (a.r_save) a.r_save[px] = ok ? r : 0.0;
+        if (a.r_out) a.r_out[px] = ok ? r : 0.0;
       }
       c = (ok && !dark && al > 0.0) ? r * al : 0.0;
     }
@@ -647,12 +679,10 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
       s2 = fma(c, c, s2);
       if (__ballot(c != 0.0)) {                 // wave-uniform
         cbuf[wid * kChunk + lane] = c;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync_lds();
         const int b0 = lane, b1 = lane + 64;
-        const double lb0 = b0 < B ? cst[4 * b0 + 3] : 0.0;
-        const double lb1 = b1 < B ? cst[4 * b1 + 3] : 0.0;
+        const double lb0 = b0 < B ? cst[2 * kPad + b0] : 0.0;
+        const double lb1 = b1 < B ? cst[2 * kPad + b1] : 0.0;
         for (int p = 0; p < n; ++p) {
           const double cp = cbuf[wid * kChunk + p];
           if (cp != 0.0) {                      // wave-uniform; skips invalid pixels too
@@ -663,9 +693,51 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
       }
     }
     // the tile is rewritten by this wave only after every lane is done with it
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync_lds();
+  };
+
+  // Fast path over whole chunks of a 16-byte aligned work item: each chunk is
+  // loaded one chunk ahead, 16 bytes per load, into registers.  The loads of a
+  // chunk's per-pixel inputs (valid flag, alpha^{j-2}) are issued before its
+  // tile: vector loads retire in order, so waiting for them never waits for
+  // the tile in flight.  When there is no next chunk the loads repeat one
+  // line of the current chunk, so the loop body has no branch around a load.
+  if (fast) {
+    while (true) {
+      const uint32_t vld = vld_n;
+      const double ap = ap_n, rp = rp_n;
+      float4* t4 = reinterpret_cast<float4*>(my);
+#pragma unroll
+      for (int k = 0; k < kF4; ++k) t4[lane + 64 * k] = pre[k];
+      wave_sync_lds();
+      const int64_t nx = c0 + step;
+      const bool more = nx + kChunk <= end;
+      {                                       // in flight while this chunk is scored
+        const int64_t cn = more ? nx : c0;
+        const int64_t pn = cn + (more ? lane : 0);
+        vld_n = a.valid ? (uint32_t)a.valid[pn] : 1u;
+        ap_n = a.alpha_prev ? a.alpha_prev[pn] : 0.0;
+        rp_n = a.r_in ? a.r_in[pn] : 0.0;
+        const float4* g4 = reinterpret_cast<const float4*>(a.L + cn * B);
+#pragma unroll
+        for (int k = 0; k < kF4; ++k) pre[k] = (lane + 64 * k < n4) ? g4[more ? lane + 64 * k : 0] : float4{0.f, 0.f, 0.f, 0.f};
+      }
+      score(c0, kChunk, vld, ap, rp);
+      c0 = nx;
+      if (!more) break;
+    }
+  }
+  // the rest (a ragged last chunk, or an item that is not 16-byte aligned):
+  // synchronous copies
+  for (; c0 < end; c0 += step) {
+    const int n = (int)min<int64_t>(kChunk, end - c0);
+    const int64_t px = c0 + lane;
+    const bool inb = lane < n;
+    const uint32_t vld = (inb && a.valid) ? (uint32_t)a.valid[px] : 1u;
+    const double ap = (inb && a.alpha_prev) ? a.alpha_prev[px] : 0.0;
+    const double rp = (inb && a.r_in) ? a.r_in[px] : 0.0;
+    copy_chunk(a.L + c0 * B, n * B, my, lane);
+    score(c0, n, vld, ap, rp);
   }
 
   if constexpr (MODE == PM_VEC) {
@@ -1441,45 +1513,6 @@ struct BwArgs {
   int albedo;
 };
 
-// Synchronous copy of one chunk (contiguous in memory) into a wave's LDS tile.
-__device__ __forceinline__ void copy_chunk(const float* g, int nfl, float* my, int lane) {
-  const uintptr_t ga = reinterpret_cast<uintptr_t>(g);
-  if ((ga & 15) == 0 && (nfl & 3) == 0) {
-    const float4* g4 = reinterpret_cast<const float4*>(g);
-    float4* t4 = reinterpret_cast<float4*>(my);
-    const int n4 = nfl / 4;
-    for (int base = 0; base < n4; base += 64 * kCopyGroup) {
-      float4 r[kCopyGroup];
-#pragma unroll
-      for (int q = 0; q < kCopyGroup; ++q) {
-        const int e = base + lane + 64 * q;
-        r[q] = e < n4 ? g4[e] : float4{0.f, 0.f, 0.f, 0.f};
-      }
-#pragma unroll
-      for (int q = 0; q < kCopyGroup; ++q) {
-        const int e = base + lane + 64 * q;
-        if (e < n4) t4[e] = r[q];
-      }
-    }
-  } else if ((ga & 7) == 0 && (nfl & 1) == 0) {
-    const float2* g2 = reinterpret_cast<const float2*>(g);
-    float2* t2 = reinterpret_cast<float2*>(my);
-    const int n2 = nfl / 2;
-    for (int e = lane; e < n2; e += 64) t2[e] = g2[e];
-  } else {
-    for (int e = lane; e < nfl; e += 64) my[e] = g[e];
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Pass A is light per pixel: eight waves per work item keep enough loads in flight.
 constexpr int kAW = 8;
 constexpr int kABlock = 64 * kAW;
@@ -2132,7 +2165,7 @@ struct mf_plan_s {
   WorkItem* items_d = nullptr;
   size_t off_state = 0, off_partials = 0, off_c0 = 0, off_pinv = 0, off_alpha0 = 0, off_alpha1 = 0;
   // save_for_backward: checkpoints and adjoint buffers
-  size_t off_ck_alpha = 0, off_ck_col = 0, off_ck_p = 0, off_bw_px = 0, off_bw_coef = 0, off_bw_u = 0,
+  size_t off_r = 0, off_ck_alpha = 0, off_ck_col = 0, off_ck_p = 0, off_bw_px = 0, off_bw_coef = 0, off_bw_u = 0,
          off_bw_col = 0;
   size_t ws_bytes = 0;
 };
@@ -2286,7 +2319,10 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
     }
     pa.alpha_final = j == K + 1 ? alpha : nullptr;
     pa.p_save = (ck_p && j >= 1) ? ck_p + (int64_t)(j - 1) * p->max_px : nullptr;
-    pa.r_save = (ck_p && j == 1) ? ck_p + (int64_t)(K + 1) * p->max_px : nullptr;
+    const bool lowrank = p->opt.cov == MF_COV_LOWRANK;
+    double* rbuf = (double*)(ws + p->off_r);
+    pa.r_out = (lowrank && j == 1) ? rbuf : nullptr;
+    pa.r_in = (lowrank && j >= 2) ? rbuf : nullptr;
     const bool mom = j <= K;
     const int mode = pass_mode(p->opt.cov, j, K);
     {
@@ -2449,14 +2485,16 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   off = align256(off + (size_t)max_px * sizeof(double));
   p->off_alpha1 = off;
   off = align256(off + (size_t)max_px * sizeof(double));
+  p->off_r = off;                              // r per pixel (low-rank form)
+  if (opt->cov == MF_COV_LOWRANK) off = align256(off + (size_t)max_px * sizeof(double));
   if (opt->save_for_backward) {
     const size_t K1 = (size_t)opt->n_iter + 1;
     p->off_ck_alpha = off;
     off = align256(off + K1 * (size_t)max_px * sizeof(double));
     p->off_ck_col = off;
     off = align256(off + K1 * (size_t)p->n_cols * kCk * sizeof(double));
-    p->off_ck_p = off;                       // p^0..p^K, then r
-    off = align256(off + (K1 + 1) * (size_t)max_px * sizeof(double));
+    p->off_ck_p = off;                       // p^0..p^K
+    off = align256(off + K1 * (size_t)max_px * sizeof(double));
     p->off_bw_px = off;
     off = align256(off + 3 * (size_t)max_px * sizeof(double));
     p->off_bw_coef = off;
@@ -2558,7 +2596,7 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
   ba.items = p->items_d;
   ba.state = state;
   ba.grad_alpha = grad_alpha;
-  ba.r_px = ck_p + (int64_t)(K + 1) * mp;
+  ba.r_px = (double*)(ws + p->off_r);
   ba.abar = bwpx;
   ba.rbar = bwpx + mp;
   ba.pbar = bwpx + 2 * mp;

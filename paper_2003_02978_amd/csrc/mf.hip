@@ -531,6 +531,19 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// 16-byte loads through a buffer resource that covers [p, p + bytes): lanes
+// past the end read zeros (raw buffer range check), so a partial last group
+// needs neither a branch nor a select.
+constexpr int kBufWord3 = 0x00020000;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const float* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, bytes, kBufWord3);
+}
+__device__ __forceinline__ float4 load16(__amdgpu_buffer_rsrc_t rs, int off) {
+  typedef int intx4 __attribute__((ext_vector_type(4)));
+  const intx4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+  return float4{__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z), __int_as_float(v.w)};
+}
+
 // A wave's radiance tile: kF4 16-byte groups per lane (a whole chunk of up to
 // 80 bands), so the fast path writes it without bounds tests.
 constexpr int kF4 = (kChunk * 80 / 4 + 63) / 64;     // 20
@@ -547,7 +560,8 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
   const WorkItem it = a.items[blockIdx.x];
   const ColState* __restrict__ st = a.state + it.col;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wid = tid >> 6;
+  const int lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
   const int B = a.B;
   const int64_t begin = it.px_begin, end = begin + it.n_px;
   extern __shared__ double dyn[];
@@ -572,10 +586,9 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
     vld_n = a.valid ? (uint32_t)a.valid[c0 + lane] : 1u;
     ap_n = a.alpha_prev ? a.alpha_prev[c0 + lane] : 0.0;
     rp_n = a.r_in ? a.r_in[c0 + lane] : 0.0;
-    const float4* g4 = reinterpret_cast<const float4*>(a.L + c0 * B);
+    const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(a.L + c0 * B, n4 * 16);
 #pragma unroll
-    for (int k = 0; k < kF4; ++k)
-      pre[k] = (lane + 64 * k < n4) ? g4[lane + 64 * k] : float4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < kF4; ++k) pre[k] = load16(rs, (lane + 64 * k) * 16);
   }
 
   if (st->status != MF_COL_OK) {           // failed column: alpha = 0, no moments
@@ -700,8 +713,8 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
   // loaded one chunk ahead, 16 bytes per load, into registers.  The loads of a
   // chunk's per-pixel inputs (valid flag, alpha^{j-2}) are issued before its
   // tile: vector loads retire in order, so waiting for them never waits for
-  // the tile in flight.  When there is no next chunk the loads repeat one
-  // line of the current chunk, so the loop body has no branch around a load.
+  // the tile in flight.  When there is no next chunk the resource covers 16
+  // bytes of the current chunk, so the loop body has no branch around a load.
   if (fast) {
     while (true) {
       const uint32_t vld = vld_n;
@@ -718,9 +731,9 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
         vld_n = a.valid ? (uint32_t)a.valid[pn] : 1u;
         ap_n = a.alpha_prev ? a.alpha_prev[pn] : 0.0;
         rp_n = a.r_in ? a.r_in[pn] : 0.0;
-        const float4* g4 = reinterpret_cast<const float4*>(a.L + cn * B);
+        const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(a.L + cn * B, more ? n4 * 16 : 16);
 #pragma unroll
-        for (int k = 0; k < kF4; ++k) pre[k] = (lane + 64 * k < n4) ? g4[more ? lane + 64 * k : 0] : float4{0.f, 0.f, 0.f, 0.f};
+        for (int k = 0; k < kF4; ++k) pre[k] = load16(rs, (lane + 64 * k) * 16);
       }
       score(c0, kChunk, vld, ap, rp);
       c0 = nx;

@@ -1276,44 +1276,54 @@ __device__ void r3_prepare(const double (&Pb)[kBlk][kBlk], bool owner, int bi, i
   block_symv<3>(Pb, owner, bi, bj, tid, B, sm.U3, sm.X3, sm.prow, sm.pcol);
   if (wid == 0) {
     double W[9];
+#pragma unroll
     for (int r = 0; r < 3; ++r)
+#pragma unroll
       for (int c = 0; c < 3; ++c) W[r * 3 + c] = wave_dot(sm.U3 + r * kPad, sm.X3 + c * kPad, B, lane);
     if (lane == 0) {
-      double M[9], I3[9];
+      // Gauss-Jordan with partial pivoting on [M | I]; rows are exchanged by
+      // selects, so every index is a compile-time constant (registers only)
+      double A[3][6];
+#pragma unroll
       for (int r = 0; r < 3; ++r)
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
           double s = (r == c) ? 1.0 : 0.0;
+#pragma unroll
           for (int k = 0; k < 3; ++k) s += sm.S3[r * 3 + k] * W[k * 3 + c];
-          M[r * 3 + c] = s;
-          I3[r * 3 + c] = (r == c) ? 1.0 : 0.0;
+          A[r][c] = s;
+          A[r][3 + c] = (r == c) ? 1.0 : 0.0;
         }
+      bool ok = true;
+#pragma unroll
       for (int k = 0; k < 3; ++k) {
-        int piv = k;
-        for (int r = k + 1; r < 3; ++r)
-          if (fabs(M[r * 3 + k]) > fabs(M[piv * 3 + k])) piv = r;
-        if (!(fabs(M[piv * 3 + k]) > 0.0)) {
-          sm.bad = 1;
-          break;
-        }
-        for (int c = 0; c < 3; ++c) {
-          double t0 = M[k * 3 + c]; M[k * 3 + c] = M[piv * 3 + c]; M[piv * 3 + c] = t0;
-          t0 = I3[k * 3 + c]; I3[k * 3 + c] = I3[piv * 3 + c]; I3[piv * 3 + c] = t0;
-        }
-        const double inv = 1.0 / M[k * 3 + k];
-        for (int c = 0; c < 3; ++c) {
-          M[k * 3 + c] *= inv;
-          I3[k * 3 + c] *= inv;
-        }
-        for (int r = 0; r < 3; ++r) {
-          if (r == k) continue;
-          const double f = M[r * 3 + k];
-          for (int c = 0; c < 3; ++c) {
-            M[r * 3 + c] -= f * M[k * 3 + c];
-            I3[r * 3 + c] -= f * I3[k * 3 + c];
+#pragma unroll
+        for (int r = k + 1; r < 3; ++r) {
+          const bool sw = fabs(A[r][k]) > fabs(A[k][k]);
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            const double x = A[k][c], y = A[r][c];
+            A[k][c] = sw ? y : x;
+            A[r][c] = sw ? x : y;
           }
         }
+        ok = ok && fabs(A[k][k]) > 0.0;
+        const double inv = 1.0 / A[k][k];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) A[k][c] *= inv;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          if (r == k) continue;
+          const double f = A[r][k];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) A[r][c] -= f * A[k][c];
+        }
       }
-      for (int e = 0; e < 9; ++e) sm.Ginv[e] = I3[e];
+      if (!ok) sm.bad = 1;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sm.Ginv[r * 3 + c] = A[r][3 + c];
     }
   }
   __syncthreads();
@@ -1409,12 +1419,15 @@ __global__ void __launch_bounds__(kBlock) lowrank_kernel(SolveArgs a) {
   double Cb[kBlk][kBlk], Pb[kBlk][kBlk];
   load_blocks(a.c0 + (int64_t)col * (kNBlk * 16), a.pinv + (int64_t)col * (kNBlk * 16), owner, tid,
               Cb, Pb);
+  // the column's moments: m (kPad), S1, S2 summed over its work items
+  for (int e = tid; e < kPad + 2; e += kBlock) {
+    double acc = 0.0;
+    for (int it = 0; it < ci.n_items; ++it) acc += P[it * stride + e];
+    sm.X3[e] = acc;                              // scratch until r3_prepare
+  }
+  __syncthreads();
   if (tid == 0) {
-    double s1 = 0.0, s2 = 0.0;
-    for (int it = 0; it < ci.n_items; ++it) {
-      s1 += P[it * stride + kVecS1];
-      s2 += P[it * stride + kVecS2];
-    }
+    const double s1 = sm.X3[kVecS1], s2 = sm.X3[kVecS2];
     sc[0] = st.n_valid;
     sc[1] = s1;
     sc[2] = s2;
@@ -1426,7 +1439,7 @@ __global__ void __launch_bounds__(kBlock) lowrank_kernel(SolveArgs a) {
   for (int b = tid; b < kPad; b += kBlock) {
     double m = 0.0, mu = 0.0, t = 0.0, d = 0.0;
     if (b < B) {
-      for (int it = 0; it < ci.n_items; ++it) m += P[it * stride + b];
+      m = sm.X3[b];
       mu = st.lbar[b] - abar * st.t[b];          // Eq. 10
       t = mu * (double)a.s[b];                   // Eq. 9
       d = st.t[b] - t;
@@ -1869,14 +1882,16 @@ __global__ void __launch_bounds__(kBlock) bwd_colA_kernel(BwColArgs a) {
   load_blocks(a.c0 + (int64_t)col * (kNBlk * 16), a.pinv + (int64_t)col * (kNBlk * 16), owner, tid,
               Cb, Pb);
   const double q = ck[kCkScal + 2], N = ck[kCkScal + 3];
+  // pass A sums over the column's work items: V (kPad), Q1, P1
+  for (int e = tid; e < kPad + 2; e += kBlock) {
+    double acc = 0.0;
+    for (int it = 0; it < ci.n_items; ++it) acc += P[it * stride + e];
+    sm.X3[e] = acc;                              // scratch until r3_prepare
+  }
+  __syncthreads();
   if (tid == 0) {
-    double q1 = 0.0, p1 = 0.0;
-    for (int it = 0; it < ci.n_items; ++it) {
-      q1 += P[it * stride + kBwQ1];
-      p1 += P[it * stride + kBwP1];
-    }
-    sc[0] = q1;
-    sc[1] = p1;
+    sc[0] = sm.X3[kBwQ1];
+    sc[1] = sm.X3[kBwP1];
     if (k >= 1) rank3_S(sm.S3, ck[kCkScal + 0], ck[kCkScal + 1], N);
     else
       for (int e = 0; e < 9; ++e) sm.S3[e] = 0.0;
@@ -1885,9 +1900,7 @@ __global__ void __launch_bounds__(kBlock) bwd_colA_kernel(BwColArgs a) {
   const double qbar = -sc[0] / q, P1 = sc[1];
   const double* ckm1 = k >= 1 ? a.ck_km1 + (int64_t)col * kCk : nullptr;
   for (int b = tid; b < kPad; b += kBlock) {
-    double V = 0.0;
-    if (b < B)
-      for (int it = 0; it < ci.n_items; ++it) V += P[it * stride + b];
+    const double V = b < B ? sm.X3[b] : 0.0;
     const double t = ck[kCkT + b];
     vbar[b] = b < B ? V + qbar * t : 0.0;
     sm.U3[b] = (k >= 1 && b < B) ? ckm1[kCkT + b] - t : 0.0;

@@ -849,6 +849,10 @@ __device__ void wave_chol_solve(const double* __restrict__ Lf, double invd_lo, d
 constexpr int kBlk = 4;
 constexpr int kNBlkRows = kPad / kBlk;                            // 20
 constexpr int kNBlk = kNBlkRows * (kNBlkRows + 1) / 2;            // 210
+// Per-column C^0 and P = (C^0)^-1 in HBM: 16 doubles per 4x4 block, stored
+// element-major (element e of every block contiguous), so the owner threads
+// of a workgroup read and write them with coalesced accesses.
+__device__ __forceinline__ int blk_at(int blk, int x, int y) { return (x * kBlk + y) * kNBlk + blk; }
 
 // Dot product of two LDS vectors (length B) on one wave; every lane gets it.
 __device__ __forceinline__ double wave_dot(const double* x, const double* y, int B, int lane) {
@@ -1009,7 +1013,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
       double c = (i == jj) ? 1.0 : 0.0;        // padding keeps the factor regular
       if (owner && i < B && jj < B && i >= jj) {
         if (rank3) {
-          c = c0[tid * 16 + x * kBlk + y] + abar * abar * D[i] * D[jj] +
+          c = c0[blk_at(tid, x, y)] + abar * abar * D[i] * D[jj] +
               (S2 / N - abar * abar) * tn[i] * tn[jj] - (g1[i] * tn[jj] + tn[i] * g1[jj]) / N;
         } else {
           c = gram_elem<NB, WIDE>(P, ci.n_items, i, jj);
@@ -1028,7 +1032,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
 #pragma unroll
     for (int x = 0; x < kBlk; ++x)
 #pragma unroll
-      for (int y = 0; y < kBlk; ++y) c0[tid * 16 + x * kBlk + y] = A_[x][y];
+      for (int y = 0; y < kBlk; ++y) c0[blk_at(tid, x, y)] = A_[x][y];
   }
   if (myfail) fail = 1;
   __syncthreads();
@@ -1099,7 +1103,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
 #pragma unroll
       for (int x = 0; x < kBlk; ++x)
 #pragma unroll
-        for (int y = 0; y < kBlk; ++y) pinv[tid * 16 + x * kBlk + y] = A_[x][y];
+        for (int y = 0; y < kBlk; ++y) pinv[blk_at(tid, x, y)] = A_[x][y];
     }
     for (int b = tid; b < kPad; b += kBlock) rbuf[b] = b < B ? tn[b] : 0.0;
     __syncthreads();
@@ -1329,11 +1333,18 @@ __device__ void r3_prepare(const double (&Pb)[kBlk][kBlk], bool owner, int bi, i
   __syncthreads();
 }
 
-// sm.vbuf = C^-1 b (b: LDS vector, zero beyond B), with `refine` refinement steps.
+// sm.vbuf = C^-1 b (b: LDS vector, zero beyond B), with `refine` refinement
+// steps.  pb, if not null, already holds P b (an LDS vector).
 __device__ void r3_solve(const double (&Pb)[kBlk][kBlk], const double (&Cb)[kBlk][kBlk], bool owner,
-                         int bi, int bj, int tid, int B, int refine, const double* b, R3Smem& sm) {
+                         int bi, int bj, int tid, int B, int refine, const double* b, R3Smem& sm,
+                         const double* pb = nullptr) {
   const int lane = tid & 63, wid = tid >> 6;
-  block_symv<1>(Pb, owner, bi, bj, tid, B, b, sm.wbuf, sm.prow, sm.pcol);   // y = P b
+  if (pb) {
+    for (int e = tid; e < kPad; e += kBlock) sm.wbuf[e] = pb[e];
+    __syncthreads();
+  } else {
+    block_symv<1>(Pb, owner, bi, bj, tid, B, b, sm.wbuf, sm.prow, sm.pcol);   // y = P b
+  }
   for (int step = 0; step <= refine; ++step) {
     if (wid == 0) {
       double u[3];
@@ -1382,8 +1393,8 @@ __device__ void load_blocks(const double* c0, const double* pinv, bool owner, in
   for (int x = 0; x < kBlk; ++x)
 #pragma unroll
     for (int y = 0; y < kBlk; ++y) {
-      Cb[x][y] = owner ? c0[tid * 16 + x * kBlk + y] : 0.0;
-      Pb[x][y] = owner ? pinv[tid * 16 + x * kBlk + y] : 0.0;
+      Cb[x][y] = owner ? c0[blk_at(tid, x, y)] : 0.0;
+      Pb[x][y] = owner ? pinv[blk_at(tid, x, y)] : 0.0;
     }
 }
 
@@ -1455,7 +1466,8 @@ __global__ void __launch_bounds__(kBlock) lowrank_kernel(SolveArgs a) {
     if (tid == 0) st.status = MF_COL_NOT_SPD;
     return;
   }
-  r3_solve(Pb, Cb, owner, bi, bj, tid, B, a.refine, sm.U3 + kPad, sm);
+  // b = t^j is the second column of U, so P b is the second column of X = P U
+  r3_solve(Pb, Cb, owner, bi, bj, tid, B, a.refine, sm.U3 + kPad, sm, sm.X3 + kPad);
   if (wid == 0) {
     const double q = wave_dot(sm.U3 + kPad, sm.vbuf, B, lane);
     if (lane == 0) {

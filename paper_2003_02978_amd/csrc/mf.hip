@@ -98,6 +98,7 @@ struct PassArgs {
   float* alpha_final;        // alpha^K (j = K + 1), the caller's FP32 output
   double* partials;          // [item][T][16][16] FP64
   double* p_save;            // save_for_backward: p^{j-1} = (L - mu) . v per pixel (j >= 1)
+  int64_t n_floats;          // floats of the radiance array (max_px * B)
   double* r_out;             // r per pixel written by this pass (low-rank form, j = 1)
   const double* r_in;        // r per pixel from pass 1, or null: computed here
   int B;
@@ -572,21 +573,30 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
 
   const int64_t step = (int64_t)kSW * kChunk;
   int64_t c0 = begin + (int64_t)kChunk * wid;
-  const uintptr_t lp = reinterpret_cast<uintptr_t>(a.L);
-  const bool aligned = ((lp + (uintptr_t)(begin * B) * 4) & 15) == 0;
-  const bool fast = aligned && c0 + kChunk <= end;
-  const int n4 = kChunk * B / 4;
+  // A chunk is loaded from the 16-byte boundary at or below its first float,
+  // so its tile starts `shift` floats into the LDS buffer; shift is the same
+  // for every chunk of this wave (a chunk step is a multiple of 4 floats).
+  // The loaded span, rounded out to 16 bytes, must lie inside the radiance
+  // array: true for every chunk but possibly the first and last ones of the
+  // array, which are copied synchronously.
+  const int shift = (int)((reinterpret_cast<uintptr_t>(a.L + c0 * B) & 15) >> 2);
+  const int n4 = (shift + kChunk * B + 3) / 4;        // 16-byte groups per chunk span
+  auto span_ok = [&](int64_t c) {
+    return c * B - shift >= 0 && (c * B - shift) + 4 * (int64_t)n4 <= a.n_floats;
+  };
+  const float* tile = my + shift;
 
   // The first chunk is requested before the column state: its loads do not
   // depend on it, and the two latencies overlap.
   float4 pre[kF4];
   uint32_t vld_n = 1;
   double ap_n = 0.0, rp_n = 0.0;
+  const bool fast = c0 < end && span_ok(c0);
   if (fast) {
     vld_n = a.valid ? (uint32_t)a.valid[c0 + lane] : 1u;
     ap_n = a.alpha_prev ? a.alpha_prev[c0 + lane] : 0.0;
     rp_n = a.r_in ? a.r_in[c0 + lane] : 0.0;
-    const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(a.L + c0 * B, n4 * 16);
+    const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(a.L + (c0 * B - shift), n4 * 16);
 #pragma unroll
     for (int k = 0; k < kF4; ++k) pre[k] = load16(rs, (lane + 64 * k) * 16);
   }
@@ -624,20 +634,22 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
   // it in pass 1 and later passes read it (r_in), so their band loop reads
   // only v.  p = L . v - mu . v, with even and odd bands on two FMA chains.
   const bool own_r = a.r_in == nullptr;
-  auto score = [&](int64_t c0, int n, uint32_t vld, double ap, double rp) {
+  auto score = [&](int64_t c0, int n, uint32_t vld, double ap, double rp, const float* tl) {
     const int64_t px = c0 + lane;
     const bool inb = lane < n;
     const bool ok = inb && vld != 0;
     double pp = 0.0, rr = 0.0;
     if (ok) {
-      const float* rowp = my + lane * B;
+      const float* rowp = tl + lane * B;
       const double2* v2 = reinterpret_cast<const double2*>(cst);
       const double2* m2 = reinterpret_cast<const double2*>(cst + kPad);
       double pe = 0.0, po = 0.0;
       int b = 0;
+      // pairs of bands need 8-byte aligned rows (B even, tile 8-byte aligned)
+      const bool pairs = (B & 1) == 0 && (reinterpret_cast<uintptr_t>(tl) & 7) == 0;
       if (own_r) {
         double re = 0.0, ro = 0.0;
-        if ((B & 1) == 0) {                   // pairs of bands: 8-byte tile reads
+        if (pairs) {                          // 8-byte tile reads
 #pragma unroll 4
           for (; b < B; b += 2) {
             const float2 l2 = *reinterpret_cast<const float2*>(rowp + b);
@@ -656,7 +668,7 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
         }
         rr = re + ro;
       } else {
-        if ((B & 1) == 0) {
+        if (pairs) {
           double2 cv = v2[0];
 #pragma unroll 4
           for (; b < B; b += 2) {
@@ -699,8 +711,8 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
         for (int p = 0; p < n; ++p) {
           const double cp = cbuf[wid * kChunk + p];
           if (cp != 0.0) {                      // wave-uniform; skips invalid pixels too
-            if (b0 < B) m_lo = fma(cp, (double)my[p * B + b0] - lb0, m_lo);
-            if (b1 < B) m_hi = fma(cp, (double)my[p * B + b1] - lb1, m_hi);
+            if (b0 < B) m_lo = fma(cp, (double)tl[p * B + b0] - lb0, m_lo);
+            if (b1 < B) m_hi = fma(cp, (double)tl[p * B + b1] - lb1, m_hi);
           }
         }
       }
@@ -709,14 +721,17 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
     wave_sync_lds();
   };
 
-  // Fast path over whole chunks of a 16-byte aligned work item: each chunk is
-  // loaded one chunk ahead, 16 bytes per load, into registers.  The loads of a
-  // chunk's per-pixel inputs (valid flag, alpha^{j-2}) are issued before its
-  // tile: vector loads retire in order, so waiting for them never waits for
-  // the tile in flight.  When there is no next chunk the resource covers 16
-  // bytes of the current chunk, so the loop body has no branch around a load.
+  // Fast path: each chunk (a ragged last one of the item too) is loaded one
+  // chunk ahead, 16 bytes per load, into registers.  Lanes past the item's
+  // end load pixels of the next column, which stay unused (the span check
+  // keeps every such read inside the arrays).  The loads of a chunk's
+  // per-pixel inputs (valid flag, alpha^{j-2}, r) are issued before its tile:
+  // vector loads retire in order, so waiting for them never waits for the
+  // tile in flight.  When there is no next chunk the resource covers 16 bytes
+  // of the current chunk, so the loop body has no branch around a load.
   if (fast) {
     while (true) {
+      const int n = (int)min<int64_t>(kChunk, end - c0);
       const uint32_t vld = vld_n;
       const double ap = ap_n, rp = rp_n;
       float4* t4 = reinterpret_cast<float4*>(my);
@@ -724,23 +739,23 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
       for (int k = 0; k < kF4; ++k) t4[lane + 64 * k] = pre[k];
       wave_sync_lds();
       const int64_t nx = c0 + step;
-      const bool more = nx + kChunk <= end;
+      const bool more = nx < end && span_ok(nx);
       {                                       // in flight while this chunk is scored
         const int64_t cn = more ? nx : c0;
         const int64_t pn = cn + (more ? lane : 0);
         vld_n = a.valid ? (uint32_t)a.valid[pn] : 1u;
         ap_n = a.alpha_prev ? a.alpha_prev[pn] : 0.0;
         rp_n = a.r_in ? a.r_in[pn] : 0.0;
-        const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(a.L + cn * B, more ? n4 * 16 : 16);
+        const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(a.L + (cn * B - shift), more ? n4 * 16 : 16);
 #pragma unroll
         for (int k = 0; k < kF4; ++k) pre[k] = load16(rs, (lane + 64 * k) * 16);
       }
-      score(c0, kChunk, vld, ap, rp);
+      score(c0, n, vld, ap, rp, tile);
       c0 = nx;
       if (!more) break;
     }
   }
-  // the rest (a ragged last chunk, or an item that is not 16-byte aligned):
+  // the rest (the last chunk of the array, when its span would pass the end):
   // synchronous copies
   for (; c0 < end; c0 += step) {
     const int n = (int)min<int64_t>(kChunk, end - c0);
@@ -750,7 +765,7 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
     const double ap = (inb && a.alpha_prev) ? a.alpha_prev[px] : 0.0;
     const double rp = (inb && a.r_in) ? a.r_in[px] : 0.0;
     copy_chunk(a.L + c0 * B, n * B, my, lane);
-    score(c0, n, vld, ap, rp);
+    score(c0, n, vld, ap, rp, my);
   }
 
   if constexpr (MODE == PM_VEC) {
@@ -2331,6 +2346,7 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   pa.albedo = p->opt.albedo;
   pa.lam = p->opt.lambda;
   pa.eps = p->opt.epsilon;
+  pa.n_floats = p->max_px * B;
   pa.partial_stride = n_tiles(p->nb) * 256;
   SolveArgs sa{};
   sa.cols = p->cols_d;

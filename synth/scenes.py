@@ -35,7 +35,7 @@ SeedSequence(seed, spawn_key=(flightline,)).
 from __future__ import annotations
 
 import os
-from dataclasses import dataclass, field
+from dataclasses import dataclass, replace, field
 from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -56,6 +56,7 @@ class SceneSpec:
     flightline: int = 0
     mask_max_frac: float = 0.0     # 0 => no mask
     noise_frac: float = 0.01
+    s_flightline: int = -1         # >= 0: use that flightline's target spectrum
 
 
 @dataclass
@@ -101,6 +102,10 @@ def make_globals(spec: SceneSpec) -> SceneGlobals:
     shape = (h[:, None] * _gauss(wl, c, w)).sum(0)
     kappa = -np.log(DIP_AT_1000) / 1000.0 / shape.max()
     s = (-kappa * shape).astype(np.float32)
+    if spec.s_flightline >= 0 and spec.s_flightline != spec.flightline:
+        # one gas and one instrument for a whole batch: a shared spectrum
+        # (drawn after this flightline's own, so its other draws are unchanged)
+        s = make_globals(replace(spec, flightline=spec.s_flightline, s_flightline=-1)).s
     # plumes
     P = spec.n_plumes
     pc = rng.uniform(0.0, spec.n_columns, P)
@@ -210,8 +215,9 @@ def diff_spec(seed: int = 1004) -> SceneSpec:
 
 def batch_specs(seed: int = 1003, n_flightlines: int = 32,
                 n_columns: int = 598) -> List[SceneSpec]:
-    """Ragged batch: lengths U{1000..12000}, 0-20 % masked per column."""
+    """Ragged batch: lengths U{1000..12000}, 0-20 % masked per column, one
+    target spectrum (flightline 0's) for the whole batch."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
     lens = rng.integers(1000, 12001, n_flightlines)
     return [SceneSpec(n_columns, int(n), 74, 40, (200.0, 8000.0), (3.0, 30.0),
-                      seed, f, 0.2) for f, n in enumerate(lens)]
+                      seed, f, 0.2, s_flightline=0) for f, n in enumerate(lens)]

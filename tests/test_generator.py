@@ -64,3 +64,8 @@ def test_batch_lengths():
     lens = np.array([s.n_lines for s in specs])
     assert lens.min() >= 1000 and lens.max() <= 12000
     assert all(s.n_columns == 598 and s.mask_max_frac == 0.2 for s in specs)
+    # one target spectrum for the whole batch; backgrounds and plumes differ
+    g0, g7 = make_globals(specs[0]), make_globals(specs[7])
+    assert np.array_equal(g0.s, g7.s)
+    assert not np.array_equal(g0.endmembers, g7.endmembers)
+    assert not np.array_equal(g0.plumes, g7.plumes)

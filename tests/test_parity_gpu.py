@@ -150,3 +150,24 @@ def test_full_flightline_sampled_columns(flightline, cov):
     cols = sorted(set([int(g.plumes[i, 0]) for i in range(3)] + list(rng.choice(598, 3, replace=False))))
     ref, _ = oracle_retrieve(sc.radiance, sc.s, 30, lam, columns=cols, workers=6)
     assert_fp32_parity(a[cols], ref, label=f"flightline cov={cov} cols {cols}")
+
+
+@pytest.mark.parametrize("cov", EXACT)
+@pytest.mark.parametrize("offset", [0, 1, 2])
+def test_odd_lines_and_unaligned_radiance(cov, offset):
+    """Odd line counts put every other column on an 8-byte (not 16-byte)
+    boundary, and an offset view of a larger buffer moves the whole cube off
+    16-byte alignment; work items of 128 lines leave ragged chunks."""
+    spec = SceneSpec(6, 1001, 74, 2, (500.0, 5000.0), (3.0, 30.0), seed=13)
+    sc = make_scene(spec)
+    S, N, B = sc.radiance.shape
+    big = torch.zeros(S * N * B + 4, dtype=torch.float32, device=DEV)
+    L = big[offset:offset + S * N * B]
+    L.copy_(torch.from_numpy(sc.radiance.reshape(-1)).to(DEV))
+    s = torch.from_numpy(sc.s).to(DEV)
+    ref, rst = oracle_retrieve(sc.radiance, sc.s, 15, 3.0)
+    for chunk in (128, 0):
+        a, st = mf.retrieve(L.view(S, N, B), s, n_iter=15, lam=3.0, cov=cov, chunk_lines=chunk)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(st.cpu().numpy(), rst)
+        assert_fp32_parity(a.cpu().numpy(), ref, label=f"odd lines offset={offset} chunk={chunk}")

@@ -1543,6 +1543,7 @@ constexpr int kBwA0 = 80, kBwB0 = 81, kBwA1 = 82, kBwB1 = 83, kBwRR = 84;   // p
 
 struct BwArgs {
   const float* L;
+  int64_t n_floats;          // floats of the radiance array (max_px * B)
   const uint8_t* valid;
   const WorkItem* items;
   const ColState* state;
@@ -1690,140 +1691,119 @@ __global__ void __launch_bounds__(kABlock) bwd_passA_kernel(BwArgs a) {
   }
 }
 
-// Dynamic LDS of bwd_passB_kernel: tiles, per-pixel weights, partial rows, constants.
+// Dynamic LDS of bwd_passB_kernel: per-pixel weights, partial rows, u^k, tiles.
 __host__ __device__ constexpr size_t bwd_lds_bytes(int B) {
-  return (size_t)kSW * kChunk * B * sizeof(float) + kSW * kChunk * sizeof(double) +
-         kSW * (kPad + 8) * sizeof(double) + 4 * kPad * sizeof(double);
+  return (size_t)kSW * kChunk * sizeof(double) + kSW * (kPad + 8) * sizeof(double) +
+         kPad * sizeof(double) + (size_t)kSW * kTileF * sizeof(float);
 }
 
-// Reverse pass B of iteration k (streams the radiance for beta = u^k . d).
+// Reverse pass B of iteration k: streams the radiance for L . u^k; p^k and r
+// come from the forward pass.  Same chunk pipeline as stream_kernel.
 __global__ void __launch_bounds__(kSBlock) bwd_passB_kernel(BwArgs a) {
   const WorkItem it = a.items[blockIdx.x];
   const ColState* __restrict__ st = a.state + it.col;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wid = tid >> 6;
+  const int lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
   const int B = a.B, k = a.k;
   const int64_t begin = it.px_begin, end = begin + it.n_px;
   extern __shared__ double dyn[];
   double* cbuf = dyn;                                   // [kSW][kChunk]
   double* redm = cbuf + kSW * kChunk;                   // [kSW][kPad + 8]
-  double* cst = redm + kSW * (kPad + 8);                // [kPad][4]: mu, v, m0, u
-  float* my = reinterpret_cast<float*>(cst + 4 * kPad) + wid * kChunk * B;
+  double* ucs = redm + kSW * (kPad + 8);                // [kPad] u^k
+  float* my = reinterpret_cast<float*>(ucs + kPad) + wid * kTileF;
+
+  const int64_t step = (int64_t)kSW * kChunk;
+  int64_t c0 = begin + (int64_t)kChunk * wid;
+  const int shift = (int)((reinterpret_cast<uintptr_t>(a.L + c0 * B) & 15) >> 2);
+  const int n4 = (shift + kChunk * B + 3) / 4;
+  auto span_ok = [&](int64_t c) {
+    return c * B - shift >= 0 && (c * B - shift) + 4 * (int64_t)n4 <= a.n_floats;
+  };
+  const float* tile = my + shift;
+
+  // per-pixel inputs, one chunk ahead: valid, p^k, r, alpha^{k-1}, pbar, abar, rbar
+  float4 pre[kF4];
+  uint32_t vld_n = 1;
+  double pp_n = 0.0, r_n = 0.0, am_n = 0.0, pb_n = 0.0, ab_n = 0.0, rb_n = 0.0;
+  const bool fast = c0 < end && span_ok(c0);
+  if (fast) {
+    const int64_t px = c0 + lane;
+    vld_n = a.valid ? (uint32_t)a.valid[px] : 1u;
+    pp_n = a.p_k[px];
+    r_n = a.r_px[px];
+    am_n = k >= 1 ? a.a_km1[px] : 0.0;
+    pb_n = a.pbar[px];
+    ab_n = a.abar[px];
+    rb_n = a.rbar[px];
+    const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(a.L + (c0 * B - shift), n4 * 16);
+#pragma unroll
+    for (int q = 0; q < kF4; ++q) pre[q] = load16(rs, (lane + 64 * q) * 16);
+  }
 
   if (st->status != MF_COL_OK) return;       // failed column: gradient 0 (assembly)
   const double* ck = a.ck_k + (int64_t)it.col * kCk;
   const double* bw = a.bwcol + (int64_t)it.col * kBw;
-  for (int b = tid; b < kPad; b += kSBlock) {
-    cst[4 * b + 0] = ck[kCkMu + b];
-    cst[4 * b + 1] = ck[kCkV + b];
-    cst[4 * b + 2] = st->m0[b];
-    cst[4 * b + 3] = a.u_k[(int64_t)it.col * kPad + b];
-  }
+  for (int b = tid; b < kPad; b += kSBlock) ucs[b] = a.u_k[(int64_t)it.col * kPad + b];
   __syncthreads();
   const double q = ck[kCkScal + 2], N = ck[kCkScal + 3];
-  const double gamma = bw[kBwScal + 0], tu = bw[kBwScal + 1], muu = bw[kBwScal + 2];
-  const double lam = a.lam, eps = a.eps;
+  const double tu = bw[kBwScal + 1], muu = bw[kBwScal + 2];
   // weighted band sum (k = 0 only): sum rbar L
   const bool vec = k == 0;
   double m_lo = 0.0, m_hi = 0.0;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
 
-  // chunk pipeline as in stream_kernel: whole 16-byte aligned chunks are
-  // prefetched one chunk ahead in registers, other chunks copied in place
-  const uintptr_t lp = reinterpret_cast<uintptr_t>(a.L);
-  constexpr int kF4 = (kChunk * 78 / 4 + 63) / 64;
-  float4 pre[kF4];
-  auto fast = [&](int64_t c) {
-    return c + kChunk <= end && ((lp + (uintptr_t)(c * B) * 4) & 15) == 0;
-  };
-  auto prefetch = [&](int64_t c) {
-    const float4* g4 = reinterpret_cast<const float4*>(a.L + c * B);
-    const int n4 = kChunk * B / 4;
-#pragma unroll
-    for (int q = 0; q < kF4; ++q) {
-      const int e = lane + 64 * q;
-      pre[q] = e < n4 ? g4[e] : float4{0.f, 0.f, 0.f, 0.f};
-    }
-  };
-  int64_t c0 = begin + (int64_t)kChunk * wid;
-  bool have = c0 < end && fast(c0);
-  if (have) prefetch(c0);
-  for (; c0 < end; c0 += kSW * kChunk) {
-    const int n = (int)min<int64_t>(kChunk, end - c0);
-    if (have) {
-      float4* t4 = reinterpret_cast<float4*>(my);
-      const int n4 = kChunk * B / 4;
-#pragma unroll
-      for (int q = 0; q < kF4; ++q) {
-        const int e = lane + 64 * q;
-        if (e < n4) t4[e] = pre[q];
-      }
-      wave_sync_lds();
-    } else {
-      copy_chunk(a.L + c0 * B, n * B, my, lane);
-    }
-    {
-      const int64_t nx = c0 + kSW * kChunk;
-      have = nx < end && fast(nx);
-      if (have) prefetch(nx);
-    }
+  auto score = [&](int64_t c0, int n, uint32_t vld, double pp, double r, double am1_in,
+                   double pb_in, double ab_in, double rb_in, const float* tl) {
     const int64_t px = c0 + lane;
     const bool inb = lane < n;
-    bool ok = inb;
-    if (inb && a.valid) ok = a.valid[px] != 0;
-    double pp = 0.0, rr = 0.0, lu = 0.0;
+    const bool ok = inb && vld != 0;
+    double lu = 0.0;
     if (ok) {
-      const float* rowp = my + lane * B;
+      const float* rowp = tl + lane * B;
+      const double2* u2 = reinterpret_cast<const double2*>(ucs);
+      double le = 0.0, lo = 0.0;
       int b = 0;
-      if ((B & 1) == 0) {
+      if ((B & 1) == 0 && (reinterpret_cast<uintptr_t>(tl) & 7) == 0) {
 #pragma unroll 4
         for (; b < B; b += 2) {
           const float2 l2 = *reinterpret_cast<const float2*>(rowp + b);
-          const double4 c0v = *reinterpret_cast<const double4*>(cst + 4 * b);
-          const double4 c1v = *reinterpret_cast<const double4*>(cst + 4 * b + 4);
-          const double l0 = (double)l2.x, l1 = (double)l2.y;
-          pp = fma(l0 - c0v.x, c0v.y, pp);
-          rr = fma(l0, c0v.z, rr);
-          pp = fma(l1 - c1v.x, c1v.y, pp);
-          rr = fma(l1, c1v.z, rr);
-          lu = fma(l0, c0v.w, lu);
-          lu = fma(l1, c1v.w, lu);
+          const double2 cu = u2[b >> 1];
+          le = fma((double)l2.x, cu.x, le);
+          lo = fma((double)l2.y, cu.y, lo);
         }
       }
-      for (; b < B; ++b) {
-        const double l = (double)rowp[b];
-        pp = fma(l - cst[4 * b], cst[4 * b + 1], pp);
-        rr = fma(l, cst[4 * b + 2], rr);
-        lu = fma(l, cst[4 * b + 3], lu);
-      }
+      for (; b < B; ++b) le = fma((double)rowp[b], ucs[b], le);
+      lu = le + lo;
     }
-    const double r = a.albedo ? rr : 1.0;
+    if (!ok) {
+      pp = 0.0;
+      r = 0.0;
+    }
     const bool live = ok && (r > 0.0);          // dark pixels keep alpha = 0
     double wgt = 0.0;
-    {
-      const double am1 = (k >= 1 && live) ? a.a_km1[px] : 0.0;
-      const double c = r * am1;
-      const double al = ok ? pp - c * q : 0.0;
-      const double be = ok ? lu - c * tu - muu : 0.0;
-      const double pb = inb ? a.pbar[px] : 0.0;
-      const double cbar = (al * tu + be * q) / N;
-      if (inb) {
-        a.coef_v[px] = ok ? pb - be / N : 0.0;
-        a.coef_u[px] = ok ? -al / N : 0.0;
-        if (k >= 1 && live) {
-          a.abar[px] += r * cbar;
-          a.rbar[px] += am1 * cbar;
-        }
+    const double am1 = (k >= 1 && live) ? am1_in : 0.0;
+    const double c = r * am1;
+    const double al = ok ? pp - c * q : 0.0;
+    const double be = ok ? lu - c * tu - muu : 0.0;
+    const double pb = inb ? pb_in : 0.0;
+    const double cbar = (al * tu + be * q) / N;
+    if (inb) {
+      a.coef_v[px] = ok ? pb - be / N : 0.0;
+      a.coef_u[px] = ok ? -al / N : 0.0;
+      if (k >= 1 && live) {
+        a.abar[px] = ab_in + r * cbar;
+        a.rbar[px] = rb_in + am1 * cbar;
       }
-      s0 += al;
-      s1 += be;
-      s2 += c * al;
-      s3 += c * be;
-      if (k == 0) {
-        const double rb = ok ? a.rbar[px] : 0.0;
-        s4 += rb * r;
-        wgt = rb;
-      }
+    }
+    s0 += al;
+    s1 += be;
+    s2 += c * al;
+    s3 += c * be;
+    if (k == 0) {
+      const double rb = ok ? rb_in : 0.0;
+      s4 += rb * r;
+      wgt = rb;
     }
     if (vec && __ballot(wgt != 0.0)) {             // wave-uniform; sparse weights
       cbuf[wid * kChunk + lane] = wgt;
@@ -1832,12 +1812,54 @@ __global__ void __launch_bounds__(kSBlock) bwd_passB_kernel(BwArgs a) {
       for (int p = 0; p < n; ++p) {
         const double cp = cbuf[wid * kChunk + p];
         if (cp != 0.0) {
-          if (b0 < B) m_lo = fma(cp, (double)my[p * B + b0], m_lo);
-          if (b1 < B) m_hi = fma(cp, (double)my[p * B + b1], m_hi);
+          if (b0 < B) m_lo = fma(cp, (double)tl[p * B + b0], m_lo);
+          if (b1 < B) m_hi = fma(cp, (double)tl[p * B + b1], m_hi);
         }
       }
     }
     wave_sync_lds();
+  };
+
+  if (fast) {
+    while (true) {
+      const int n = (int)min<int64_t>(kChunk, end - c0);
+      const uint32_t vld = vld_n;
+      const double pp = pp_n, r = r_n, am = am_n, pb = pb_n, ab = ab_n, rb = rb_n;
+      float4* t4 = reinterpret_cast<float4*>(my);
+#pragma unroll
+      for (int q = 0; q < kF4; ++q) t4[lane + 64 * q] = pre[q];
+      wave_sync_lds();
+      const int64_t nx = c0 + step;
+      const bool more = nx < end && span_ok(nx);
+      {                                       // in flight while this chunk is scored
+        const int64_t cn = more ? nx : c0;
+        const int64_t pn = cn + (more ? lane : 0);
+        vld_n = a.valid ? (uint32_t)a.valid[pn] : 1u;
+        pp_n = a.p_k[pn];
+        r_n = a.r_px[pn];
+        am_n = k >= 1 ? a.a_km1[pn] : 0.0;
+        pb_n = a.pbar[pn];
+        ab_n = a.abar[pn];
+        rb_n = a.rbar[pn];
+        const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(a.L + (cn * B - shift), more ? n4 * 16 : 16);
+#pragma unroll
+        for (int q = 0; q < kF4; ++q) pre[q] = load16(rs, (lane + 64 * q) * 16);
+      }
+      score(c0, n, vld, pp, r, am, pb, ab, rb, tile);
+      c0 = nx;
+      if (!more) break;
+    }
+  }
+  for (; c0 < end; c0 += step) {               // the last chunk of the array
+    const int n = (int)min<int64_t>(kChunk, end - c0);
+    const int64_t px = c0 + lane;
+    const bool inb = lane < n;
+    const uint32_t vld = (inb && a.valid) ? (uint32_t)a.valid[px] : 1u;
+    const double pp = inb ? a.p_k[px] : 0.0, r = inb ? a.r_px[px] : 0.0;
+    const double am = (inb && k >= 1) ? a.a_km1[px] : 0.0, pb = inb ? a.pbar[px] : 0.0;
+    const double ab = inb ? a.abar[px] : 0.0, rb = inb ? a.rbar[px] : 0.0;
+    copy_chunk(a.L + c0 * B, n * B, my, lane);
+    score(c0, n, vld, pp, r, am, pb, ab, rb, my);
   }
   for (int off = 32; off >= 1; off >>= 1) {
     s0 += __shfl_xor(s0, off, 64);
@@ -2646,6 +2668,7 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
   }
   BwArgs ba{};
   ba.L = radiance;
+  ba.n_floats = mp * B;
   ba.valid = valid;
   ba.items = p->items_d;
   ba.state = state;

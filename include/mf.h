@@ -73,8 +73,8 @@ enum {
 };
 
 /* How C^k of Eq. 11 is formed.  Every form computes the same matrix in exact
-   arithmetic; they differ in rounding and speed.  The per-pixel scores are
-   FP32 and the factorisation FP64 in every form. */
+   arithmetic; they differ in rounding and speed.  The per-pixel scores
+   (Eqs. 6-7) and the factorisation are FP64 in every form. */
 typedef enum {
   MF_COV_LOWRANK = 0,    /* default.  C^0 from one exact Gram (FP64 MFMA); C^k
                             from C^0 by an exact rank-3 update built from
@@ -137,7 +137,8 @@ MF_API int64_t mf_plan_columns(mf_plan plan);
 MF_API int64_t mf_plan_pixels(mf_plan plan);
 
 /* Runs Fig. 1 on every column of the plan.
-     radiance       [max_px][B] float32, uW cm^-2 sr^-1 nm^-1 (read only)
+     radiance       [max_px][B] float32, uW cm^-2 sr^-1 nm^-1 (read only); any
+                    float-aligned pointer (16-byte alignment is not required)
      valid          [max_px] uint8, nonzero = valid pixel, or NULL (all valid).
                     Invalid pixels are excluded from every mean and covariance
                     (censored data is skipped, Sec. III-C) and get alpha = 0;

@@ -488,8 +488,8 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
 // band-per-lane from the same tile, and skipped when the chunk has no
 // nonzero c (the enhancement is sparse).
 
-constexpr int kChunk = 64;                 // pixels per wave chunk
-constexpr int kSW = 2;                     // waves per stream workgroup
+constexpr int kChunk = 32;                 // pixels per wave chunk (streaming passes)
+constexpr int kSW = 4;                     // waves per stream workgroup
 constexpr int kSBlock = 64 * kSW;
 constexpr int kCopyGroup = 10;             // 16-byte loads in flight per lane while copying
 
@@ -547,10 +547,10 @@ __device__ __forceinline__ float4 load16(__amdgpu_buffer_rsrc_t rs, int off) {
 
 // A wave's radiance tile: kF4 16-byte groups per lane (a whole chunk of up to
 // 80 bands), so the fast path writes it without bounds tests.
-constexpr int kF4 = (kChunk * 80 / 4 + 63) / 64;     // 20
+constexpr int kF4 = (kChunk * 80 / 4 + 63) / 64;     // 10
 constexpr int kTileF = kF4 * 64 * 4;                  // floats per wave tile
 
-// Dynamic LDS bytes of stream_kernel (about 45 KB).
+// Dynamic LDS bytes of stream_kernel (about 46 KB).
 __host__ __device__ constexpr size_t stream_lds_bytes(int B) {
   return (size_t)kSW * kChunk * sizeof(double) + kSW * (kPad + 2) * sizeof(double) +
          4 * kPad * sizeof(double) + (size_t)kSW * kTileF * sizeof(float);
@@ -703,7 +703,7 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
       s1 += c;
       s2 = fma(c, c, s2);
       if (__ballot(c != 0.0)) {                 // wave-uniform
-        cbuf[wid * kChunk + lane] = c;
+        if (lane < kChunk) cbuf[wid * kChunk + lane] = c;
         wave_sync_lds();
         const int b0 = lane, b1 = lane + 64;
         const double lb0 = b0 < B ? cst[2 * kPad + b0] : 0.0;
@@ -1570,10 +1570,11 @@ struct BwArgs {
 // Pass A is light per pixel: eight waves per work item keep enough loads in flight.
 constexpr int kAW = 8;
 constexpr int kABlock = 64 * kAW;
+constexpr int kAChunk = 64;                // pixels per wave chunk in pass A
 
 // Dynamic LDS of bwd_passA_kernel: per-pixel weights, partial rows, mu^k.
 __host__ __device__ constexpr size_t bwdA_lds_bytes(int B) {
-  return (size_t)kAW * kChunk * sizeof(double) + kAW * (kPad + 8) * sizeof(double) +
+  return (size_t)kAW * kAChunk * sizeof(double) + kAW * (kPad + 8) * sizeof(double) +
          kPad * sizeof(double);
 }
 
@@ -1588,8 +1589,8 @@ __global__ void __launch_bounds__(kABlock) bwd_passA_kernel(BwArgs a) {
   const int B = a.B, k = a.k;
   const int64_t begin = it.px_begin, end = begin + it.n_px;
   extern __shared__ double dyn[];
-  double* cbuf = dyn;                                   // [kAW][kChunk]
-  double* redm = cbuf + kAW * kChunk;                   // [kAW][kPad + 8]
+  double* cbuf = dyn;                                   // [kAW][kAChunk]
+  double* redm = cbuf + kAW * kAChunk;                   // [kAW][kPad + 8]
   double* mu = redm + kAW * (kPad + 8);                 // [kPad]
 
   if (st->status != MF_COL_OK) return;       // failed column: gradient 0 (assembly)
@@ -1601,8 +1602,8 @@ __global__ void __launch_bounds__(kABlock) bwd_passA_kernel(BwArgs a) {
   const double gamma = bw[kBwScal + 0];
   const double lam = a.lam, eps = a.eps;
   double m_lo = 0.0, m_hi = 0.0, s0 = 0.0, s1 = 0.0;
-  for (int64_t c0 = begin + (int64_t)kChunk * wid; c0 < end; c0 += kAW * kChunk) {
-    const int n = (int)min<int64_t>(kChunk, end - c0);
+  for (int64_t c0 = begin + (int64_t)kAChunk * wid; c0 < end; c0 += kAW * kAChunk) {
+    const int n = (int)min<int64_t>(kAChunk, end - c0);
     const int64_t px = c0 + lane;
     const bool inb = lane < n;
     bool ok = inb;
@@ -1636,7 +1637,7 @@ __global__ void __launch_bounds__(kABlock) bwd_passA_kernel(BwArgs a) {
     s1 += pb;
     uint64_t mask = __ballot(pb != 0.0);        // wave-uniform; sparse weights
     if (mask) {
-      cbuf[wid * kChunk + lane] = pb;
+      cbuf[wid * kAChunk + lane] = pb;
       wave_sync_lds();
       const float* Lc = a.L + c0 * B;
       const int b0 = lane, b1 = lane + 64;
@@ -1659,7 +1660,7 @@ __global__ void __launch_bounds__(kABlock) bwd_passA_kernel(BwArgs a) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           if (pi[u] >= 0) {
-            const double cp = cbuf[wid * kChunk + pi[u]];
+            const double cp = cbuf[wid * kAChunk + pi[u]];
             m_lo = fma(cp, (double)l0[u] - o0, m_lo);
             m_hi = fma(cp, (double)l1[u] - o1, m_hi);
           }
@@ -1806,7 +1807,7 @@ __global__ void __launch_bounds__(kSBlock) bwd_passB_kernel(BwArgs a) {
       wgt = rb;
     }
     if (vec && __ballot(wgt != 0.0)) {             // wave-uniform; sparse weights
-      cbuf[wid * kChunk + lane] = wgt;
+      if (lane < kChunk) cbuf[wid * kChunk + lane] = wgt;
       wave_sync_lds();
       const int b0 = lane, b1 = lane + 64;
       for (int p = 0; p < n; ++p) {

@@ -100,7 +100,8 @@ typedef struct {
                              per-iteration column state for mf_backward (needs
                              MF_COV_LOWRANK and n_iter <= 30; larger workspace) */
   int32_t  chunk_lines;   /* pixels per work item along a column (multiple of
-                             128; 0 = library default) */
+                             128; 0 = library default: 1024 for the low-rank
+                             form, 4096 for the Gram forms) */
 } mf_options;
 
 typedef struct {

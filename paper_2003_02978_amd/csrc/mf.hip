@@ -45,7 +45,12 @@ namespace {
 constexpr int kBlock = 256;      // 4 waves of 64
 constexpr int kPad = 80;         // bands of the per-column state (5 x 16)
 constexpr int kMaxTri = 80 * 81 / 2;
-constexpr int kDefaultChunk = 1024;
+// Default work-item lengths (lines): the low-rank form's partials are 82
+// doubles per item, so short items balance the streaming passes best; the
+// Gram forms combine a 30 KB partial Gram per item in every solve, so they
+// prefer long items.
+constexpr int kDefaultChunkLowrank = 1024;
+constexpr int kDefaultChunkGram = 4096;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
@@ -341,13 +346,16 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
         const bool in = ok && band_of<NB, WIDE>(k, c16) < B;
         l[k] = in ? (double)Lc[s][k] : 0.0;
         x[k] = in ? l[k] - mu[k] : 0.0;
-        pp = fma(x[k], vv[k], pp);
-        rr = fma(l[k], m0[k], rr);
       }
-      pp = row_sum16_f64(pp);
-      rr = row_sum16_f64(rr);
       double c = 0.0;
-      if (j >= 1) {
+      if (j >= 1) {                       // pass 0 only accumulates the Gram
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          pp = fma(x[k], vv[k], pp);
+          rr = fma(l[k], m0[k], rr);
+        }
+        pp = row_sum16_f64(pp);
+        rr = row_sum16_f64(rr);
         const double r = a.albedo ? rr : 1.0;
         const double num = (j == 1) ? pp : pp - lam / (apc[s] + eps);
         double al = num / (r * q);
@@ -2487,7 +2495,8 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
     return fail_with(MF_E_ARG, "chunk_lines must be a non-negative multiple of 128");
   if (n_fl < 1) return fail_with(MF_E_SHAPE, "need at least one flightline");
 
-  const int chunk = opt->chunk_lines ? opt->chunk_lines : kDefaultChunk;
+  const int chunk = opt->chunk_lines ? opt->chunk_lines
+                                     : (opt->cov == MF_COV_LOWRANK ? kDefaultChunkLowrank : kDefaultChunkGram);
   std::vector<ColInfo> cols;
   std::vector<WorkItem> items;
   std::vector<std::pair<int64_t, int64_t>> ranges;

@@ -1575,8 +1575,9 @@ struct BwArgs {
   int albedo;
 };
 
-// Pass A is light per pixel: eight waves per work item keep enough loads in flight.
-constexpr int kAW = 8;
+// Pass A is light per pixel; four waves per work item measured best (8 and 16
+// waves per workgroup were slower, 2 about the same).
+constexpr int kAW = 4;
 constexpr int kABlock = 64 * kAW;
 constexpr int kAChunk = 64;                // pixels per wave chunk in pass A
 

@@ -955,7 +955,6 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   const int j = a.j;
   constexpr int T = n_tiles(NB);
   const double* P = a.partials + (int64_t)ci.first_item * T * 256;
-  const bool rank3 = a.lowrank && j >= 1;
   double* c0 = a.c0 + (int64_t)col * (kNBlk * 16);
   double* pinv = a.pinv + (int64_t)col * (kNBlk * 16);
 
@@ -973,32 +972,14 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   if (owner) block_coords(tid, bi, bj);
 
   if (tid == 0) {
-    if (rank3) {
-      double s1 = 0.0, s2 = 0.0;
-      for (int it = 0; it < ci.n_items; ++it) {
-        s1 += P[(int64_t)it * T * 256 + kVecS1];
-        s2 += P[(int64_t)it * T * 256 + kVecS2];
-      }
-      sc[0] = st.n_valid;
-      sc[1] = s1;
-      sc[2] = s2;
-    } else {
-      sc[0] = gram_elem<NB, WIDE>(P, ci.n_items, B, B);          // N
-      sc[1] = gram_elem<NB, WIDE>(P, ci.n_items, B + 1, B);      // S1 = sum c
-      sc[2] = gram_elem<NB, WIDE>(P, ci.n_items, B + 1, B + 1);  // S2 = sum c^2
-    }
+    sc[0] = gram_elem<NB, WIDE>(P, ci.n_items, B, B);          // N
+    sc[1] = gram_elem<NB, WIDE>(P, ci.n_items, B + 1, B);      // S1 = sum c
+    sc[2] = gram_elem<NB, WIDE>(P, ci.n_items, B + 1, B + 1);  // S2 = sum c^2
     fail = 0;
   }
   for (int b = tid; b < B; b += kBlock) {
-    if (rank3) {
-      double m = 0.0;
-      for (int it = 0; it < ci.n_items; ++it) m += P[(int64_t)it * T * 256 + b];
-      g1[b] = m;
-      g2[b] = 0.0;
-    } else {
-      g1[b] = gram_elem<NB, WIDE>(P, ci.n_items, B, b);
-      g2[b] = gram_elem<NB, WIDE>(P, ci.n_items, B + 1, b);
-    }
+    g1[b] = gram_elem<NB, WIDE>(P, ci.n_items, B, b);
+    g2[b] = gram_elem<NB, WIDE>(P, ci.n_items, B + 1, b);
   }
   __syncthreads();
   const double N = sc[0], S1 = sc[1], S2 = sc[2];
@@ -1014,19 +995,13 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
     }
     mun[b] = m;
     tn[b] = m * sb;                            // Eq. 9
-    if (rank3) {
-      D[b] = st.t[b] - tn[b];                  // t^{j-1} - t^j
-      E[b] = 0.0;
-    } else {
-      D[b] = mu_used - m;
-      E[b] = j == 0 ? 0.0 : t_used - tn[b];
-    }
+    D[b] = mu_used - m;
+    E[b] = j == 0 ? 0.0 : t_used - tn[b];
   }
   __syncthreads();
 
   // ---- assembly of C (Eq. 11) into the register blocks
   double A_[kBlk][kBlk], C_[kBlk][kBlk];
-  const double abar = S1 / N;
   int myfail = 0;
 #pragma unroll
   for (int x = 0; x < kBlk; ++x)
@@ -1035,15 +1010,10 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
       const int i = kBlk * bi + x, jj = kBlk * bj + y;
       double c = (i == jj) ? 1.0 : 0.0;        // padding keeps the factor regular
       if (owner && i < B && jj < B && i >= jj) {
-        if (rank3) {
-          c = c0[blk_at(tid, x, y)] + abar * abar * D[i] * D[jj] +
-              (S2 / N - abar * abar) * tn[i] * tn[jj] - (g1[i] * tn[jj] + tn[i] * g1[jj]) / N;
-        } else {
-          c = gram_elem<NB, WIDE>(P, ci.n_items, i, jj);
-          c += g1[i] * D[jj] + D[i] * g1[jj] + g2[i] * E[jj] + E[i] * g2[jj] +
-               N * D[i] * D[jj] + S1 * (D[i] * E[jj] + E[i] * D[jj]) + S2 * E[i] * E[jj];
-          c /= N;
-        }
+        c = gram_elem<NB, WIDE>(P, ci.n_items, i, jj);
+        c += g1[i] * D[jj] + D[i] * g1[jj] + g2[i] * E[jj] + E[i] * g2[jj] +
+             N * D[i] * D[jj] + S1 * (D[i] * E[jj] + E[i] * D[jj]) + S2 * E[i] * E[jj];
+        c /= N;
         if (!isfinite(c)) myfail = 1;
       } else if (owner && i < B && jj < B) {
         c = 0.0;                               // upper half of a diagonal block: unused

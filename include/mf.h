@@ -24,8 +24,10 @@
  *    NULL = the default stream).  No entry point synchronises the stream.
  *  - Argument and shape errors are detected on the host before anything is
  *    enqueued and returned as an mf_status; nothing is launched then.
- *  - Numerical failures are per column and asynchronous: they are written to
- *    column_status (see MF_COL_*) and the column's alpha is set to 0.
+ *  - Numerical failures are per partition and asynchronous: they are written
+ *    to column_status (see MF_COL_*) and the partition's alpha is set to 0.
+ *    A partition is one detector column, or `group` adjacent columns
+ *    (mf_options.group); "column" below means a partition.
  *  - No C++ exception crosses this boundary.
  *
  * Radiance layout: float32, band-contiguous pixels ("[px][B]").  Flightline f
@@ -50,7 +52,7 @@ extern "C" {
 #define MF_API
 #endif
 
-#define MF_ABI_VERSION 1
+#define MF_ABI_VERSION 2
 #define MF_MAX_BANDS 78      /* B + 2 <= 80: five 16-band MFMA blocks */
 
 typedef struct mf_plan_s* mf_plan;
@@ -102,6 +104,10 @@ typedef struct {
   int32_t  chunk_lines;   /* pixels per work item along a column (multiple of
                              128; 0 = library default: 1024 for the low-rank
                              form, 4096 for the Gram forms) */
+  int32_t  group;         /* detectors per partition (Sec. II-E), >= 1: each run
+                             of `group` adjacent columns of a flightline (the
+                             last run takes the remainder) shares one mean and
+                             covariance; 1 = one partition per column */
 } mf_options;
 
 typedef struct {
@@ -133,7 +139,8 @@ MF_API mf_status mf_plan_create(const mf_options* opt, const mf_flightline* flig
 /* Bytes of device workspace mf_retrieve needs (256-byte aligned start). */
 MF_API size_t mf_workspace_bytes(mf_plan plan);
 
-/* Total number of columns and of pixels (sum of n_columns * n_lines) of the plan. */
+/* Number of partitions (columns when group = 1, else sum over flightlines of
+   ceil(n_columns / group)) and of pixels (sum of n_columns * n_lines). */
 MF_API int64_t mf_plan_columns(mf_plan plan);
 MF_API int64_t mf_plan_pixels(mf_plan plan);
 

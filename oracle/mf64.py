@@ -205,5 +205,28 @@ def retrieve(L, s, n_iter: int, lam: float = 1.0, eps: float = 1e-9,
     return alpha, status
 
 
+def retrieve_grouped(L, s, n_iter: int, lam: float = 1.0, eps: float = 1e-9,
+                     albedo: bool = True, valid=None, group: int = 1):
+    """Detector grouping (Sec. II-E): `group` adjacent columns of a [S, N, B]
+    cube form one partition (the last partition takes the remainder) whose
+    pixels share one mean and one covariance.  Each partition is run through
+    Fig. 1 as a single column of (columns x N) pixels.
+
+    Returns (alpha [S, N] float64, status [ceil(S / group)] int32).
+    """
+    L = np.asarray(L)
+    S, N, B = L.shape
+    alpha = np.zeros((S, N))
+    status = []
+    for c0 in range(0, S, group):
+        c1 = min(S, c0 + group)
+        Lp = L[c0:c1].reshape((c1 - c0) * N, B)
+        vp = None if valid is None else np.asarray(valid)[c0:c1].reshape(-1)
+        a, st = retrieve_column(Lp, s, n_iter, lam, eps, albedo, vp)
+        alpha[c0:c1] = a.reshape(c1 - c0, N)
+        status.append(st)
+    return alpha, np.array(status, dtype=np.int32)
+
+
 def host_cores() -> int:
     return len(os.sched_getaffinity(0))

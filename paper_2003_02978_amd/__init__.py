@@ -24,6 +24,7 @@ EXPORTS = ("mf_abi_version", "mf_options_default", "mf_status_str", "mf_last_err
            "mf_retrieve", "mf_backward", "mf_plan_set_graph", "mf_plan_set_timing", "mf_plan_kernel_times", "mf_stream_read",
            "mf_plan_destroy")
 KERNEL_KINDS = ("pass_gram", "pass_vec", "pass_last", "solve", "other")
+ABI_VERSION = 2          # MF_ABI_VERSION of include/mf.h (mf_options layout)
 
 
 class Options(ctypes.Structure):
@@ -31,7 +32,8 @@ class Options(ctypes.Structure):
                 ("n_iter", ctypes.c_int32), ("albedo", ctypes.c_int32),
                 ("lambda_", ctypes.c_double), ("epsilon", ctypes.c_double),
                 ("cov", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
-                ("save_for_backward", ctypes.c_int32), ("chunk_lines", ctypes.c_int32)]
+                ("save_for_backward", ctypes.c_int32), ("chunk_lines", ctypes.c_int32),
+                ("group", ctypes.c_int32)]
 
 
 class Flightline(ctypes.Structure):
@@ -85,8 +87,8 @@ def load_library(path: str = LIB_PATH):
                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     lib.mf_stream_read.restype = ctypes.c_int
     lib.mf_stream_read.argtypes = [vp, i64, vp, i32, ctypes.POINTER(ctypes.c_float), vp]
-    if lib.mf_abi_version() != 1:
-        raise ImportError("libmf.so ABI version mismatch")
+    if lib.mf_abi_version() != ABI_VERSION:
+        raise ImportError(f"libmf.so ABI version {lib.mf_abi_version()}, binding expects {ABI_VERSION}")
     _lib = lib
     return lib
 
@@ -113,13 +115,14 @@ class Plan:
     def __init__(self, flightlines: Iterable[Tuple[int, int, int]], n_bands: int = 74,
                  n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9, albedo: bool = True,
                  cov: str = "lowrank", refine_steps: int = 1, chunk_lines: int = 0,
-                 save_for_backward: bool = False):
+                 save_for_backward: bool = False, group: int = 1):
         lib = load_library()
         o = default_options()
         o.n_bands, o.n_iter, o.albedo = n_bands, n_iter, int(bool(albedo))
         o.lambda_, o.epsilon, o.cov = float(lam), float(eps), COV[cov]
         o.refine_steps, o.chunk_lines = refine_steps, chunk_lines
         o.save_for_backward = int(bool(save_for_backward))
+        o.group = int(group)
         fls = list(flightlines)
         arr = (Flightline * max(1, len(fls)))(*[Flightline(int(a), int(b), int(c)) for a, b, c in fls])
         h = ctypes.c_void_p()
@@ -289,10 +292,11 @@ def _make_autograd():
         through the library's hand-written adjoint (mf_backward)."""
 
         @staticmethod
-        def forward(ctx, radiance, s, n_iter, lam, eps, albedo, valid, refine_steps, chunk_lines):
+        def forward(ctx, radiance, s, n_iter, lam, eps, albedo, valid, refine_steps, chunk_lines,
+                    group):
             S, N, B = radiance.shape
             plan = Plan([(0, S, N)], B, n_iter, lam, eps, albedo, "lowrank", refine_steps,
-                        chunk_lines, save_for_backward=True)
+                        chunk_lines, save_for_backward=True, group=group)
             ws = plan.alloc_workspace(radiance.device)
             L = radiance.detach().contiguous()
             sv = s.detach().contiguous()
@@ -307,7 +311,7 @@ def _make_autograd():
             plan, ws, L, sv, vv = ctx.state
             gL, gs = plan.backward(L, sv, grad_alpha.contiguous().float(), vv, ws)
             ctx.state = None
-            return gL, gs.to(sv.dtype), None, None, None, None, None, None, None
+            return gL, gs.to(sv.dtype), None, None, None, None, None, None, None, None
 
     return RetrieveFunction
 
@@ -317,13 +321,13 @@ _RetrieveFunction = None
 
 def retrieve_differentiable(radiance, s, n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9,
                             albedo: bool = True, valid=None, refine_steps: int = 1,
-                            chunk_lines: int = 0):
+                            chunk_lines: int = 0, group: int = 1):
     """alpha [S, N] with autograd support (radiance and s), low-rank form."""
     global _RetrieveFunction
     if _RetrieveFunction is None:
         _RetrieveFunction = _make_autograd()
     return _RetrieveFunction.apply(radiance, s, n_iter, lam, eps, albedo, valid, refine_steps,
-                                   chunk_lines)
+                                   chunk_lines, group)
 
 
 def _need(t, dtype, name):
@@ -337,16 +341,19 @@ def _need(t, dtype, name):
 
 def retrieve(radiance, s, n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9,
              albedo: bool = True, cov: str = "lowrank", valid=None, refine_steps: int = 1,
-             chunk_lines: int = 0):
+             chunk_lines: int = 0, group: int = 1):
     """Retrieve alpha (ppm*m) for a [S, N, B] float32 radiance cube on the GPU.
 
-    Returns (alpha [S, N] float32, column_status [S] int32), both on the GPU.
+    group > 1 pools `group` adjacent columns per partition (the last one takes
+    the remainder).  Returns (alpha [S, N] float32, status int32 per partition
+    [ceil(S / group)]), both on the GPU.
     """
     import torch
     S, N, B = radiance.shape
-    plan = Plan([(0, S, N)], B, n_iter, lam, eps, albedo, cov, refine_steps, chunk_lines)
+    plan = Plan([(0, S, N)], B, n_iter, lam, eps, albedo, cov, refine_steps, chunk_lines,
+                group=group)
     alpha = torch.empty((S, N), dtype=torch.float32, device=radiance.device)
-    status = torch.empty((S,), dtype=torch.int32, device=radiance.device)
+    status = torch.empty((plan.n_columns,), dtype=torch.int32, device=radiance.device)
     plan.retrieve(radiance.contiguous(), s.contiguous(), alpha,
                   None if valid is None else valid.contiguous(), status)
     return alpha, status

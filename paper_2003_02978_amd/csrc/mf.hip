@@ -66,9 +66,11 @@ enum PassMode {
 };
 constexpr int kVecM = 80, kVecS1 = 80, kVecS2 = 81;   // PM_VEC partial layout
 
+// One partition (Sec. II-E): `group` adjacent detector columns of a
+// flightline, contiguous in memory, solved as one problem.
 struct ColInfo {
   int64_t first_px;
-  int32_t n_lines;
+  int32_t n_px;              // pixels of the partition
   int32_t first_item;
   int32_t n_items;
   int32_t pad;
@@ -161,10 +163,10 @@ __global__ void __launch_bounds__(64) setup_kernel(const float* __restrict__ L,
   const ColInfo ci = cols[col];
   int64_t z = -1;
   if (valid == nullptr) {
-    z = ci.n_lines > 0 ? ci.first_px : -1;
+    z = ci.n_px > 0 ? ci.first_px : -1;
   } else {
-    for (int64_t l0 = 0; l0 < ci.n_lines; l0 += 64) {
-      const bool v = (l0 + lane < ci.n_lines) && valid[ci.first_px + l0 + lane] != 0;
+    for (int64_t l0 = 0; l0 < ci.n_px; l0 += 64) {
+      const bool v = (l0 + lane < ci.n_px) && valid[ci.first_px + l0 + lane] != 0;
       const unsigned long long m = __ballot(v);
       if (m) {
         z = ci.first_px + l0 + (__ffsll(m) - 1);
@@ -2421,6 +2423,7 @@ void mf_options_default(mf_options* o) {
   o->refine_steps = 1;
   o->save_for_backward = 0;
   o->chunk_lines = 0;
+  o->group = 1;
 }
 
 const char* mf_status_str(mf_status s) {
@@ -2464,6 +2467,7 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
     return fail_with(MF_E_UNSUPPORTED, "save_for_backward supports n_iter <= 30");
   if (opt->chunk_lines < 0 || opt->chunk_lines % 128 != 0)
     return fail_with(MF_E_ARG, "chunk_lines must be a non-negative multiple of 128");
+  if (opt->group < 1) return fail_with(MF_E_ARG, "group must be >= 1");
   if (n_fl < 1) return fail_with(MF_E_SHAPE, "need at least one flightline");
 
   const int chunk = opt->chunk_lines ? opt->chunk_lines
@@ -2480,21 +2484,27 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
     ranges.push_back({F.first_px, F.first_px + np});
     n_px += np;
     max_px = std::max(max_px, F.first_px + np);
-    for (int c = 0; c < F.n_columns; ++c) {
+    // partitions of `group` adjacent columns (the last one takes the remainder)
+    const int g = opt->group;
+    if ((int64_t)std::min(g, F.n_columns) * F.n_lines > (int64_t)INT32_MAX)
+      return fail_with(MF_E_SHAPE, "flightline " + std::to_string(f) + ": a partition exceeds 2^31 pixels");
+    for (int c = 0; c < F.n_columns; c += g) {
+      const int ncol = std::min(g, F.n_columns - c);
+      const int npart = ncol * F.n_lines;
       ColInfo ci{};
       ci.first_px = F.first_px + (int64_t)c * F.n_lines;
-      ci.n_lines = F.n_lines;
+      ci.n_px = npart;
       ci.first_item = (int32_t)items.size();
-      const int nit = (F.n_lines + chunk - 1) / chunk;
+      const int nit = (int)(((int64_t)npart + chunk - 1) / chunk);
       // split evenly, in multiples of 128 pixels
-      int per = (F.n_lines + nit - 1) / nit;
+      int per = (int)(((int64_t)npart + nit - 1) / nit);
       per = (per + 127) / 128 * 128;
       int done = 0;
-      for (int k = 0; k < nit && done < F.n_lines; ++k) {
+      for (int k = 0; k < nit && done < npart; ++k) {
         WorkItem w{};
         w.px_begin = ci.first_px + done;
         w.col = (int32_t)cols.size();
-        w.n_px = std::min(per, F.n_lines - done);
+        w.n_px = std::min(per, npart - done);
         done += w.n_px;
         items.push_back(w);
       }

@@ -80,6 +80,37 @@ def test_adjoint_odd_lines_ragged_items():
     plan.close()
 
 
+def test_adjoint_detector_grouping():
+    """Partitions of 3 adjacent columns (remainder 2): the adjoint against the
+    reference gradient of each partition run as one column."""
+    sc = make_scene(SceneSpec(5, 200, 74, 2, (800.0, 5000.0), (3.0, 12.0), seed=41))
+    S, N, B = sc.radiance.shape
+    K, lam, g = 5, 2.0, 3
+    L = torch.from_numpy(sc.radiance).to(DEV).requires_grad_(True)
+    s = torch.from_numpy(sc.s).to(DEV).requires_grad_(True)
+    at = torch.from_numpy(sc.alpha_true).to(DEV)
+    alpha = mf.retrieve_differentiable(L, s, K, lam, 1e-9, True, None, group=g)
+    J = ((alpha.double() - at) ** 2).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    gL = L.grad.cpu().numpy().astype(np.float64)
+    gs = s.grad.cpu().numpy().astype(np.float64)
+    Jr, gLr, gsr = 0.0, np.zeros_like(gL), np.zeros(B)
+    for c0 in range(0, S, g):
+        c1 = min(S, c0 + g)
+        Lp = sc.radiance[c0:c1].astype(np.float64).reshape(1, (c1 - c0) * N, B)
+        Ap = sc.alpha_true[c0:c1].reshape(1, -1)
+        j, gl, gsp = loss_and_grads(Lp, sc.s, Ap, K, lam)
+        Jr += j
+        gLr[c0:c1] = gl.reshape(c1 - c0, N, B)
+        gsr += gsp
+    print(f"grouping: J {float(J):.6e} ref {Jr:.6e}, grad L rel err {_rel_err(gL, gLr):.2e}, "
+          f"grad s rel err {_rel_err(gs, gsr):.2e}", flush=True)
+    assert abs(float(J) - Jr) <= 1e-6 * Jr
+    assert _rel_err(gL, gLr) < 1e-4
+    assert _rel_err(gs, gsr) < 1e-4
+
+
 def test_adjoint_subscene_16x256_30_iterations():
     """The differentiation workload's reference check: a 16 x 256 sub-scene of
     the 598 x 4000 scene, 30 iterations, against torch FP64 autograd."""

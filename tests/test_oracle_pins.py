@@ -10,7 +10,7 @@ import pytest
 import scipy.optimize
 
 from oracle.mf64 import (STATUS_FEW_PIXELS, STATUS_NONFINITE, STATUS_OK,
-                         alpha_step, retrieve, retrieve_column)
+                         alpha_step, retrieve, retrieve_column, retrieve_grouped)
 
 
 BRUTE_RTOL = 1e-6   # resolution of the brute-force searches (see below)
@@ -285,6 +285,60 @@ def test_columns_are_independent():
     for c in range(3):
         ac, _ = retrieve_column(L[c], s, 5, lam=1.0)
         np.testing.assert_array_equal(a[c], ac)
+
+
+# ---------------------------------------------------------------------------
+# Detector grouping (Sec. II-E): g adjacent columns share one mean and one
+# covariance.  Pins that do not restate the grouping itself:
+#  * g = 1 is the per-column retrieval;
+#  * a partition made of g identical copies of one column has the same 1/N
+#    means and covariances as the column alone (R2), so every copy gets the
+#    single-column alpha - by induction over the iterations;
+#  * pixels are exchangeable: permuting the columns inside a partition
+#    permutes the outputs;
+#  * the remainder partition of S = 7, g = 3 is the last column alone.
+
+def _group_scene(rng, S=7, N=150, B=8):
+    L = np.stack([_background_column(rng, N, B, 0.3) for _ in range(S)])
+    s = _s(rng, B) * 5
+    for c in range(S):                       # a few plume pixels per column
+        L[c, :6] *= np.exp(800.0 * s)[None, :]
+    return L, s
+
+
+def test_grouping_of_one_is_the_per_column_retrieval():
+    rng = _rng(61)
+    L, s = _group_scene(rng)
+    a1, st1 = retrieve(L, s, 6, lam=0.5)
+    ag, stg = retrieve_grouped(L, s, 6, lam=0.5, group=1)
+    np.testing.assert_array_equal(ag, a1)
+    np.testing.assert_array_equal(stg, st1)
+
+
+def test_grouping_identical_copies_keep_the_column_result():
+    rng = _rng(62)
+    L, s = _group_scene(rng, S=1, N=200)
+    a1, _ = retrieve_column(L[0], s, 8, lam=0.5)
+    Lg = np.repeat(L, 4, axis=0)             # 4 copies in one partition
+    ag, st = retrieve_grouped(Lg, s, 8, lam=0.5, group=4)
+    assert list(st) == [STATUS_OK]
+    for c in range(4):
+        np.testing.assert_allclose(ag[c], a1, rtol=1e-9, atol=1e-9)
+
+
+def test_grouping_permutation_and_remainder():
+    rng = _rng(63)
+    L, s = _group_scene(rng)
+    a, st = retrieve_grouped(L, s, 6, lam=0.5, group=3)
+    assert len(st) == 3                      # partitions {0,1,2}, {3,4,5}, {6}
+    perm = [2, 0, 1, 5, 3, 4, 6]             # permute inside each partition
+    ap, _ = retrieve_grouped(L[perm], s, 6, lam=0.5, group=3)
+    np.testing.assert_allclose(ap, a[perm], rtol=1e-10, atol=1e-10)
+    a6, _ = retrieve_column(L[6], s, 6, lam=0.5)
+    np.testing.assert_array_equal(a[6], a6)
+    # a partition differs from its columns run alone (shared statistics)
+    a0, _ = retrieve_column(L[0], s, 6, lam=0.5)
+    assert np.abs(a[0] - a0).max() > 1e-6
 
 
 # ---------------------------------------------------------------------------

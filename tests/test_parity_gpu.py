@@ -171,3 +171,47 @@ def test_odd_lines_and_unaligned_radiance(cov, offset):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(st.cpu().numpy(), rst)
         assert_fp32_parity(a.cpu().numpy(), ref, label=f"odd lines offset={offset} chunk={chunk}")
+
+
+@pytest.mark.parametrize("cov", EXACT)
+def test_detector_grouping(cov):
+    """Partitions of g = 5 adjacent columns (the last takes the remaining 3)
+    share one mean and covariance (Sec. II-E); masked pixels included."""
+    from oracle.mf64 import retrieve_grouped
+    spec = SceneSpec(13, 400, 74, 3, (500.0, 5000.0), (3.0, 20.0), seed=17, mask_max_frac=0.15)
+    sc = make_scene(spec)
+    S, N, B = sc.radiance.shape
+    L = torch.from_numpy(sc.radiance).to(DEV)
+    s = torch.from_numpy(sc.s).to(DEV)
+    V = torch.from_numpy(sc.valid).to(DEV)
+    ref, rst = retrieve_grouped(sc.radiance, sc.s, 12, 2.0, valid=sc.valid, group=5)
+    assert len(rst) == 3
+    for chunk in (128, 0):
+        a, st = mf.retrieve(L, s, n_iter=12, lam=2.0, cov=cov, valid=V, chunk_lines=chunk, group=5)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(st.cpu().numpy(), rst)
+        assert_fp32_parity(a.cpu().numpy(), ref, label=f"group 5 cov={cov} chunk={chunk}")
+    # two flightlines in one plan: 7 columns -> groups of 3, 3, 1; 4 columns -> 3, 1
+    spec2 = SceneSpec(4, 300, 74, 1, (500.0, 5000.0), (3.0, 20.0), seed=19)
+    sc2 = make_scene(spec2)
+    off = 7 * N + 50
+    total = off + 4 * 300
+    Lb = torch.zeros((total, B), dtype=torch.float32, device=DEV)
+    Lb[:7 * N] = L[:7].reshape(-1, B)
+    Lb[off:] = torch.from_numpy(sc2.radiance.reshape(-1, B)).to(DEV)
+    Vb = torch.ones(total, dtype=torch.uint8, device=DEV)
+    Vb[:7 * N] = V[:7].reshape(-1)
+    plan = mf.Plan([(0, 7, N), (off, 4, 300)], B, 12, 2.0, 1e-9, True, cov, group=3)
+    assert plan.n_columns == 5
+    ws = plan.alloc_workspace(DEV)
+    ab = torch.empty(total, dtype=torch.float32, device=DEV)
+    stb = torch.empty(plan.n_columns, dtype=torch.int32, device=DEV)
+    plan.retrieve(Lb, s, ab, Vb, stb, ws)
+    torch.cuda.synchronize()
+    r1, s1 = retrieve_grouped(sc.radiance[:7], sc.s, 12, 2.0, valid=sc.valid[:7], group=3)
+    r2, s2 = retrieve_grouped(sc2.radiance, sc.s, 12, 2.0, group=3)
+    np.testing.assert_array_equal(stb.cpu().numpy(), np.concatenate([s1, s2]))
+    abh = ab.cpu().numpy()
+    assert_fp32_parity(abh[:7 * N].reshape(7, N), r1, label="batch group 3, flightline 0")
+    assert_fp32_parity(abh[off:].reshape(4, 300), r2, label="batch group 3, flightline 1")
+    plan.close()

@@ -159,6 +159,30 @@ def main():
         plan.close()
         del ws
 
+    # detector grouping (Sec. II-E): partitions of 5 adjacent columns, the
+    # paper's setting for its real flightlines, low-rank form
+    grouped = None
+    if "lowrank" in forms:
+        plan = mf.Plan([(0, S, N)], B, K, lam, eps, True, "lowrank", group=5)
+        ws = plan.alloc_workspace(dev)
+        gst = torch.empty((plan.n_columns,), dtype=torch.int32, device=dev)
+        for _ in range(max(1, args.warmup)):
+            plan.retrieve(L, s, alpha, None, gst, ws)
+        torch.cuda.synchronize()
+        gsteps = max(3, args.steps // 4)
+        t6 = time.perf_counter()
+        for _ in range(gsteps):
+            plan.retrieve(L, s, alpha, None, gst, ws)
+        torch.cuda.synchronize()
+        dtg = (time.perf_counter() - t6) / gsteps
+        grouped = {"workload": f"flightline {S}x{N}x{B}, partitions of 5 columns "
+                               f"({plan.n_columns} partitions), {K} iterations, low-rank form",
+                   "px_per_s": round(n_px / dtg, 1), "ms_per_step": round(1e3 * dtg, 3),
+                   "partitions_failed": int((gst.cpu().numpy() != 0).sum())}
+        log(f"grouped (5 columns): {grouped['px_per_s'] / 1e6:.1f} Mpx/s, {grouped['ms_per_step']:.2f} ms")
+        plan.close()
+        del ws
+
     # forward + backward (hand-written adjoint) on the differentiation scene:
     # 598 x 4000 x 74, 30 iterations, J = sum (alpha - alpha_true)^2
     fwdbwd = None
@@ -283,6 +307,7 @@ def main():
                       "dominant_GBps": round(r["dominant_GBps"], 1),
                       "error_vs_fp64": errors.get(f)} for f, r in results.items()},
     }
+    out["grouped"] = grouped
     out["fwd_bwd"] = fwdbwd
     out["batch"] = batch
     if "bf16" in results and "fp32" in results:

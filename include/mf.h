@@ -203,6 +203,20 @@ MF_API mf_status mf_plan_set_timing(mf_plan plan, int enable);
    Either output pointer may be NULL.  Host pointers. */
 MF_API mf_status mf_plan_kernel_times(mf_plan plan, double* times_ms, int64_t* counts, int n);
 
+/* Ingest: repacks a band-interleaved-by-line cube bil [n_lines][n_bands]
+   [n_samples] (the ENVI "BIL" layout of imaging-spectrometer radiance files,
+   one detector per sample) into the column-contiguous layout mf_retrieve
+   reads: pixel (sample c, line l) goes to radiance[first_px + c * n_lines + l]
+   (n_bands floats), i.e. one flightline of n_samples columns and n_lines lines
+   starting at first_px.  If valid is non-NULL, valid[that pixel] = 0 when any
+   band is NaN or +-Inf, or (use_nodata = 1) equals nodata exactly, else 1
+   (censored samples are excluded from the statistics, Sec. III-C).  Device
+   pointers; bil and radiance must not overlap; enqueued on the stream. */
+MF_API mf_status mf_repack_bil(const float* bil, int64_t n_lines, int32_t n_bands,
+                               int32_t n_samples, float* radiance, uint8_t* valid,
+                               int64_t first_px, int32_t use_nodata, float nodata,
+                               void* stream);
+
 /* Diagnostic: reads n floats of src (device, 16-byte aligned, n a multiple of
    4) once with n_blocks workgroups and discards them, the achievable HBM read
    bandwidth used as the measured ceiling of the streaming passes.  sink

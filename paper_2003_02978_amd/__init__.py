@@ -21,8 +21,8 @@ COV = {"lowrank": 0, "fp64": 1, "fp32": 2, "bf16": 3}
 # Every symbol declared in include/mf.h.
 EXPORTS = ("mf_abi_version", "mf_options_default", "mf_status_str", "mf_last_error",
            "mf_plan_create", "mf_workspace_bytes", "mf_plan_columns", "mf_plan_pixels",
-           "mf_retrieve", "mf_backward", "mf_plan_set_graph", "mf_plan_set_timing", "mf_plan_kernel_times", "mf_stream_read",
-           "mf_plan_destroy")
+           "mf_retrieve", "mf_backward", "mf_plan_set_graph", "mf_plan_set_timing",
+           "mf_plan_kernel_times", "mf_repack_bil", "mf_stream_read", "mf_plan_destroy")
 KERNEL_KINDS = ("pass_gram", "pass_vec", "pass_last", "solve", "other")
 ABI_VERSION = 2          # MF_ABI_VERSION of include/mf.h (mf_options layout)
 
@@ -87,6 +87,8 @@ def load_library(path: str = LIB_PATH):
                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     lib.mf_stream_read.restype = ctypes.c_int
     lib.mf_stream_read.argtypes = [vp, i64, vp, i32, ctypes.POINTER(ctypes.c_float), vp]
+    lib.mf_repack_bil.restype = ctypes.c_int
+    lib.mf_repack_bil.argtypes = [vp, i64, i32, i32, vp, vp, i64, i32, ctypes.c_float, vp]
     if lib.mf_abi_version() != ABI_VERSION:
         raise ImportError(f"libmf.so ABI version {lib.mf_abi_version()}, binding expects {ABI_VERSION}")
     _lib = lib
@@ -242,6 +244,41 @@ def autotune_chunk(flightlines, radiance, s, valid=None, candidates=(512, 1024, 
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1)
     return best, times
+
+
+def repack_bil(bil, radiance=None, valid=None, first_px: int = 0, nodata=None, stream=None):
+    """Band-interleaved-by-line cube bil [n_lines, B, n_samples] (float32,
+    GPU) to the retrieval layout: returns (radiance, valid) where radiance is
+    [n_samples, n_lines, B] (or, if given, the caller's flat buffer written at
+    pixel first_px) and valid the uint8 mask (0 where a band is non-finite or
+    equals nodata), or None if valid is False."""
+    import torch
+    _need(bil, torch.float32, "bil")
+    nl, B, ns = bil.shape
+    if radiance is None:
+        radiance = torch.empty((ns, nl, B), dtype=torch.float32, device=bil.device)
+        first_px = 0
+    else:
+        _need(radiance, torch.float32, "radiance")
+        if radiance.numel() < (first_px + ns * nl) * B:
+            raise ValueError("radiance buffer is too small")
+    if valid is None:
+        valid = torch.empty((first_px + ns * nl,) if first_px else (ns, nl), dtype=torch.uint8,
+                            device=bil.device)
+    elif valid is False:
+        valid = None
+    if valid is not None:
+        _need(valid, torch.uint8, "valid")
+        if valid.numel() < first_px + ns * nl:
+            raise ValueError("valid buffer is too small")
+    if stream is None:
+        stream = torch.cuda.current_stream(bil.device)
+    _check(load_library().mf_repack_bil(bil.data_ptr(), nl, B, ns, radiance.data_ptr(),
+                                        None if valid is None else valid.data_ptr(), first_px,
+                                        0 if nodata is None else 1,
+                                        0.0 if nodata is None else float(nodata),
+                                        stream.cuda_stream))
+    return radiance, valid
 
 
 def stream_read_ms(x, n_blocks: int = 4096) -> float:

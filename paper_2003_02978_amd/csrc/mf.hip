@@ -2173,6 +2173,59 @@ __global__ void __launch_bounds__(kBlock) stream_read_kernel(const float4* __res
   if (acc == 1.2345e-30f) sink[blockIdx.x] = acc;   // keeps the loads alive
 }
 
+// ---------------------------------------------------------------------------
+// Ingest: band-interleaved-by-line cube [line][band][sample] (the ENVI "BIL"
+// layout of imaging-spectrometer radiance files) to the column-contiguous
+// [sample][line][band] layout of the retrieval, optionally with the valid mask
+// (0 where a band is non-finite or equals the no-data value).  A workgroup
+// moves a tile of kRpS samples x kRpL lines through LDS: rows of kRpS samples
+// are read coalesced, and each sample's kRpL x B floats are written as one
+// contiguous run.  The LDS rows are padded by one float (no bank conflicts
+// when a sample's bands are gathered).
+constexpr int kRpS = 64;
+constexpr int kRpL = 2;
+constexpr int kRpRow = kRpS + 1;
+
+__global__ void __launch_bounds__(256) repack_bil_kernel(const float* __restrict__ bil, int64_t n_lines,
+                                                         int B, int n_samples, float* __restrict__ out,
+                                                         uint8_t* __restrict__ valid, int64_t first_px,
+                                                         int use_nodata, float nodata) {
+  extern __shared__ float tile[];                      // [kRpL][B][kRpRow]
+  const int tid = threadIdx.x;
+  const int64_t l0 = (int64_t)blockIdx.x * kRpL;       // lines on x (no 64 K limit)
+  const int s0 = blockIdx.y * kRpS;
+  const int ns = min(kRpS, n_samples - s0);
+  const int nl = (int)min<int64_t>(kRpL, n_lines - l0);
+  // read: rows (line l, band b) of ns samples
+  const int nrows = nl * B;
+  for (int e = tid; e < nrows * kRpS; e += 256) {
+    const int r = e / kRpS, s = e - r * kRpS;
+    if (s < ns) {
+      const int l = r / B, b = r - l * B;
+      tile[(l * B + b) * kRpRow + s] = bil[((l0 + l) * B + b) * (int64_t)n_samples + s0 + s];
+    }
+  }
+  __syncthreads();
+  // write: for each sample, nl consecutive pixels of B floats (one run)
+  const int run = nl * B;
+  for (int e = tid; e < ns * run; e += 256) {
+    const int s = e / run, k = e - s * run;
+    const int l = k / B, b = k - l * B;
+    out[((first_px + (int64_t)(s0 + s) * n_lines + l0) * B) + k] = tile[(l * B + b) * kRpRow + s];
+  }
+  if (valid) {
+    for (int e = tid; e < ns * nl; e += 256) {
+      const int s = e / nl, l = e - s * nl;
+      bool ok = true;
+      for (int b = 0; b < B; ++b) {
+        const float x = tile[(l * B + b) * kRpRow + s];
+        ok = ok && isfinite(x) && !(use_nodata && x == nodata);
+      }
+      valid[first_px + (int64_t)(s0 + s) * n_lines + l0 + l] = ok ? 1 : 0;
+    }
+  }
+}
+
 __global__ void status_kernel(const ColState* __restrict__ state, int32_t* __restrict__ out,
                               int64_t n) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2749,6 +2802,28 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
 mf_status mf_plan_set_graph(mf_plan p, int enable) {
   if (!p) return fail_with(MF_E_ARG, "plan is NULL");
   p->use_graph = enable != 0;
+  return MF_OK;
+}
+
+mf_status mf_repack_bil(const float* bil, int64_t n_lines, int32_t n_bands, int32_t n_samples,
+                        float* radiance, uint8_t* valid, int64_t first_px, int32_t use_nodata,
+                        float nodata, void* stream) {
+  if (!bil || !radiance) return fail_with(MF_E_ARG, "bil or radiance is NULL");
+  if (n_lines < 1 || n_samples < 1 || first_px < 0)
+    return fail_with(MF_E_SHAPE, "n_lines and n_samples must be >= 1, first_px >= 0");
+  if (n_bands < 1 || n_bands > MF_MAX_BANDS)
+    return fail_with(MF_E_UNSUPPORTED, "n_bands must be in [1, 78]");
+  if (use_nodata != 0 && use_nodata != 1) return fail_with(MF_E_ARG, "use_nodata must be 0 or 1");
+  const int64_t ly = (n_lines + kRpL - 1) / kRpL;
+  const int64_t sy = (n_samples + kRpS - 1) / kRpS;
+  if (ly > INT32_MAX || sy > 65535) return fail_with(MF_E_SHAPE, "cube too large for one call");
+  hipStream_t st = (hipStream_t)stream;
+  (void)hipGetLastError();
+  const size_t lds = (size_t)kRpL * n_bands * kRpRow * sizeof(float);
+  const dim3 grid((unsigned)ly, (unsigned)sy);
+  hipLaunchKernelGGL(repack_bil_kernel, grid, dim3(256), lds, st, bil, n_lines, (int)n_bands,
+                     (int)n_samples, radiance, valid, first_px, (int)use_nodata, nodata);
+  if (hipGetLastError() != hipSuccess) return fail_with(MF_E_DEVICE, "repack launch failed");
   return MF_OK;
 }
 

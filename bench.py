@@ -55,6 +55,8 @@ def main():
                     help="skip the forward+backward leg on the 598x4000 differentiation scene")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched leg (32 ragged masked flightlines, ~37 GB)")
+    ap.add_argument("--no-ingest", action="store_true",
+                    help="skip the ingest leg (BIL repack; host-to-device campaign pipeline)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 1 GiB device copies (known bytes) for HBM counter scaling")
     args = ap.parse_args()
@@ -232,6 +234,9 @@ def main():
         plan.close()
         del ws, dL
 
+    ingest = None
+    if not args.no_ingest:
+        ingest = run_ingest(mf, torch, np, dev, sc, K, lam, eps)
     del L, alpha, status
     torch.cuda.empty_cache()
     batch = None
@@ -308,11 +313,82 @@ def main():
                       "error_vs_fp64": errors.get(f)} for f, r in results.items()},
     }
     out["grouped"] = grouped
+    out["ingest"] = ingest
     out["fwd_bwd"] = fwdbwd
     out["batch"] = batch
     if "bf16" in results and "fp32" in results:
         out["bf16_vs_fp32_gram_speedup"] = round(results["bf16"]["px_per_s"] / results["fp32"]["px_per_s"], 3)
     print(json.dumps(out), flush=True)
+
+
+def run_ingest(mf, torch, np, dev, sc, K, lam, eps, n_fl=3):
+    """Ingest of band-interleaved-by-line flightlines: the repack kernel's
+    bandwidth, and a campaign pipeline (host-to-device copy of flightline f+1
+    on a copy stream while flightline f is repacked and retrieved on a
+    compute stream; double-buffered device BIL, events between the streams).
+    The host cube is pinned memory; the end-to-end rate includes the copy."""
+    S, N, B = sc.radiance.shape
+    n_px = S * N
+    bil_host = torch.from_numpy(np.ascontiguousarray(np.transpose(sc.radiance, (1, 2, 0)))).pin_memory()
+    bil = [torch.empty((N, B, S), dtype=torch.float32, device=dev) for _ in range(2)]
+    rad = torch.empty((S, N, B), dtype=torch.float32, device=dev)
+    val = torch.empty((S, N), dtype=torch.uint8, device=dev)
+    s = torch.from_numpy(sc.s).to(dev)
+    alpha = torch.empty((S, N), dtype=torch.float32, device=dev)
+    bil[0].copy_(bil_host)
+    torch.cuda.synchronize()
+    # repack bandwidth (events on the stream the kernel runs on)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    mf.repack_bil(bil[0], rad, val)
+    e0.record()
+    for _ in range(5):
+        mf.repack_bil(bil[0], rad, val)
+    e1.record()
+    torch.cuda.synchronize()
+    rp_ms = e0.elapsed_time(e1) / 5
+    rp_bytes = 2 * n_px * B * 4 + n_px
+    # host-to-device copy alone
+    e0.record()
+    bil[1].copy_(bil_host, non_blocking=True)
+    e1.record()
+    torch.cuda.synchronize()
+    h2d_ms = e0.elapsed_time(e1)
+    plan = mf.Plan([(0, S, N)], B, K, lam, eps, True, "lowrank")
+    ws = plan.alloc_workspace(dev)
+    plan.retrieve(rad, s, alpha, val, None, ws)
+    torch.cuda.synchronize()
+    cp, cs = torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)
+    copied = [torch.cuda.Event() for _ in range(2)]
+    freed = [torch.cuda.Event() for _ in range(2)]
+    t0 = time.perf_counter()
+    for f in range(n_fl):
+        k = f % 2
+        with torch.cuda.stream(cp):
+            if f >= 2:
+                cp.wait_event(freed[k])             # the compute stream is done with it
+            bil[k].copy_(bil_host, non_blocking=True)
+            copied[k].record(cp)
+        with torch.cuda.stream(cs):
+            cs.wait_event(copied[k])
+            mf.repack_bil(bil[k], rad, val, stream=cs)
+            freed[k].record(cs)
+            plan.retrieve(rad, s, alpha, val, None, ws, stream=cs)
+    torch.cuda.synchronize()
+    pipe_s = time.perf_counter() - t0
+    plan.close()
+    del ws, bil, rad, val
+    torch.cuda.empty_cache()
+    res = {"workload": f"{n_fl} flightlines {S}x{N}x{B} from pinned host memory, BIL layout",
+           "repack_ms": round(rp_ms, 4), "repack_GBps": round(rp_bytes / (rp_ms * 1e-3) / 1e9, 1),
+           "h2d_ms_per_flightline": round(h2d_ms, 3),
+           "h2d_GBps": round(n_px * B * 4 / (h2d_ms * 1e-3) / 1e9, 1),
+           "pipeline_ms_per_flightline": round(1e3 * pipe_s / n_fl, 3),
+           "end_to_end_px_per_s": round(n_fl * n_px / pipe_s, 1)}
+    log(f"ingest: repack {res['repack_ms']:.3f} ms = {res['repack_GBps']:.0f} GB/s, "
+        f"H2D {res['h2d_ms_per_flightline']:.1f} ms/flightline ({res['h2d_GBps']:.1f} GB/s), "
+        f"pipeline {res['pipeline_ms_per_flightline']:.1f} ms/flightline, "
+        f"{res['end_to_end_px_per_s'] / 1e6:.1f} Mpx/s end to end")
+    return res
 
 
 def run_batch(mf, torch, np, dev, K, lam, eps, steps, warmup):

@@ -31,6 +31,11 @@ in the design notes of the repository):
       covariance that is not positive definite gets a non-zero status and
       alpha = 0.  A pixel with r_i <= 0 keeps alpha = 0 (it stays in the
       background statistics).
+  R14 the energy monitored per iteration (Eq. 8, Sec. III-B) is the objective
+      the update of R5 minimises: E^k = sum_i 1/2 d_i^T C^k^-1 d_i
+      + r_i w^k_i alpha^k_i with d_i = L_i - r_i alpha^k_i t^k - mu^k, alpha^k
+      as carried into the next iteration (alpha^0 clamped unless K = 0) and
+      w^0 = 0.
 """
 from __future__ import annotations
 
@@ -65,6 +70,16 @@ def _solve_spd(C: np.ndarray, t: np.ndarray) -> np.ndarray:
     return scipy.linalg.cho_solve(cf, t, check_finite=False)
 
 
+def energy_k(X, mu, C, t, r, w, alpha) -> float:
+    """E^k of R14 (Eq. 8 with the 1/2 of R5), from its definition: the
+    residuals d_i formed explicitly and solved against C^k."""
+    d = X - (r * alpha)[:, None] * t[None, :] - mu
+    cf = scipy.linalg.cho_factor(C, lower=True, check_finite=True)
+    quad = np.einsum("ij,ji->i", d, scipy.linalg.cho_solve(cf, d.T, check_finite=False))
+    pen = 0.0 if w is None else float(np.sum(r * w * alpha))
+    return float(0.5 * quad.sum() + pen)
+
+
 def alpha_step(L, mu, C, t, r, w):
     """One albedo-scaled soft-threshold step (Fig. 1, inner loop; Eq. 6, 8).
 
@@ -76,7 +91,8 @@ def alpha_step(L, mu, C, t, r, w):
 
 
 def retrieve_column(L, s, n_iter: int, lam: float = 1.0, eps: float = 1e-9,
-                    albedo: bool = True, valid=None, trace: Optional[List] = None):
+                    albedo: bool = True, valid=None, trace: Optional[List] = None,
+                    energy: Optional[List] = None):
     """Run Fig. 1 on one column.
 
     L      [N, B] radiance (any float dtype; used in float64)
@@ -84,6 +100,7 @@ def retrieve_column(L, s, n_iter: int, lam: float = 1.0, eps: float = 1e-9,
     n_iter number of reweighting iterations K (>= 0)
     lam    weight scale (w = lam / (alpha + eps))
     valid  [N] bool/uint8 or None
+    energy if a list, E^0..E^K (R14) are appended to it
     Returns (alpha [N] float64, status int).
     """
     L = np.asarray(L, dtype=np.float64)
@@ -124,9 +141,13 @@ def retrieve_column(L, s, n_iter: int, lam: float = 1.0, eps: float = 1e-9,
     if trace is not None:
         trace.append(IterState(0, mu.copy(), C.copy(), t.copy(), None, None, alpha.copy()))
     if n_iter == 0:
+        if energy is not None:
+            energy.append(energy_k(X, mu, C, t, r, None, alpha))
         out[idx] = alpha
         return out, STATUS_OK
     alpha = np.maximum(alpha, 0.0)  # R4
+    if energy is not None:
+        energy.append(energy_k(X, mu, C, t, r, None, alpha))
 
     for k in range(1, n_iter + 1):
         # w^k = lam / (alpha^{k-1} + eps)      (Eq. 5, R7)
@@ -153,6 +174,8 @@ def retrieve_column(L, s, n_iter: int, lam: float = 1.0, eps: float = 1e-9,
         if trace is not None:
             trace.append(IterState(k, mu_new.copy(), C.copy(), t.copy(), w.copy(),
                                    alpha.copy(), alpha_new.copy()))
+        if energy is not None:
+            energy.append(energy_k(X, mu_new, C, t, r, w, alpha_new))
         alpha = alpha_new
         mu = mu_new
     out[idx] = alpha

@@ -10,7 +10,7 @@ import pytest
 import scipy.optimize
 
 from oracle.mf64 import (STATUS_FEW_PIXELS, STATUS_NONFINITE, STATUS_OK,
-                         alpha_step, retrieve, retrieve_column, retrieve_grouped)
+                         alpha_step, energy_k, retrieve, retrieve_column, retrieve_grouped)
 
 
 BRUTE_RTOL = 1e-6   # resolution of the brute-force searches (see below)
@@ -339,6 +339,85 @@ def test_grouping_permutation_and_remainder():
     # a partition differs from its columns run alone (shared statistics)
     a0, _ = retrieve_column(L[0], s, 6, lam=0.5)
     assert np.abs(a[0] - a0).max() > 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Energy monitor (Eq. 8 with the 1/2 of R5; R14).
+#  * K = 0, no albedo: the sample covariance gives sum_i (L_i-mu)^T C^-1
+#    (L_i-mu) = N B exactly, and alpha_i = p_i / q, so E^0 = N B/2 - q/2 sum
+#    alpha_i^2 (a dropped 1/2 or a wrong residual breaks it).
+#  * the update minimises E at fixed mu^k, C^k, w^k: moving any alpha^k_i
+#    (within alpha >= 0) cannot lower it.
+#  * the column part used on the GPU: with C^k = C^0 + U S U^T (rank 3),
+#    sum_i (L_i - mu^k)^T C^k^-1 (L_i - mu^k) = N (B - tr(S M)) + N abar^2
+#    e^T M e, M = U^T C^k^-1 U = W - W (I + S W)^-1 S W, W = U^T C^0^-1 U,
+#    e = (1, 1, 0); checked against the direct sum.
+
+def test_energy_closed_form_k0():
+    rng = _rng(71)
+    L = _background_column(rng, 300, 8, 0.0)
+    s = _s(rng, 8) * 5
+    E = []
+    a, st = retrieve_column(L, s, 0, lam=1.0, albedo=False, energy=E)
+    mu = L.mean(axis=0)
+    C = (L - mu).T @ (L - mu) / len(L)
+    t = mu * s
+    q = t @ np.linalg.solve(C, t)
+    assert len(E) == 1
+    np.testing.assert_allclose(E[0], 0.5 * len(L) * 8 - 0.5 * q * np.sum(a ** 2), rtol=1e-10)
+
+
+def test_energy_update_is_a_minimiser():
+    rng = _rng(72)
+    L = _background_column(rng, 250, 8, 0.3)
+    s = _s(rng, 8) * 5
+    L[:10] *= np.exp(700.0 * s)[None, :]
+    trace = []
+    retrieve_column(L, s, 4, lam=0.3, trace=trace)
+    mu0 = L.mean(axis=0)
+    r = L @ mu0 / (mu0 @ mu0)
+    for it in trace[1:]:
+        base = energy_k(L, it.mu, it.C, it.t, r, it.w, it.alpha)
+        act = np.flatnonzero(it.alpha > 0)[:5]
+        zero = np.flatnonzero(it.alpha == 0)[:5]
+        assert len(act) > 0
+        for i in act:
+            for dlt in (1e-3, -1e-3):
+                a2 = it.alpha.copy()
+                a2[i] = max(0.0, a2[i] + dlt * max(1.0, a2[i]))
+                assert energy_k(L, it.mu, it.C, it.t, r, it.w, a2) >= base - 1e-9 * abs(base)
+        for i in zero:
+            a2 = it.alpha.copy()
+            a2[i] = 1e-2
+            assert energy_k(L, it.mu, it.C, it.t, r, it.w, a2) >= base
+
+
+def test_energy_column_term_by_rank3_identity():
+    rng = _rng(73)
+    N, B = 400, 8
+    L = _background_column(rng, N, B, 0.3)
+    s = _s(rng, B) * 5
+    L[:15] *= np.exp(900.0 * s)[None, :]
+    trace = []
+    retrieve_column(L, s, 3, lam=0.2, trace=trace)
+    Lbar = L.mean(axis=0)
+    C0 = (L - Lbar).T @ (L - Lbar) / N
+    r = L @ Lbar / (Lbar @ Lbar)
+    for k in range(1, len(trace)):
+        it, prev = trace[k], trace[k - 1]
+        c = r * it.alpha_prev
+        abar, S2 = c.mean(), np.sum(c * c)
+        m = ((L - Lbar) * c[:, None]).sum(axis=0)
+        U = np.stack([prev.t - it.t, it.t, m], axis=1)
+        S = np.array([[abar ** 2, 0, 0], [0, S2 / N - abar ** 2, -1 / N], [0, -1 / N, 0]])
+        np.testing.assert_allclose(C0 + U @ S @ U.T, it.C, rtol=1e-9, atol=1e-12)
+        W = U.T @ np.linalg.solve(C0, U)
+        M = W - W @ np.linalg.solve(np.eye(3) + S @ W, S @ W)
+        e = np.array([1.0, 1.0, 0.0])
+        fast = N * (B - np.trace(S @ M)) + N * abar ** 2 * (e @ M @ e)
+        D = L - it.mu
+        direct = np.sum(D * np.linalg.solve(it.C, D.T).T)
+        np.testing.assert_allclose(fast, direct, rtol=1e-9)
 
 
 # ---------------------------------------------------------------------------

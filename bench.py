@@ -57,6 +57,10 @@ def main():
                     help="skip the batched leg (32 ragged masked flightlines, ~37 GB)")
     ap.add_argument("--no-ingest", action="store_true",
                     help="skip the ingest leg (BIL repack; host-to-device campaign pipeline)")
+    ap.add_argument("--no-energy", action="store_true",
+                    help="skip the energy-monitor leg (tracking overhead and the long grouped run)")
+    ap.add_argument("--energy-iters", type=int, default=200,
+                    help="iterations of the energy monitor's convergence run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 1 GiB device copies (known bytes) for HBM counter scaling")
     args = ap.parse_args()
@@ -184,6 +188,11 @@ def main():
         log(f"grouped (5 columns): {grouped['px_per_s'] / 1e6:.1f} Mpx/s, {grouped['ms_per_step']:.2f} ms")
         plan.close()
         del ws
+
+    energy = None
+    if "lowrank" in forms and not args.no_energy:
+        energy = run_energy(mf, torch, np, dev, L, s, S, N, B, K, lam, eps, results["lowrank"]["ms_per_step"],
+                            args.energy_iters)
 
     # forward + backward (hand-written adjoint) on the differentiation scene:
     # 598 x 4000 x 74, 30 iterations, J = sum (alpha - alpha_true)^2
@@ -313,12 +322,92 @@ def main():
                       "error_vs_fp64": errors.get(f)} for f, r in results.items()},
     }
     out["grouped"] = grouped
+    out["energy"] = energy
     out["ingest"] = ingest
     out["fwd_bwd"] = fwdbwd
     out["batch"] = batch
     if "bf16" in results and "fp32" in results:
         out["bf16_vs_fp32_gram_speedup"] = round(results["bf16"]["px_per_s"] / results["fp32"]["px_per_s"], 3)
     print(json.dumps(out), flush=True)
+
+
+def _stable_from(E, rtol):
+    """First k such that |E^j - E^{j-1}| <= rtol |E^j| for every j >= k
+    (None if the last step still exceeds it)."""
+    import numpy as np
+    d = np.abs(np.diff(E)) <= rtol * np.abs(E[1:])
+    if not d[-1]:
+        return None
+    k = len(E) - 1
+    while k >= 1 and d[k - 1]:
+        k -= 1
+    return k
+
+
+def run_energy(mf, torch, np, dev, L, s, S, N, B, K, lam, eps, plain_ms, n_long):
+    """The energy monitor (Eq. 8 per iteration, low-rank form): its cost at the
+    flightline workload (K iterations, one partition per column), and a long
+    run of n_long iterations with every detector of the flightline in one
+    partition, reporting E^k and the iteration from which it stays within a
+    relative 1e-6 (and 1e-4) of the previous one; also the per-column run at
+    n_long iterations (fraction of columns stable by iteration 20)."""
+    res = {}
+    alpha = torch.empty((S, N), dtype=torch.float32, device=dev)
+    plan = mf.Plan([(0, S, N)], B, K, lam, eps, True, "lowrank", track_energy=True)
+    ws = plan.alloc_workspace(dev)
+    st = torch.empty((plan.n_columns,), dtype=torch.int32, device=dev)
+    plan.retrieve(L, s, alpha, None, st, ws)
+    torch.cuda.synchronize()
+    steps = 5
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.retrieve(L, s, alpha, None, st, ws)
+        E = plan.energy(ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    res["tracked_ms_per_step"] = round(1e3 * dt, 3)
+    res["untracked_ms_per_step"] = round(plain_ms, 3)
+    res["overhead_frac"] = round(1e3 * dt / plain_ms - 1.0, 4)
+    plan.close()
+    del ws
+    log(f"energy tracking at K={K}: {1e3 * dt:.2f} ms vs {plain_ms:.2f} ms untracked")
+
+    for label, group in (("all_detectors_one_partition", S), ("per_column", 1)):
+        plan = mf.Plan([(0, S, N)], B, n_long, lam, eps, True, "lowrank", track_energy=True, group=group,
+                       chunk_lines=8192 if group > 1 else 0)
+        ws = plan.alloc_workspace(dev)
+        st = torch.empty((plan.n_columns,), dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plan.retrieve(L, s, alpha, None, st, ws)
+        E = plan.energy(ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        E = E.cpu().numpy()
+        ok = st.cpu().numpy() == 0
+        r = {"partitions": plan.n_columns, "partitions_failed": int((~ok).sum()), "iterations": n_long,
+             "ms": round(1e3 * dt, 2)}
+        if group > 1:
+            e = E[:, 0]
+            marks = [k for k in (0, 1, 2, 3, 5, 10, 20, 30, 50, 100, 150, 200, n_long) if k <= n_long]
+            r["E"] = {str(k): float(e[k]) for k in sorted(set(marks))}
+            r["stable_from_rtol_1e-6"] = _stable_from(e, 1e-6)
+            r["stable_from_rtol_1e-4"] = _stable_from(e, 1e-4)
+            log(f"energy, {S} detectors in one partition, {n_long} iterations ({1e3 * dt:.0f} ms): "
+                f"stable within 1e-6 from k={r['stable_from_rtol_1e-6']}, within 1e-4 from "
+                f"k={r['stable_from_rtol_1e-4']}")
+        else:
+            ks = [_stable_from(E[:, c], 1e-6) for c in np.flatnonzero(ok)]
+            k4 = [_stable_from(E[:, c], 1e-4) for c in np.flatnonzero(ok)]
+            r["frac_stable_1e-6_by_20"] = round(float(np.mean([k is not None and k <= 20 for k in ks])), 4)
+            r["frac_stable_1e-4_by_20"] = round(float(np.mean([k is not None and k <= 20 for k in k4])), 4)
+            r["median_stable_from_1e-6"] = float(np.median([k if k is not None else n_long + 1 for k in ks]))
+            log(f"energy, per column, {n_long} iterations ({1e3 * dt:.0f} ms): "
+                f"{100 * r['frac_stable_1e-6_by_20']:.1f}% of columns stable within 1e-6 by k=20")
+        res[label] = r
+        plan.close()
+        del ws
+    return res
 
 
 def run_ingest(mf, torch, np, dev, sc, K, lam, eps, n_fl=3):

@@ -52,7 +52,7 @@ extern "C" {
 #define MF_API
 #endif
 
-#define MF_ABI_VERSION 2
+#define MF_ABI_VERSION 3
 #define MF_MAX_BANDS 78      /* B + 2 <= 80: five 16-band MFMA blocks */
 
 typedef struct mf_plan_s* mf_plan;
@@ -108,6 +108,9 @@ typedef struct {
                              of `group` adjacent columns of a flightline (the
                              last run takes the remainder) shares one mean and
                              covariance; 1 = one partition per column */
+  int32_t  track_energy;  /* 1: mf_retrieve also records the objective E^k of
+                             every iteration (Eq. 8 with the 1/2 of the alpha
+                             update; see mf_plan_energy); needs MF_COV_LOWRANK */
 } mf_options;
 
 typedef struct {
@@ -176,6 +179,19 @@ MF_API mf_status mf_retrieve(mf_plan plan, const float* radiance, const uint8_t*
 MF_API mf_status mf_backward(mf_plan plan, const float* radiance, const uint8_t* valid,
                              const float* s, const float* grad_alpha, float* grad_radiance,
                              double* grad_s, void* workspace, void* stream);
+
+/* Per-iteration energy (Sec. III-B, Eq. 8): after an mf_retrieve of a plan
+   created with track_energy = 1, copies E^0..E^K of every partition into
+   energy_out [K + 1][mf_plan_columns] float64 (device memory), where
+     E^k = sum_i 1/2 (L_i - r_i alpha^k_i t^k - mu^k)^T C^k^-1 (.)
+           + r_i w^k_i alpha^k_i,   w^0 = 0, w^k = lambda / (alpha^{k-1} + eps),
+   the sum over the partition's valid pixels, alpha^0 clamped at 0 when K >= 1
+   (the objective each alpha update minimises with mu^k and C^k held fixed).
+   Entries of a partition whose status is not MF_COL_OK are NaN from the
+   iteration where it failed on.  The retrieval on the same workspace must be
+   ordered before this call on the stream; enqueued on the stream. */
+MF_API mf_status mf_plan_energy(mf_plan plan, const void* workspace, double* energy_out,
+                                void* stream);
 
 /* Graph replay.  While enabled, mf_retrieve captures its launch sequence on
    the caller's stream into a HIP graph the first time it sees a set of

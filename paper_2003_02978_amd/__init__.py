@@ -22,9 +22,10 @@ COV = {"lowrank": 0, "fp64": 1, "fp32": 2, "bf16": 3}
 EXPORTS = ("mf_abi_version", "mf_options_default", "mf_status_str", "mf_last_error",
            "mf_plan_create", "mf_workspace_bytes", "mf_plan_columns", "mf_plan_pixels",
            "mf_retrieve", "mf_backward", "mf_plan_set_graph", "mf_plan_set_timing",
-           "mf_plan_kernel_times", "mf_repack_bil", "mf_stream_read", "mf_plan_destroy")
+           "mf_plan_kernel_times", "mf_plan_energy", "mf_repack_bil", "mf_stream_read",
+           "mf_plan_destroy")
 KERNEL_KINDS = ("pass_gram", "pass_vec", "pass_last", "solve", "other")
-ABI_VERSION = 2          # MF_ABI_VERSION of include/mf.h (mf_options layout)
+ABI_VERSION = 3          # MF_ABI_VERSION of include/mf.h (mf_options layout)
 
 
 class Options(ctypes.Structure):
@@ -33,7 +34,7 @@ class Options(ctypes.Structure):
                 ("lambda_", ctypes.c_double), ("epsilon", ctypes.c_double),
                 ("cov", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
                 ("save_for_backward", ctypes.c_int32), ("chunk_lines", ctypes.c_int32),
-                ("group", ctypes.c_int32)]
+                ("group", ctypes.c_int32), ("track_energy", ctypes.c_int32)]
 
 
 class Flightline(ctypes.Structure):
@@ -87,6 +88,8 @@ def load_library(path: str = LIB_PATH):
                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     lib.mf_stream_read.restype = ctypes.c_int
     lib.mf_stream_read.argtypes = [vp, i64, vp, i32, ctypes.POINTER(ctypes.c_float), vp]
+    lib.mf_plan_energy.restype = ctypes.c_int
+    lib.mf_plan_energy.argtypes = [vp, vp, vp, vp]
     lib.mf_repack_bil.restype = ctypes.c_int
     lib.mf_repack_bil.argtypes = [vp, i64, i32, i32, vp, vp, i64, i32, ctypes.c_float, vp]
     if lib.mf_abi_version() != ABI_VERSION:
@@ -117,7 +120,7 @@ class Plan:
     def __init__(self, flightlines: Iterable[Tuple[int, int, int]], n_bands: int = 74,
                  n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9, albedo: bool = True,
                  cov: str = "lowrank", refine_steps: int = 1, chunk_lines: int = 0,
-                 save_for_backward: bool = False, group: int = 1):
+                 save_for_backward: bool = False, group: int = 1, track_energy: bool = False):
         lib = load_library()
         o = default_options()
         o.n_bands, o.n_iter, o.albedo = n_bands, n_iter, int(bool(albedo))
@@ -125,6 +128,7 @@ class Plan:
         o.refine_steps, o.chunk_lines = refine_steps, chunk_lines
         o.save_for_backward = int(bool(save_for_backward))
         o.group = int(group)
+        o.track_energy = int(bool(track_energy))
         fls = list(flightlines)
         arr = (Flightline * max(1, len(fls)))(*[Flightline(int(a), int(b), int(c)) for a, b, c in fls])
         h = ctypes.c_void_p()
@@ -164,6 +168,19 @@ class Plan:
         c = (ctypes.c_int64 * n)()
         _check(self._lib.mf_plan_kernel_times(self._h, t, c, n))
         return {k: (t[i], int(c[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+    def energy(self, workspace, stream=None):
+        """E^0..E^K of every partition from the last retrieval on `workspace`
+        (a plan made with track_energy=True): float64 [n_iter + 1, n_columns]
+        on the workspace's device, NaN from the iteration a partition failed."""
+        import torch
+        out = torch.empty((self.options.n_iter + 1, self.n_columns), dtype=torch.float64,
+                          device=workspace.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(workspace.device)
+        ws = workspace.data_ptr()
+        _check(self._lib.mf_plan_energy(self._h, (ws + 255) & ~255, out.data_ptr(), stream.cuda_stream))
+        return out
 
     def alloc_workspace(self, device=None):
         import torch

@@ -65,6 +65,7 @@ enum PassMode {
   PM_BF16 = 4    // Gram on v_mfma_f32_16x16x32_bf16, FP64 flush every 256 px
 };
 constexpr int kVecM = 80, kVecS1 = 80, kVecS2 = 81;   // PM_VEC partial layout
+constexpr int kVecE = 82;      // energy: pixel part of E^{j-1} (both streaming modes)
 
 // One partition (Sec. II-E): `group` adjacent detector columns of a
 // flightline, contiguous in memory, solved as one problem.
@@ -106,6 +107,7 @@ struct PassArgs {
   double* partials;          // [item][T][16][16] FP64
   double* p_save;            // save_for_backward: p^{j-1} = (L - mu) . v per pixel (j >= 1)
   int64_t n_floats;          // floats of the radiance array (max_px * B)
+  int track_energy;          // accumulate the pixel part of E^{j-1} (partial slot kVecE)
   double* r_out;             // r per pixel written by this pass (low-rank form, j = 1)
   const double* r_in;        // r per pixel from pass 1, or null: computed here
   int B;
@@ -130,6 +132,7 @@ struct SolveArgs {
   int lowrank;
   int partial_stride;        // doubles per work item in the partial buffer
   double* ck;                // save_for_backward: column checkpoints [K+1][n_cols][kCk]
+  double* energy;            // track_energy: E^k per partition [K+1][n_cols], or null
   int n_cols;
 };
 
@@ -157,7 +160,9 @@ __device__ __forceinline__ float row_sum16(float x) {
 __global__ void __launch_bounds__(64) setup_kernel(const float* __restrict__ L,
                                                    const uint8_t* __restrict__ valid,
                                                    const ColInfo* __restrict__ cols,
-                                                   ColState* __restrict__ state, int B) {
+                                                   ColState* __restrict__ state, int B,
+                                                   double* __restrict__ energy, int K1,
+                                                   int64_t n_cols) {
   const int col = blockIdx.x;
   const int lane = threadIdx.x;
   const ColInfo ci = cols[col];
@@ -187,6 +192,8 @@ __global__ void __launch_bounds__(64) setup_kernel(const float* __restrict__ L,
     st.n_valid = 0.0;
     st.status = z >= 0 ? MF_COL_OK : MF_COL_FEW_PIXELS;
   }
+  if (energy)              // E^k stays NaN for a partition that fails before iteration k
+    for (int k = lane; k < K1; k += 64) energy[(int64_t)k * n_cols + col] = __builtin_nan("");
 }
 
 // ---------------------------------------------------------------------------
@@ -562,7 +569,7 @@ constexpr int kTileF = kF4 * 64 * 4;                  // floats per wave tile
 
 // Dynamic LDS bytes of stream_kernel (about 46 KB).
 __host__ __device__ constexpr size_t stream_lds_bytes(int B) {
-  return (size_t)kSW * kChunk * sizeof(double) + kSW * (kPad + 2) * sizeof(double) +
+  return (size_t)kSW * kChunk * sizeof(double) + kSW * (kPad + 3) * sizeof(double) +
          4 * kPad * sizeof(double) + (size_t)kSW * kTileF * sizeof(float);
 }
 
@@ -577,8 +584,8 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
   const int64_t begin = it.px_begin, end = begin + it.n_px;
   extern __shared__ double dyn[];
   double* cbuf = dyn;                                   // [kSW][kChunk]
-  double* redm = cbuf + kSW * kChunk;                   // [kSW][kPad + 2]
-  double* cst = redm + kSW * (kPad + 2);                // [kPad] v, m0, lbar; mu . v
+  double* redm = cbuf + kSW * kChunk;                   // [kSW][kPad + 3]
+  double* cst = redm + kSW * (kPad + 3);                // [kPad] v, m0, lbar; mu . v
   float* my = reinterpret_cast<float*>(cst + 4 * kPad) + wid * kTileF;   // [kChunk][B]
 
   const int64_t step = (int64_t)kSW * kChunk;
@@ -637,6 +644,7 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
   const int j = a.j;
 
   [[maybe_unused]] double m_lo = 0.0, m_hi = 0.0, s1 = 0.0, s2 = 0.0;
+  double se = 0.0;                       // pixel part of E^{j-1} (R14)
 
   // Scores the chunk at c0 (n pixels, tile in LDS): alpha^{j-1}, and for the
   // low-rank form the moment contributions of the pixels with c != 0.
@@ -708,6 +716,11 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
         if (a.r_out) a.r_out[px] = ok ? r : 0.0;
       }
       c = (ok && !dark && al > 0.0) ? r * al : 0.0;
+      if (a.track_energy && ok && !dark) {
+        // -r a p + 1/2 r^2 a^2 q + r w a, with w^0 = 0
+        const double w = (j == 1) ? 0.0 : lam / (ap + eps);
+        se += r * al * (0.5 * r * al * q - pp + w);
+      }
     }
     if constexpr (MODE == PM_VEC) {
       s1 += c;
@@ -778,24 +791,37 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
     score(c0, n, vld, ap, rp, my);
   }
 
+  if (a.track_energy)
+    for (int off = 32; off >= 1; off >>= 1) se += __shfl_xor(se, off, 64);
   if constexpr (MODE == PM_VEC) {
     for (int off = 32; off >= 1; off >>= 1) {
       s1 += __shfl_xor(s1, off, 64);
       s2 += __shfl_xor(s2, off, 64);
     }
-    double* rw = redm + wid * (kPad + 2);
+    double* rw = redm + wid * (kPad + 3);
     if (lane < kPad) rw[lane] = lane < B ? m_lo : 0.0;
     if (lane + 64 < kPad) rw[lane + 64] = lane + 64 < B ? m_hi : 0.0;
     if (lane == 0) {
       rw[kVecS1] = s1;
       rw[kVecS2] = s2;
+      rw[kVecE] = se;
     }
     __syncthreads();
     double* out = a.partials + (int64_t)blockIdx.x * a.partial_stride;
-    for (int e = tid; e < kPad + 2; e += kSBlock) {
+    for (int e = tid; e < kPad + 3; e += kSBlock) {
       double sum = 0.0;
-      for (int w = 0; w < kSW; ++w) sum += redm[w * (kPad + 2) + e];
+      for (int w = 0; w < kSW; ++w) sum += redm[w * (kPad + 3) + e];
       out[e] = sum;
+    }
+  } else {
+    if (a.track_energy) {                // last pass: only the energy slot
+      if (lane == 0) redm[wid] = se;
+      __syncthreads();
+      if (tid == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < kSW; ++w) sum += redm[w];
+        a.partials[(int64_t)blockIdx.x * a.partial_stride + kVecE] = sum;
+      }
     }
   }
 }
@@ -1220,6 +1246,9 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
       st.q = q;
       if (j == 0) st.n_valid = N;
       if (!(q > 0.0) || !isfinite(q)) st.status = MF_COL_NOT_SPD;
+      // column part of E^0 (R14): the sample covariance gives sum_i
+      // (L_i - mu^0)^T C^0^-1 (L_i - mu^0) = N B
+      else if (j == 0 && a.energy) a.energy[col] = 0.5 * N * (double)B;
     }
   }
   __syncthreads();
@@ -1263,7 +1292,7 @@ struct R3Smem {
   double X3[3 * kPad];
   double vbuf[kPad], rbuf[kPad], wbuf[kPad];
   double prow[3 * kNBlk * kBlk], pcol[3 * kNBlk * kBlk];
-  double S3[9], Ginv[9], zbuf[8];
+  double S3[9], Ginv[9], W3[9], zbuf[8];
   int bad;
 };
 
@@ -1323,6 +1352,8 @@ __device__ void r3_prepare(const double (&Pb)[kBlk][kBlk], bool owner, int bi, i
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c) sm.Ginv[r * 3 + c] = A[r][3 + c];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) sm.W3[e] = W[e];
     }
   }
   __syncthreads();
@@ -1425,8 +1456,10 @@ __global__ void __launch_bounds__(kBlock) lowrank_kernel(SolveArgs a) {
   double Cb[kBlk][kBlk], Pb[kBlk][kBlk];
   load_blocks(a.c0 + (int64_t)col * (kNBlk * 16), a.pinv + (int64_t)col * (kNBlk * 16), owner, tid,
               Cb, Pb);
-  // the column's moments: m (kPad), S1, S2 summed over its work items
-  for (int e = tid; e < kPad + 2; e += kBlock) {
+  // the column's moments: m (kPad), S1, S2 summed over its work items (and
+  // the pixel part of E^{j-1} when the energy is tracked)
+  const int nsum = kPad + (a.energy ? 3 : 2);
+  for (int e = tid; e < nsum; e += kBlock) {
     double acc = 0.0;
     for (int it = 0; it < ci.n_items; ++it) acc += P[it * stride + e];
     sm.X3[e] = acc;                              // scratch until r3_prepare
@@ -1438,6 +1471,7 @@ __global__ void __launch_bounds__(kBlock) lowrank_kernel(SolveArgs a) {
     sc[1] = s1;
     sc[2] = s2;
     rank3_S(sm.S3, s1 / st.n_valid, s2, st.n_valid);
+    if (a.energy) a.energy[(int64_t)(a.j - 1) * a.n_cols + col] += sm.X3[kVecE];
   }
   __syncthreads();
   const double N = sc[0], S1 = sc[1], S2 = sc[2];
@@ -1461,13 +1495,46 @@ __global__ void __launch_bounds__(kBlock) lowrank_kernel(SolveArgs a) {
     if (tid == 0) st.status = MF_COL_NOT_SPD;
     return;
   }
+  if (a.energy && tid == 0) {
+    // column part of E^j (R14): 1/2 sum_i (L_i - mu^j)^T C^j^-1 (L_i - mu^j)
+    //   = N/2 (B - tr(S M)) + N abar^2 / 2 e^T M e,  M = U^T C^j^-1 U = W - W G S W
+    //   (Woodbury with P = C^0^-1, W = U^T P U, G = (I + S W)^-1), e = (1, 1, 0):
+    // mean(L) - mu^j = abar t^{j-1} = abar U e  (Eq. 10)
+    double SW[9], GSW[9], M[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double x = 0.0;
+        for (int k = 0; k < 3; ++k) x += sm.S3[r * 3 + k] * sm.W3[k * 3 + c];
+        SW[r * 3 + c] = x;
+      }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double x = 0.0;
+        for (int k = 0; k < 3; ++k) x += sm.Ginv[r * 3 + k] * SW[k * 3 + c];
+        GSW[r * 3 + c] = x;
+      }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double x = sm.W3[r * 3 + c];
+        for (int k = 0; k < 3; ++k) x -= sm.W3[r * 3 + k] * GSW[k * 3 + c];
+        M[r * 3 + c] = x;
+      }
+    double trSM = 0.0;
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) trSM += sm.S3[r * 3 + k] * M[k * 3 + r];
+    const double eMe = M[0] + M[1] + M[3] + M[4];
+    a.energy[(int64_t)a.j * a.n_cols + col] = 0.5 * N * ((double)B - trSM) + 0.5 * N * abar * abar * eMe;
+  }
   // b = t^j is the second column of U, so P b is the second column of X = P U
   r3_solve(Pb, Cb, owner, bi, bj, tid, B, a.refine, sm.U3 + kPad, sm, sm.X3 + kPad);
   if (wid == 0) {
     const double q = wave_dot(sm.U3 + kPad, sm.vbuf, B, lane);
     if (lane == 0) {
       st.q = q;
-      if (!(q > 0.0) || !isfinite(q)) st.status = MF_COL_NOT_SPD;
+      if (!(q > 0.0) || !isfinite(q)) {
+        st.status = MF_COL_NOT_SPD;
+        if (a.energy) a.energy[(int64_t)a.j * a.n_cols + col] = __builtin_nan("");
+      }
     }
   }
   for (int b = tid; b < kPad; b += kBlock) {
@@ -2226,6 +2293,20 @@ __global__ void __launch_bounds__(256) repack_bil_kernel(const float* __restrict
   }
 }
 
+// Adds the pixel part of E^K (the last streaming pass, partial slot kVecE of
+// each work item) to the column part the last solve wrote, for the columns
+// that finished healthy.
+__global__ void energy_last_kernel(const ColInfo* __restrict__ cols, const ColState* __restrict__ state,
+                                   const double* __restrict__ partials, int64_t stride,
+                                   double* __restrict__ energy_k, int64_t n_cols) {
+  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= n_cols || state[col].status != MF_COL_OK) return;
+  const ColInfo ci = cols[col];
+  double acc = 0.0;
+  for (int it = 0; it < ci.n_items; ++it) acc += partials[(int64_t)(ci.first_item + it) * stride + kVecE];
+  energy_k[col] += acc;
+}
+
 __global__ void status_kernel(const ColState* __restrict__ state, int32_t* __restrict__ out,
                               int64_t n) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2277,6 +2358,7 @@ struct mf_plan_s {
   // save_for_backward: checkpoints and adjoint buffers
   size_t off_r = 0, off_ck_alpha = 0, off_ck_col = 0, off_ck_p = 0, off_bw_px = 0, off_bw_coef = 0, off_bw_u = 0,
          off_bw_col = 0;
+  size_t off_energy = 0;     // track_energy: E^k per partition [K+1][n_cols]
   size_t ws_bytes = 0;
 };
 
@@ -2387,11 +2469,12 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   double* ck_p = p->opt.save_for_backward ? (double*)(ws + p->off_ck_p) : nullptr;
   const int B = p->opt.n_bands;
   const int K = p->opt.n_iter;
+  double* energy = p->opt.track_energy ? (double*)(ws + p->off_energy) : nullptr;
 
   {
     LaunchTimer tm(p, MF_KERNEL_OTHER, st);
     hipLaunchKernelGGL(setup_kernel, dim3((unsigned)p->n_cols), dim3(64), 0, st, radiance, valid,
-                       p->cols_d, state, B);
+                       p->cols_d, state, B, energy, K + 1, p->n_cols);
   }
   PassArgs pa{};
   pa.L = radiance;
@@ -2418,8 +2501,10 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   sa.lowrank = p->opt.cov == MF_COV_LOWRANK;
   sa.ck = p->opt.save_for_backward ? (double*)(ws + p->off_ck_col) : nullptr;
   sa.n_cols = (int)p->n_cols;
+  sa.energy = energy;
   for (int j = 0; j <= K + 1; ++j) {
     pa.j = j;
+    pa.track_energy = (energy && j >= 1) ? 1 : 0;
     pa.unclamped = (j == 1 && K == 0) ? 1 : 0;
     if (ck_alpha) {          // save_for_backward: keep alpha^0..alpha^K
       pa.alpha_prev = j >= 2 ? ck_alpha + (int64_t)(j - 2) * p->max_px : nullptr;
@@ -2450,6 +2535,12 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
         dispatch_solve(p, sa, st);
     }
   }
+  if (energy) {
+    LaunchTimer tm(p, MF_KERNEL_OTHER, st);
+    hipLaunchKernelGGL(energy_last_kernel, dim3((unsigned)((p->n_cols + 255) / 256)), dim3(256), 0, st,
+                       (const ColInfo*)p->cols_d, (const ColState*)state, (const double*)partials,
+                       (int64_t)n_tiles(p->nb) * 256, energy + (int64_t)K * p->n_cols, p->n_cols);
+  }
   if (column_status) {
     const unsigned nb = (unsigned)((p->n_cols + 255) / 256);
     LaunchTimer tm(p, MF_KERNEL_OTHER, st);
@@ -2477,6 +2568,7 @@ void mf_options_default(mf_options* o) {
   o->save_for_backward = 0;
   o->chunk_lines = 0;
   o->group = 1;
+  o->track_energy = 0;
 }
 
 const char* mf_status_str(mf_status s) {
@@ -2521,6 +2613,10 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   if (opt->chunk_lines < 0 || opt->chunk_lines % 128 != 0)
     return fail_with(MF_E_ARG, "chunk_lines must be a non-negative multiple of 128");
   if (opt->group < 1) return fail_with(MF_E_ARG, "group must be >= 1");
+  if (opt->track_energy != 0 && opt->track_energy != 1)
+    return fail_with(MF_E_ARG, "track_energy must be 0 or 1");
+  if (opt->track_energy && opt->cov != MF_COV_LOWRANK)
+    return fail_with(MF_E_UNSUPPORTED, "track_energy needs the low-rank covariance form");
   if (n_fl < 1) return fail_with(MF_E_SHAPE, "need at least one flightline");
 
   const int chunk = opt->chunk_lines ? opt->chunk_lines
@@ -2623,6 +2719,10 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
     off = align256(off + K1 * (size_t)p->n_cols * kPad * sizeof(double));
     p->off_bw_col = off;
     off = align256(off + (size_t)p->n_cols * kBw * sizeof(double));
+  }
+  if (opt->track_energy) {
+    p->off_energy = off;
+    off = align256(off + ((size_t)opt->n_iter + 1) * (size_t)p->n_cols * sizeof(double));
   }
   p->ws_bytes = off;
   *out = p;
@@ -2855,6 +2955,16 @@ mf_status mf_stream_read(const float* src, int64_t n, float* sink, int32_t n_blo
 mf_status mf_plan_set_timing(mf_plan p, int enable) {
   if (!p) return fail_with(MF_E_ARG, "plan is NULL");
   p->timing = enable != 0;
+  return MF_OK;
+}
+
+mf_status mf_plan_energy(mf_plan p, const void* workspace, double* energy_out, void* stream) {
+  if (!p || !workspace || !energy_out) return fail_with(MF_E_ARG, "plan, workspace or energy_out is NULL");
+  if (!p->opt.track_energy) return fail_with(MF_E_STATE, "the plan was created without track_energy");
+  const size_t bytes = ((size_t)p->opt.n_iter + 1) * (size_t)p->n_cols * sizeof(double);
+  if (hipMemcpyAsync(energy_out, (const char*)workspace + p->off_energy, bytes, hipMemcpyDeviceToDevice,
+                     (hipStream_t)stream) != hipSuccess)
+    return fail_with(MF_E_DEVICE, std::string("energy copy: ") + hipGetErrorString(hipGetLastError()));
   return MF_OK;
 }
 

@@ -24,14 +24,14 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(mf.EXPORTS)
-    assert lib.mf_abi_version() == mf.ABI_VERSION == 2
+    assert lib.mf_abi_version() == mf.ABI_VERSION == 3
 
 
 def test_options_default_and_struct_layout():
     o = mf.default_options()
     assert o.struct_size == ctypes.sizeof(mf.Options)
     assert (o.n_bands, o.n_iter, o.albedo, o.cov, o.refine_steps) == (74, 30, 1, 0, 1)
-    assert (o.chunk_lines, o.group, o.save_for_backward) == (0, 1, 0)
+    assert (o.chunk_lines, o.group, o.save_for_backward, o.track_energy) == (0, 1, 0, 0)
     assert o.lambda_ == 1.0 and o.epsilon == 1e-9
 
 
@@ -62,6 +62,7 @@ def _create(**kw):
     ("save_for_backward", 2, mf.MF_E_ARG),
     ("group", 0, mf.MF_E_ARG),
     ("group", -3, mf.MF_E_ARG),
+    ("track_energy", 2, mf.MF_E_ARG),
 ])
 def test_bad_options_rejected_on_host(field, value, code):
     rc, h, msg = _create(**{field: value})
@@ -75,6 +76,13 @@ def test_backward_needs_low_rank_form_and_k_le_30():
     assert rc == mf.MF_E_UNSUPPORTED
     lib = mf.load_library()
     assert lib.mf_backward(None, None, None, None, None, None, None, None, None) == mf.MF_E_ARG
+
+
+def test_energy_needs_low_rank_form():
+    rc, h, msg = _create(track_energy=1, cov=1)
+    assert rc == mf.MF_E_UNSUPPORTED and "low-rank" in msg
+    lib = mf.load_library()
+    assert lib.mf_plan_energy(None, None, None, None) == mf.MF_E_ARG
 
 
 def test_bad_geometry_rejected_on_host():

@@ -216,6 +216,31 @@ __global__ void __launch_bounds__(64) setup_kernel(const float* __restrict__ L,
 // far above 1 and amplifies any rounding, and FP64 costs the same VALU rate
 // as unpacked FP32 on CDNA.
 
+// Loads through a buffer resource that covers [p, p + bytes): offsets at or
+// past the end read zeros (raw buffer range check), so a partial last group
+// or a null pointer (bytes = 0) needs neither a branch nor a select.
+constexpr int kBufWord3 = 0x00020000;
+constexpr int kOffNone = 0x7ffffff0;       // an offset past every resource
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, kBufWord3);
+}
+__device__ __forceinline__ float4 load16(__amdgpu_buffer_rsrc_t rs, int off) {
+  typedef int intx4 __attribute__((ext_vector_type(4)));
+  const intx4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+  return float4{__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z), __int_as_float(v.w)};
+}
+__device__ __forceinline__ float load4(__amdgpu_buffer_rsrc_t rs, int off) {
+  return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+}
+__device__ __forceinline__ double load8(__amdgpu_buffer_rsrc_t rs, int off) {
+  typedef int intx2 __attribute__((ext_vector_type(2)));
+  const intx2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+  return __hiloint2double(v.y, v.x);
+}
+__device__ __forceinline__ uint32_t load1(__amdgpu_buffer_rsrc_t rs, int off) {
+  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0);
+}
+
 template <int NB, bool WIDE>
 __host__ __device__ constexpr int band_of(int k, int c) {
   return WIDE ? (k < 4 ? 4 * c + k : 64 + c) : c + 16 * k;
@@ -236,49 +261,62 @@ __device__ __forceinline__ double row_sum16_f64(double x) {
   return x;
 }
 
-template <int NB, bool WIDE, int S8>
-__device__ __forceinline__ void load_super(const PassArgs& a, int64_t base, int64_t end,
-                                           int row, int c16, float (&Lv)[S8][NB],
-                                           double (&ap)[S8], unsigned& okmask) {
-  static_assert(S8 == 8, "a super-step is 8 sub-steps");
-  okmask = 0;
+// Issues the loads of one super-step (the 32 pixels from base, pixel 4s + row
+// in sub-step s) through buffer resources sized to the pixels that exist:
+// rows past the work item's end, and alpha / valid when their pointer is
+// null, read zeros.  No load is conditional, so the next super-step's loads
+// stay in flight while the current one is computed.  Lane l (mod 32) holds
+// alpha^{j-2} and the valid flag of pixel base + l.
+template <int NB, bool WIDE>
+__device__ __forceinline__ void load_super(const PassArgs& a, int64_t base, int64_t end, int lane,
+                                           int row, int c16, float (&Lv)[8][NB], double& ap,
+                                           uint32_t& vb) {
+  const int B = a.B;
+  const int n = (int)max<int64_t>(0, min<int64_t>(32, end - base));
+  const __amdgpu_buffer_rsrc_t ra = chunk_rsrc(a.alpha_prev ? a.alpha_prev + base : nullptr,
+                                               a.alpha_prev ? n * 8 : 0);
+  const __amdgpu_buffer_rsrc_t rv = chunk_rsrc(a.valid ? a.valid + base : nullptr, a.valid ? n : 0);
+  // one resource per sub-step (its 4 rows, or fewer at the item's end), so
+  // the lane offsets are the same in every sub-step and every range check is
+  // on the offset itself
+  const int o4 = (row * B + 4 * c16) * 4;
+  const int o1 = 64 + c16 < B ? (row * B + 64 + c16) * 4 : kOffNone;
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
-    const int64_t px = base + 4 * s + row;
-    const bool inb = px < end;
-    const float* pl = a.L + px * a.B;
-    if constexpr (WIDE) {
-      float4 v4 = float4{0.f, 0.f, 0.f, 0.f};
-      if (inb) v4 = *reinterpret_cast<const float4*>(pl + 4 * c16);   // 4-byte aligned rows
+    const int rows = __builtin_amdgcn_readfirstlane(max(0, min(4, n - 4 * s)));   // wave-uniform
+    const __amdgpu_buffer_rsrc_t rl = chunk_rsrc(a.L + (base + 4 * s) * B, rows * B * 4);
+    if constexpr (WIDE) {        // bands 4c..4c+3 < 64 <= B never straddle a row
+      const float4 v4 = load16(rl, o4);
       Lv[s][0] = v4.x;
       Lv[s][1] = v4.y;
       Lv[s][2] = v4.z;
       Lv[s][3] = v4.w;
-      Lv[s][4] = (inb && 64 + c16 < a.B) ? pl[64 + c16] : 0.f;
+      Lv[s][4] = load4(rl, o1);
     } else {
 #pragma unroll
       for (int k = 0; k < NB; ++k) {
         const int b = band_of<NB, WIDE>(k, c16);
-        Lv[s][k] = (inb && b < a.B) ? pl[b] : 0.f;
+        Lv[s][k] = load4(rl, b < B ? (row * B + b) * 4 : kOffNone);
       }
     }
-    ap[s] = (inb && a.alpha_prev) ? a.alpha_prev[px] : 0.0;
-    bool ok = inb;
-    if (inb && a.valid) ok = a.valid[px] != 0;
-    okmask |= (ok ? 1u : 0u) << s;
   }
+  ap = load8(ra, (lane & 31) * 8);
+  vb = load1(rv, lane & 31);
 }
 
-template <int NB, bool WIDE, int MODE>
-__global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
+// SCORE: passes j >= 1 (alpha^{j-1} and c = r alpha enter the Gram); pass 0
+// (SCORE = false) is the Gram of the shifted radiance alone.
+template <int NB, bool WIDE, int MODE, bool SCORE>
+__global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && !SCORE) ? 2 : 1) pass_kernel(PassArgs a) {
   constexpr int T = n_tiles(NB);
-  constexpr bool GRAM = MODE >= PM_F64;
+  static_assert(MODE >= PM_F64, "the Gram pass; the streaming passes are stream_kernel");
   constexpr bool F32ACC = MODE == PM_F32 || MODE == PM_BF16;
   constexpr int FLUSH = MODE == PM_BF16 ? 8 : 2;   // super-steps between FP64 flushes
   const WorkItem it = a.items[blockIdx.x];
   const ColState& st = a.state[it.col];
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wid = tid >> 6;
+  const int lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
   const int row = lane >> 4, c16 = lane & 15;
   const int B = a.B;
   const int64_t begin = it.px_begin, end = begin + it.n_px;
@@ -291,63 +329,42 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
     return;
   }
 
-  double mu[NB], vv[NB], tt[NB], m0[NB], lb[NB];
+  [[maybe_unused]] double mu[NB], vv[NB], tt[NB], m0[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     const int b = band_of<NB, WIDE>(k, c16);
     const bool in = b < B;
     mu[k] = in ? st.mu[b] : 0.0;
-    vv[k] = in ? st.v[b] : 0.0;
-    tt[k] = in ? st.t[b] : 0.0;
-    m0[k] = in ? st.m0[b] : 0.0;
-    lb[k] = in ? st.lbar[b] : 0.0;
+    if constexpr (SCORE) {
+      vv[k] = in ? st.v[b] : 0.0;
+      tt[k] = in ? st.t[b] : 0.0;
+      m0[k] = in ? st.m0[b] : 0.0;
+    }
   }
   const double q = st.q;
   const double lam = a.lam, eps = a.eps;
   const int j = a.j;
 
   [[maybe_unused]] floatx4 acc[F32ACC ? T : 1];
-  [[maybe_unused]] doublex4 dacc[GRAM ? T : 1];
-  [[maybe_unused]] double md[NB], s1d = 0.0, s2d = 0.0;
-  if constexpr (GRAM) {
+  doublex4 dacc[T];
 #pragma unroll
-    for (int t = 0; t < T; ++t) dacc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
-  }
+  for (int t = 0; t < T; ++t) dacc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
   if constexpr (F32ACC) {
 #pragma unroll
     for (int t = 0; t < T; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   }
-  if constexpr (MODE == PM_VEC) {
-#pragma unroll
-    for (int k = 0; k < NB; ++k) md[k] = 0.0;
-  }
 
-  // The MFMA-bound Gram passes run one wave per SIMD and prefetch the next
-  // super-step explicitly; the streaming passes keep fewer registers and
-  // hide latency with more waves instead.
-  constexpr bool PREFETCH = GRAM;
-  float Lc[8][NB];
-  double apc[8];
-  unsigned okc = 0;
-  int64_t base = begin + 32 * wid;
-  if (PREFETCH && base < end) load_super<NB, WIDE, 8>(a, base, end, row, c16, Lc, apc, okc);
-  int nsuper = 0;
-
-  for (; base < end; base += 128) {
-    [[maybe_unused]] float Ln[PREFETCH ? 8 : 1][NB];
-    [[maybe_unused]] double apn[PREFETCH ? 8 : 1];
-    [[maybe_unused]] unsigned okn = 0;
-    if constexpr (PREFETCH) {
-      if (base + 128 < end) load_super<NB, WIDE, 8>(a, base + 128, end, row, c16, Ln, apn, okn);
-    } else {
-      load_super<NB, WIDE, 8>(a, base, end, row, c16, Lc, apc, okc);
-    }
-
+  // The MFMA-bound Gram passes run one wave per SIMD: the next super-step's
+  // loads are in flight while the current one is computed, and are waited
+  // for only when they are moved into place after it.
+  [[maybe_unused]] int nsuper = 0;
+  auto compute = [&](const float (&Lc)[8][NB], double apl, uint32_t vbl, int64_t bx) {
     [[maybe_unused]] bf16x8 ybf[NB];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-      const int64_t px = base + 4 * s + row;
-      const bool ok = (okc >> s) & 1u;
+      const int64_t px = bx + 4 * s + row;
+      const uint32_t vb = (uint32_t)__shfl((int)vbl, 4 * s + row, 64);
+      const bool ok = px < end && (a.valid == nullptr || vb != 0u);
       double x[NB], l[NB];
       double pp = 0.0, rr = 0.0;
 #pragma unroll
@@ -357,7 +374,7 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
         x[k] = in ? l[k] - mu[k] : 0.0;
       }
       double c = 0.0;
-      if (j >= 1) {                       // pass 0 only accumulates the Gram
+      if constexpr (SCORE) {              // pass 0 only accumulates the Gram
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
           pp = fma(x[k], vv[k], pp);
@@ -366,7 +383,8 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
         pp = row_sum16_f64(pp);
         rr = row_sum16_f64(rr);
         const double r = a.albedo ? rr : 1.0;
-        const double num = (j == 1) ? pp : pp - lam / (apc[s] + eps);
+        const double ap = __shfl(apl, 4 * s + row, 64);
+        const double num = (j == 1) ? pp : pp - lam / (ap + eps);
         double al = num / (r * q);
         const bool dark = !(r > 0.0);
         if (!a.unclamped) al = al > 0.0 ? al : 0.0;
@@ -377,43 +395,35 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
         }
         c = (ok && !dark && al > 0.0) ? r * al : 0.0;
       }
-      if constexpr (MODE == PM_VEC) {
+      double y[NB];
 #pragma unroll
-        for (int k = 0; k < NB; ++k)
-          md[k] = fma(c, l[k] - lb[k], md[k]);   // c = 0 off valid pixels
-        s1d += c;
-        s2d = fma(c, c, s2d);
+      for (int k = 0; k < NB; ++k) {
+        const int b = band_of<NB, WIDE>(k, c16);
+        if constexpr (SCORE) y[k] = fma(-c, tt[k], x[k]);
+        else y[k] = x[k];
+        if (b == B) y[k] = ok ? 1.0 : 0.0;
+        if (b == B + 1) y[k] = c;
       }
-      if constexpr (GRAM) {
-        double y[NB];
+      if constexpr (MODE == PM_F64) {
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-          const int b = band_of<NB, WIDE>(k, c16);
-          y[k] = fma(-c, tt[k], x[k]);
-          if (b == B) y[k] = ok ? 1.0 : 0.0;
-          if (b == B + 1) y[k] = c;
-        }
-        if constexpr (MODE == PM_F64) {
+        for (int I = 0; I < NB; ++I)
 #pragma unroll
-          for (int I = 0; I < NB; ++I)
+          for (int J = 0; J <= I; ++J)
+            dacc[n_tiles(I) + J] =
+                __builtin_amdgcn_mfma_f64_16x16x4f64(y[I], y[J], dacc[n_tiles(I) + J], 0, 0, 0);
+      } else if constexpr (MODE == PM_F32) {
+        float yf[NB];
 #pragma unroll
-            for (int J = 0; J <= I; ++J)
-              dacc[n_tiles(I) + J] =
-                  __builtin_amdgcn_mfma_f64_16x16x4f64(y[I], y[J], dacc[n_tiles(I) + J], 0, 0, 0);
-        } else if constexpr (MODE == PM_F32) {
-          float yf[NB];
+        for (int k = 0; k < NB; ++k) yf[k] = (float)y[k];
 #pragma unroll
-          for (int k = 0; k < NB; ++k) yf[k] = (float)y[k];
+        for (int I = 0; I < NB; ++I)
 #pragma unroll
-          for (int I = 0; I < NB; ++I)
+          for (int J = 0; J <= I; ++J)
+            acc[n_tiles(I) + J] =
+                __builtin_amdgcn_mfma_f32_16x16x4f32(yf[I], yf[J], acc[n_tiles(I) + J], 0, 0, 0);
+      } else {
 #pragma unroll
-            for (int J = 0; J <= I; ++J)
-              acc[n_tiles(I) + J] =
-                  __builtin_amdgcn_mfma_f32_16x16x4f32(yf[I], yf[J], acc[n_tiles(I) + J], 0, 0, 0);
-        } else {
-#pragma unroll
-          for (int k = 0; k < NB; ++k) ybf[k][s] = (__bf16)(float)y[k];
-        }
+        for (int k = 0; k < NB; ++k) ybf[k][s] = (__bf16)(float)y[k];
       }
     }
     if constexpr (MODE == PM_BF16) {
@@ -435,64 +445,52 @@ __global__ void __launch_bounds__(kBlock, 1) pass_kernel(PassArgs a) {
         }
       }
     }
-    if constexpr (PREFETCH) {
+  };
+
+  int64_t base = begin + 32 * wid;
+  if (base < end) {
+    float LA[8][NB], LB[8][NB];
+    double apA, apB;
+    uint32_t vA, vB;
+    load_super<NB, WIDE>(a, base, end, lane, row, c16, LA, apA, vA);
+    for (; base < end; base += 128) {
+      load_super<NB, WIDE>(a, base + 128, end, lane, row, c16, LB, apB, vB);
+      compute(LA, apA, vA, base);
+      __builtin_amdgcn_sched_barrier(0);   // the copy below waits for the loads
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        apc[s] = apn[s];
+      for (int s = 0; s < 8; ++s)
 #pragma unroll
-        for (int k = 0; k < NB; ++k) Lc[s][k] = Ln[s][k];
-      }
-      okc = okn;
+        for (int k = 0; k < NB; ++k) LA[s][k] = LB[s][k];
+      apA = apB;
+      vA = vB;
     }
   }
 
   double* out = a.partials + (int64_t)blockIdx.x * (T * 256);
-  if constexpr (GRAM) {
-    if constexpr (F32ACC) {
+  if constexpr (F32ACC) {
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dacc[t][i] += (double)acc[t][i];
+  }
+  // Deterministic cross-wave reduction in LDS, wave 0 first.
+  __shared__ double red[T * 256];
+  for (int w = 0; w < 4; ++w) {
+    if (wid == w) {
 #pragma unroll
       for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) dacc[t][i] += (double)acc[t][i];
-    }
-    // Deterministic cross-wave reduction in LDS, wave 0 first.
-    __shared__ double red[T * 256];
-    for (int w = 0; w < 4; ++w) {
-      if (wid == w) {
-#pragma unroll
-        for (int t = 0; t < T; ++t)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            // Where D[m][n] of a tile lives: f32 MFMA lane n + 16 (m / 4),
-            // register m % 4; f64 MFMA lane n + 16 (m % 4), register m / 4.
-            const int m = MODE == PM_F64 ? row + 4 * i : 4 * row + i;
-            const int e = t * 256 + m * 16 + c16;
-            red[e] = (w == 0 ? 0.0 : red[e]) + dacc[t][i];
-          }
-      }
-      __syncthreads();
-    }
-    for (int e = tid; e < T * 256; e += kBlock) out[e] = red[e];
-  } else if constexpr (MODE == PM_VEC) {
-    // 16 (wave, row) partials per band, summed in a fixed order.
-    __shared__ double redv[16 * 82];
-    const int slot = (wid * 4 + row) * 82;
-    for (int b = c16; b < kVecM; b += 16) redv[slot + b] = 0.0;
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      const int b = band_of<NB, WIDE>(k, c16);
-      if (b < B) redv[slot + b] = md[k];
-    }
-    if (c16 == 0) {           // every lane of a row holds the same c
-      redv[slot + kVecS1] = s1d;
-      redv[slot + kVecS2] = s2d;
+        for (int i = 0; i < 4; ++i) {
+          // Where D[m][n] of a tile lives: f32 MFMA lane n + 16 (m / 4),
+          // register m % 4; f64 MFMA lane n + 16 (m % 4), register m / 4.
+          const int m = MODE == PM_F64 ? row + 4 * i : 4 * row + i;
+          const int e = t * 256 + m * 16 + c16;
+          red[e] = (w == 0 ? 0.0 : red[e]) + dacc[t][i];
+        }
     }
     __syncthreads();
-    for (int e = tid; e < 82; e += kBlock) {
-      double sum = 0.0;
-      for (int w = 0; w < 16; ++w) sum += redv[w * 82 + e];
-      out[e] = sum;
-    }
   }
+  for (int e = tid; e < T * 256; e += kBlock) out[e] = red[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -547,19 +545,6 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// 16-byte loads through a buffer resource that covers [p, p + bytes): lanes
-// past the end read zeros (raw buffer range check), so a partial last group
-// needs neither a branch nor a select.
-constexpr int kBufWord3 = 0x00020000;
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const float* p, int bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, bytes, kBufWord3);
-}
-__device__ __forceinline__ float4 load16(__amdgpu_buffer_rsrc_t rs, int off) {
-  typedef int intx4 __attribute__((ext_vector_type(4)));
-  const intx4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-  return float4{__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z), __int_as_float(v.w)};
 }
 
 // A wave's radiance tile: kF4 16-byte groups per lane (a whole chunk of up to
@@ -2402,10 +2387,20 @@ struct LaunchTimer {
 template <int NB, bool WIDE>
 void launch_pass_nb(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t s) {
   const dim3 g((unsigned)p->n_items), b(kBlock);
+  const bool sc = a.j >= 1;
   switch (mode) {
-    case PM_F64: hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F64>), g, b, 0, s, a); break;
-    case PM_F32: hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F32>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16>), g, b, 0, s, a); break;
+    case PM_F64:
+      if (sc) hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F64, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F64, false>), g, b, 0, s, a);
+      break;
+    case PM_F32:
+      if (sc) hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F32, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F32, false>), g, b, 0, s, a);
+      break;
+    default:
+      if (sc) hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16, false>), g, b, 0, s, a);
+      break;
   }
 }
 

@@ -842,6 +842,7 @@ __device__ __forceinline__ double gram_elem(const double* __restrict__ P, int n_
   }
   const int e = (n_tiles(I) + J) * 256 + mi * 16 + mj;
   double g = 0.0;
+#pragma unroll 8
   for (int it = 0; it < n_items; ++it) g += P[(int64_t)it * T * 256 + e];
   return g;
 }
@@ -908,46 +909,59 @@ __device__ __forceinline__ void block_coords(int t, int& bi, int& bj) {
 // y_r = M b_r (r < R) for a symmetric M held as lower 4x4 register blocks:
 // block (bi, bj) of thread t < kNBlk holds M[i][jj] for jj <= i; entries of
 // diagonal blocks above the diagonal and rows or columns >= B are zero, and
-// so are b_r[i >= B].  Vectors are LDS arrays of stride kPad; prow/pcol are
-// LDS scratch of R * kNBlk * kBlk doubles each.  Each row sums its blocks in
-// a fixed order (deterministic).  Contains two barriers.
+// so are b_r[i >= B].  Vectors are LDS arrays of stride kPad.  q is LDS
+// scratch of R * kPad * kNBlkRows doubles: q[r][i][k] is the product of row i
+// with block k of b_r (from block (i/4, k) for k <= i/4, from the transpose of
+// block (k, i/4) above it), so every slot is written once and row i is the
+// sum of its kNBlkRows contiguous partials in a fixed order (deterministic).
+// Contains two barriers.
+constexpr int kSymvScratch = kPad * kNBlkRows;
 template <int R>
 __device__ void block_symv(const double (&M)[kBlk][kBlk], bool owner, int bi, int bj, int tid,
-                           int B, const double* bv, double* yv, double* prow, double* pcol) {
+                           int B, const double* bv, double* yv, double* q) {
   if (owner) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const double* b = bv + r * kPad;
+      double* qr = q + r * kSymvScratch;
+      if (bi == bj) {                 // diagonal block: the full symmetric product
 #pragma unroll
-      for (int x = 0; x < kBlk; ++x) {
-        double s = 0.0;
+        for (int x = 0; x < kBlk; ++x) {
+          double s = 0.0;
 #pragma unroll
-        for (int y = 0; y < kBlk; ++y) s += M[x][y] * b[kBlk * bj + y];
-        prow[(r * kNBlk + tid) * kBlk + x] = s;
-      }
+          for (int y = 0; y < kBlk; ++y) s += (x >= y ? M[x][y] : M[y][x]) * b[kBlk * bj + y];
+          qr[(kBlk * bi + x) * kNBlkRows + bi] = s;
+        }
+      } else {
 #pragma unroll
-      for (int y = 0; y < kBlk; ++y) {
-        double s = 0.0;
+        for (int x = 0; x < kBlk; ++x) {
+          double s = 0.0;
 #pragma unroll
-        for (int x = 0; x < kBlk; ++x)
-          if (kBlk * bi + x > kBlk * bj + y) s += M[x][y] * b[kBlk * bi + x];
-        pcol[(r * kNBlk + tid) * kBlk + y] = s;
+          for (int y = 0; y < kBlk; ++y) s += M[x][y] * b[kBlk * bj + y];
+          qr[(kBlk * bi + x) * kNBlkRows + bj] = s;
+        }
+#pragma unroll
+        for (int y = 0; y < kBlk; ++y) {
+          double s = 0.0;
+#pragma unroll
+          for (int x = 0; x < kBlk; ++x) s += M[x][y] * b[kBlk * bi + x];
+          qr[(kBlk * bj + y) * kNBlkRows + bi] = s;
+        }
       }
     }
   }
   __syncthreads();
   for (int idx = tid; idx < R * kPad; idx += kBlock) {
     const int r = idx / kPad, i = idx - r * kPad;
-    if (i >= B) {
-      yv[r * kPad + i] = 0.0;
-      continue;
+    const double2* p2 = reinterpret_cast<const double2*>(q + r * kSymvScratch + i * kNBlkRows);
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kNBlkRows / 2; ++k) {
+      const double2 v = p2[k];
+      s0 += v.x;
+      s1 += v.y;
     }
-    const int ib = i / kBlk, ix = i % kBlk;
-    double acc = 0.0;
-    for (int c = 0; c <= ib; ++c) acc += prow[(r * kNBlk + ib * (ib + 1) / 2 + c) * kBlk + ix];
-    for (int rr = ib; rr < kNBlkRows; ++rr)
-      acc += pcol[(r * kNBlk + rr * (rr + 1) / 2 + ib) * kBlk + ix];
-    yv[r * kPad + i] = acc;
+    yv[r * kPad + i] = i < B ? s0 + s1 : 0.0;
   }
   __syncthreads();
 }
@@ -974,7 +988,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   __shared__ double Lf[kMaxTri];     // the factor, packed lower triangle
   __shared__ double g1[kPad], g2[kPad], D[kPad], E[kPad], tn[kPad], mun[kPad];
   __shared__ double colk[kPad], vbuf[kPad], rbuf[kPad], invd[kPad];
-  __shared__ double prow[kNBlk * kBlk], pcol[kNBlk * kBlk];
+  __shared__ __align__(16) double qsym[kSymvScratch];
   __shared__ double sc[4];
   __shared__ double sdiag;
   __shared__ int fail;
@@ -1113,12 +1127,12 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
     }
     for (int b = tid; b < kPad; b += kBlock) rbuf[b] = b < B ? tn[b] : 0.0;
     __syncthreads();
-    block_symv<1>(A_, owner, bi, bj, tid, B, rbuf, vbuf, prow, pcol);   // v = P t
+    block_symv<1>(A_, owner, bi, bj, tid, B, rbuf, vbuf, qsym);   // v = P t
     for (int step = 0; step < a.refine; ++step) {
-      block_symv<1>(C_, owner, bi, bj, tid, B, vbuf, colk, prow, pcol);  // C v
+      block_symv<1>(C_, owner, bi, bj, tid, B, vbuf, colk, qsym);  // C v
       for (int b = tid; b < kPad; b += kBlock) rbuf[b] = b < B ? tn[b] - colk[b] : 0.0;
       __syncthreads();
-      block_symv<1>(A_, owner, bi, bj, tid, B, rbuf, colk, prow, pcol);  // P r
+      block_symv<1>(A_, owner, bi, bj, tid, B, rbuf, colk, qsym);  // P r
       for (int b = tid; b < B; b += kBlock) vbuf[b] += colk[b];
       __syncthreads();
     }
@@ -1210,7 +1224,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   }
   __syncthreads();
   for (int step = 0; step < a.refine; ++step) {
-    block_symv<1>(C_, owner, bi, bj, tid, B, vbuf, rbuf, prow, pcol);   // C v
+    block_symv<1>(C_, owner, bi, bj, tid, B, vbuf, rbuf, qsym);   // C v
     for (int b = tid; b < B; b += kBlock) rbuf[b] = tn[b] - rbuf[b];
     __syncthreads();
     if (wid == 0) {
@@ -1276,7 +1290,7 @@ struct R3Smem {
   double U3[3 * kPad];
   double X3[3 * kPad];
   double vbuf[kPad], rbuf[kPad], wbuf[kPad];
-  double prow[3 * kNBlk * kBlk], pcol[3 * kNBlk * kBlk];
+  alignas(16) double qsym[3 * kSymvScratch];
   double S3[9], Ginv[9], W3[9], zbuf[8];
   int bad;
 };
@@ -1286,7 +1300,7 @@ __device__ void r3_prepare(const double (&Pb)[kBlk][kBlk], bool owner, int bi, i
                            int B, R3Smem& sm) {
   const int lane = tid & 63, wid = tid >> 6;
   if (tid == 0) sm.bad = 0;
-  block_symv<3>(Pb, owner, bi, bj, tid, B, sm.U3, sm.X3, sm.prow, sm.pcol);
+  block_symv<3>(Pb, owner, bi, bj, tid, B, sm.U3, sm.X3, sm.qsym);
   if (wid == 0) {
     double W[9];
 #pragma unroll
@@ -1354,7 +1368,7 @@ __device__ void r3_solve(const double (&Pb)[kBlk][kBlk], const double (&Cb)[kBlk
     for (int e = tid; e < kPad; e += kBlock) sm.wbuf[e] = pb[e];
     __syncthreads();
   } else {
-    block_symv<1>(Pb, owner, bi, bj, tid, B, b, sm.wbuf, sm.prow, sm.pcol);   // y = P b
+    block_symv<1>(Pb, owner, bi, bj, tid, B, b, sm.wbuf, sm.qsym);   // y = P b
   }
   for (int step = 0; step <= refine; ++step) {
     if (wid == 0) {
@@ -1378,7 +1392,7 @@ __device__ void r3_solve(const double (&Pb)[kBlk][kBlk], const double (&Cb)[kBlk
     __syncthreads();
     if (step == refine) break;
     // residual r = b - C v, C v = C^0 v + U S U^T v
-    block_symv<1>(Cb, owner, bi, bj, tid, B, sm.vbuf, sm.rbuf, sm.prow, sm.pcol);
+    block_symv<1>(Cb, owner, bi, bj, tid, B, sm.vbuf, sm.rbuf, sm.qsym);
     if (wid == 0) {
       double u[3];
       for (int r = 0; r < 3; ++r) u[r] = wave_dot(sm.U3 + r * kPad, sm.vbuf, B, lane);
@@ -1393,20 +1407,25 @@ __device__ void r3_solve(const double (&Pb)[kBlk][kBlk], const double (&Cb)[kBlk
                                 sm.U3[2 * kPad + e] * sm.zbuf[6])
                          : 0.0;
     __syncthreads();
-    block_symv<1>(Pb, owner, bi, bj, tid, B, sm.rbuf, sm.wbuf, sm.prow, sm.pcol);   // P r
+    block_symv<1>(Pb, owner, bi, bj, tid, B, sm.rbuf, sm.wbuf, sm.qsym);   // P r
   }
 }
 
-// Loads the register blocks of C^0 and P of one column.
+// Loads the register blocks of P and then C^0 of one column: P is needed
+// first (X = P U), C^0 only by the refinement, so its loads stay in flight
+// behind the products with P.  Every thread loads (threads past the owners
+// read block 0 and never use it), so the 32 loads issue back to back.
 __device__ void load_blocks(const double* c0, const double* pinv, bool owner, int tid,
                             double (&Cb)[kBlk][kBlk], double (&Pb)[kBlk][kBlk]) {
+  const int blk = owner ? tid : 0;
 #pragma unroll
   for (int x = 0; x < kBlk; ++x)
 #pragma unroll
-    for (int y = 0; y < kBlk; ++y) {
-      Cb[x][y] = owner ? c0[blk_at(tid, x, y)] : 0.0;
-      Pb[x][y] = owner ? pinv[blk_at(tid, x, y)] : 0.0;
-    }
+    for (int y = 0; y < kBlk; ++y) Pb[x][y] = pinv[blk_at(blk, x, y)];
+#pragma unroll
+  for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+    for (int y = 0; y < kBlk; ++y) Cb[x][y] = c0[blk_at(blk, x, y)];
 }
 
 // S of the rank-3 identity:  N C^j = N C^0 + N a^2 D D^T + (S2 - N a^2) t t^T - (m t^T + t m^T)
@@ -1438,18 +1457,19 @@ __global__ void __launch_bounds__(kBlock) lowrank_kernel(SolveArgs a) {
   int bi = 0, bj = 0;
   const bool owner = tid < kNBlk;
   if (owner) block_coords(tid, bi, bj);
-  double Cb[kBlk][kBlk], Pb[kBlk][kBlk];
-  load_blocks(a.c0 + (int64_t)col * (kNBlk * 16), a.pinv + (int64_t)col * (kNBlk * 16), owner, tid,
-              Cb, Pb);
   // the column's moments: m (kPad), S1, S2 summed over its work items (and
   // the pixel part of E^{j-1} when the energy is tracked)
   const int nsum = kPad + (a.energy ? 3 : 2);
   for (int e = tid; e < nsum; e += kBlock) {
     double acc = 0.0;
+#pragma unroll 8
     for (int it = 0; it < ci.n_items; ++it) acc += P[it * stride + e];
     sm.X3[e] = acc;                              // scratch until r3_prepare
   }
   __syncthreads();
+  double Cb[kBlk][kBlk], Pb[kBlk][kBlk];
+  load_blocks(a.c0 + (int64_t)col * (kNBlk * 16), a.pinv + (int64_t)col * (kNBlk * 16), owner, tid,
+              Cb, Pb);
   if (tid == 0) {
     const double s1 = sm.X3[kVecS1], s2 = sm.X3[kVecS2];
     sc[0] = st.n_valid;
@@ -1961,17 +1981,18 @@ __global__ void __launch_bounds__(kBlock) bwd_colA_kernel(BwColArgs a) {
   int bi = 0, bj = 0;
   const bool owner = tid < kNBlk;
   if (owner) block_coords(tid, bi, bj);
-  double Cb[kBlk][kBlk], Pb[kBlk][kBlk];
-  load_blocks(a.c0 + (int64_t)col * (kNBlk * 16), a.pinv + (int64_t)col * (kNBlk * 16), owner, tid,
-              Cb, Pb);
   const double q = ck[kCkScal + 2], N = ck[kCkScal + 3];
   // pass A sums over the column's work items: V (kPad), Q1, P1
   for (int e = tid; e < kPad + 2; e += kBlock) {
     double acc = 0.0;
+#pragma unroll 8
     for (int it = 0; it < ci.n_items; ++it) acc += P[it * stride + e];
     sm.X3[e] = acc;                              // scratch until r3_prepare
   }
   __syncthreads();
+  double Cb[kBlk][kBlk], Pb[kBlk][kBlk];
+  load_blocks(a.c0 + (int64_t)col * (kNBlk * 16), a.pinv + (int64_t)col * (kNBlk * 16), owner, tid,
+              Cb, Pb);
   if (tid == 0) {
     sc[0] = sm.X3[kBwQ1];
     sc[1] = sm.X3[kBwP1];

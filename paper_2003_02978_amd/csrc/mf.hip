@@ -971,7 +971,7 @@ constexpr int kCkMu = 0, kCkT = kPad, kCkV = 2 * kPad, kCkM = 3 * kPad, kCkScal 
 constexpr int kCk = 4 * kPad + 8;
 
 template <int NB, bool WIDE>
-__global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
+__global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
   const int col = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
@@ -1066,49 +1066,142 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(SolveArgs a) {
   }
 
   if (a.lowrank) {
-    // ---- low-rank form, pass 0: invert C^0 by symmetric sweeps on the
-    // register blocks (A <- -A^-1 after all pivots) and keep C^0 and its
-    // inverse for the rank-3 solves of later iterations.
-    for (int k = 0; k < B; ++k) {
-      const int kb = k >> 2, ka = k & 3;
-      if (owner && bi == kb && bj == kb) {
-        double dkk = 0.0;
+    // ---- low-rank form, pass 0: invert C^0 by a blocked symmetric sweep on
+    // the 4x4 register blocks (A <- -A^-1 after all pivot blocks) and keep
+    // C^0 and its inverse for the rank-3 solves of later iterations.  For
+    // pivot block K with D = A_KK = L L^T and Y_i = A_iK L^-T:
+    //   A_ij -= Y_i Y_j^T,  A_iK <- Y_i L^-1 (= A_iK D^-1),  A_KK <- -L^-T L^-1,
+    // the four scalar sweeps of the block in one step; going through the
+    // Cholesky factor of D (not D^-1) keeps the accuracy of the scalar
+    // sweeps when adjacent bands make D ill-conditioned.  Block column K is
+    // published by its owners right after their update of pivot block K - 1,
+    // into alternating LDS buffers: one barrier per pivot block.  Padding
+    // rows (>= B) are decoupled with unit diagonal.
+    if (owner && bi == bj) {                // full symmetric diagonal blocks
+#pragma unroll
+      for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+        for (int y = x + 1; y < kBlk; ++y) A_[x][y] = A_[y][x];
+    }
+    double* cb0 = Lf;                       // two [kNBlkRows][4][4] buffers
+    double* cb1 = Lf + kNBlkRows * 16;
+    auto publish = [&](int K, double* cb) {
+      if (owner && bj == K) {               // A_iK, i >= K
 #pragma unroll
         for (int x = 0; x < kBlk; ++x)
-          if (x == ka) dkk = A_[x][x];
-        sdiag = dkk;
+#pragma unroll
+          for (int y = 0; y < kBlk; ++y) cb[bi * 16 + x * 4 + y] = A_[x][y];
+      } else if (owner && bi == K) {        // A_jK = A_Kj^T, j < K
+#pragma unroll
+        for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+          for (int y = 0; y < kBlk; ++y) cb[bj * 16 + y * 4 + x] = A_[x][y];
       }
-      __syncthreads();
-      const double d = sdiag;
-      if (!(d > 0.0) || !isfinite(d)) {      // uniform
+    };
+    const int nkb = (B + kBlk - 1) / kBlk;
+    publish(0, cb0);
+    __syncthreads();
+    for (int K = 0; K < nkb; ++K) {
+      const double* cb = (K & 1) ? cb1 : cb0;
+      // D = L L^T and W = L^-1 (lower), every thread (same result)
+      // (only the lower triangles of Lc and W are set and read)
+      double Lc[kBlk][kBlk], W[kBlk][kBlk];
+      bool spd = true;
+#pragma unroll
+      for (int c = 0; c < kBlk; ++c) {
+        double d = cb[K * 16 + c * 4 + c];
+#pragma unroll
+        for (int z = 0; z < c; ++z) d = fma(-Lc[c][z], Lc[c][z], d);
+        spd = spd && d > 0.0 && isfinite(d);
+        const double l = sqrt(d), rl = 1.0 / l;
+        Lc[c][c] = l;
+#pragma unroll
+        for (int r = c + 1; r < kBlk; ++r) {
+          double e = cb[K * 16 + r * 4 + c];
+#pragma unroll
+          for (int z = 0; z < c; ++z) e = fma(-Lc[r][z], Lc[c][z], e);
+          Lc[r][c] = e * rl;
+        }
+      }
+      if (!spd) {                            // uniform
         if (tid == 0) st.status = MF_COL_NOT_SPD;
         return;
       }
-      if (owner) {                           // publish row/column k
 #pragma unroll
-        for (int x = 0; x < kBlk; ++x)
+      for (int c = 0; c < kBlk; ++c) {
+        W[c][c] = 1.0 / Lc[c][c];
 #pragma unroll
-          for (int y = 0; y < kBlk; ++y) {
-            const int i = kBlk * bi + x, jj = kBlk * bj + y;
-            if (jj == k && i > k && i < B) colk[i] = A_[x][y];
-            if (i == k && jj < k) colk[jj] = A_[x][y];
-          }
+        for (int r = c + 1; r < kBlk; ++r) {
+          double e = 0.0;
+#pragma unroll
+          for (int z = c; z < r; ++z) e = fma(Lc[r][z], W[z][c], e);
+          W[r][c] = -e / Lc[r][r];
+        }
       }
-      __syncthreads();
-      const double inv = 1.0 / d;
       if (owner) {
+        // Y = C W^T for the block rows this thread needs (C = A_iK from LDS)
+        auto ymul = [&](int blk, double (&Y)[kBlk][kBlk]) {
 #pragma unroll
-        for (int x = 0; x < kBlk; ++x)
+          for (int x = 0; x < kBlk; ++x) {
+            double c[kBlk];
 #pragma unroll
-          for (int y = 0; y < kBlk; ++y) {
-            const int i = kBlk * bi + x, jj = kBlk * bj + y;
-            if (i >= B || jj > i) continue;
-            if (i == k && jj == k) A_[x][y] = -inv;
-            else if (jj == k) A_[x][y] = colk[i] * inv;
-            else if (i == k) A_[x][y] = colk[jj] * inv;
-            else A_[x][y] -= colk[i] * colk[jj] * inv;
+            for (int z = 0; z < kBlk; ++z) c[z] = cb[blk * 16 + x * 4 + z];
+#pragma unroll
+            for (int y = 0; y < kBlk; ++y) {
+              double t = 0.0;
+#pragma unroll
+              for (int z = 0; z <= y; ++z) t = fma(c[z], W[y][z], t);
+              Y[x][y] = t;
+            }
           }
+        };
+        if (bi != K && bj != K) {
+          double Yi[kBlk][kBlk], Yj[kBlk][kBlk];
+          ymul(bi, Yi);
+          ymul(bj, Yj);
+#pragma unroll
+          for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+            for (int y = 0; y < kBlk; ++y) {
+              double t = A_[x][y];
+#pragma unroll
+              for (int z = 0; z < kBlk; ++z) t = fma(-Yi[x][z], Yj[y][z], t);
+              A_[x][y] = t;
+            }
+        } else if (bi == K && bj == K) {     // -W^T W (W lower: z >= max(x, y))
+#pragma unroll
+          for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+            for (int y = 0; y < kBlk; ++y) {
+              double t = 0.0;
+#pragma unroll
+              for (int z = (x > y ? x : y); z < kBlk; ++z) t = fma(W[z][x], W[z][y], t);
+              A_[x][y] = -t;
+            }
+        } else {
+          // column block (bj == K): A_iK <- Y_i W;  row block (bi == K):
+          // A_Kj <- (Y_j W)^T
+          double Y[kBlk][kBlk];
+          ymul(bj == K ? bi : bj, Y);
+          double R[kBlk][kBlk];
+#pragma unroll
+          for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+            for (int y = 0; y < kBlk; ++y) {
+              double t = 0.0;
+#pragma unroll
+              for (int z = y; z < kBlk; ++z) t = fma(Y[x][z], W[z][y], t);
+              R[x][y] = t;
+            }
+          const bool colblk = bj == K;
+#pragma unroll
+          for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+            for (int y = 0; y < kBlk; ++y) A_[x][y] = colblk ? R[x][y] : R[y][x];
+        }
       }
+      if (K + 1 < nkb) publish(K + 1, (K & 1) ? cb0 : cb1);
+      __syncthreads();
     }
     // P = (C^0)^-1; rows/columns >= B zero
 #pragma unroll

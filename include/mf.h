@@ -152,7 +152,7 @@ MF_API int64_t mf_plan_pixels(mf_plan plan);
                     float-aligned pointer (16-byte alignment is not required)
      valid          [max_px] uint8, nonzero = valid pixel, or NULL (all valid).
                     Invalid pixels are excluded from every mean and covariance
-                    (censored data is skipped, Sec. III-C) and get alpha = 0;
+                    (censored data is skipped, Sec. III-A) and get alpha = 0;
                     their radiance values are ignored (the memory must exist).
      s              [B] float32 unit absorption spectrum, (ppm*m)^-1 (Sec. II-D)
      alpha          [max_px] float32 output, ppm*m; only the plan's pixels are written
@@ -226,7 +226,7 @@ MF_API mf_status mf_plan_kernel_times(mf_plan plan, double* times_ms, int64_t* c
    (n_bands floats), i.e. one flightline of n_samples columns and n_lines lines
    starting at first_px.  If valid is non-NULL, valid[that pixel] = 0 when any
    band is NaN or +-Inf, or (use_nodata = 1) equals nodata exactly, else 1
-   (censored samples are excluded from the statistics, Sec. III-C).  Device
+   (censored samples are excluded from the statistics, Sec. III-A).  Device
    pointers; bil and radiance must not overlap; enqueued on the stream. */
 MF_API mf_status mf_repack_bil(const float* bil, int64_t n_lines, int32_t n_bands,
                                int32_t n_samples, float* radiance, uint8_t* valid,

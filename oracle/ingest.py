@@ -5,7 +5,7 @@ benchmark may use it.
 A BIL cube holds, for each line, each band's row of samples: bil[l, b, s].
 The retrieval reads radiance[s, l, b] (each detector column contiguous).
 Censored values (non-finite, or equal to the no-data value) make the pixel
-invalid; invalid pixels are skipped by the statistics (Sec. III-C).
+invalid; invalid pixels are skipped by the statistics (Sec. III-A).
 """
 from __future__ import annotations
 

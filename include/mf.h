@@ -234,10 +234,13 @@ MF_API mf_status mf_repack_bil(const float* bil, int64_t n_lines, int32_t n_band
                                void* stream);
 
 /* Diagnostic: reads n floats of src (device, 16-byte aligned, n a multiple of
-   4) once with n_blocks workgroups and discards them, the achievable HBM read
-   bandwidth used as the measured ceiling of the streaming passes.  sink
-   (device, n_blocks floats) is never written in practice.  If ms_out (host) is
-   non-NULL the call waits and stores the kernel time measured with HIP events. */
+   4) once with n_blocks workgroups, each reading a contiguous span of about
+   n / n_blocks floats (at most 2^29) with the streaming passes' non-temporal
+   loads, and discards them: the achievable HBM read bandwidth used as the
+   measured ceiling of the streaming passes.  sink (device, n_blocks floats) is
+   never written in practice.  If ms_out (host) is non-NULL the call waits and
+   stores the kernel time measured with HIP events.  MF_E_ARG for a span over
+   2^29 floats. */
 MF_API mf_status mf_stream_read(const float* src, int64_t n, float* sink, int32_t n_blocks,
                                 float* ms_out, void* stream);
 

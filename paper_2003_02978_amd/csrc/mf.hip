@@ -221,24 +221,31 @@ __global__ void __launch_bounds__(64) setup_kernel(const float* __restrict__ L,
 // or a null pointer (bytes = 0) needs neither a branch nor a select.
 constexpr int kBufWord3 = 0x00020000;
 constexpr int kOffNone = 0x7ffffff0;       // an offset past every resource
+// Cache policy of the streaming loads: non-temporal.  Every pass reads the
+// radiance (and the per-pixel vectors) exactly once, and the hint lets the
+// loads stream past the caches: a plain contiguous read of a flightline runs
+// at about 6.1 TB/s with it off and 7.0 TB/s with it on.
+constexpr int kLoadNT = 2;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const void* p, int bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, kBufWord3);
 }
 __device__ __forceinline__ float4 load16(__amdgpu_buffer_rsrc_t rs, int off) {
   typedef int intx4 __attribute__((ext_vector_type(4)));
-  const intx4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+  const intx4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kLoadNT);
   return float4{__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z), __int_as_float(v.w)};
 }
 __device__ __forceinline__ float load4(__amdgpu_buffer_rsrc_t rs, int off) {
-  return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+  return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, kLoadNT));
 }
 __device__ __forceinline__ double load8(__amdgpu_buffer_rsrc_t rs, int off) {
   typedef int intx2 __attribute__((ext_vector_type(2)));
-  const intx2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+  const intx2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, kLoadNT);
   return __hiloint2double(v.y, v.x);
 }
+template <typename T>
+__device__ __forceinline__ T ntl(const T* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ uint32_t load1(__amdgpu_buffer_rsrc_t rs, int off) {
-  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0);
+  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, kLoadNT);
 }
 
 template <int NB, bool WIDE>
@@ -594,10 +601,13 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
   uint32_t vld_n = 1;
   double ap_n = 0.0, rp_n = 0.0;
   const bool fast = c0 < end && span_ok(c0);
+  // lane l and l + 32 load pixel l of the chunk (only lanes < kChunk score),
+  // so no load reaches past the chunk
+  const int pl = lane & (kChunk - 1);
   if (fast) {
-    vld_n = a.valid ? (uint32_t)a.valid[c0 + lane] : 1u;
-    ap_n = a.alpha_prev ? a.alpha_prev[c0 + lane] : 0.0;
-    rp_n = a.r_in ? a.r_in[c0 + lane] : 0.0;
+    vld_n = a.valid ? (uint32_t)ntl(a.valid + c0 + pl) : 1u;
+    ap_n = a.alpha_prev ? ntl(a.alpha_prev + c0 + pl) : 0.0;
+    rp_n = a.r_in ? ntl(a.r_in + c0 + pl) : 0.0;
     const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(a.L + (c0 * B - shift), n4 * 16);
 #pragma unroll
     for (int k = 0; k < kF4; ++k) pre[k] = load16(rs, (lane + 64 * k) * 16);
@@ -637,24 +647,30 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
   // it in pass 1 and later passes read it (r_in), so their band loop reads
   // only v.  p = L . v - mu . v, with even and odd bands on two FMA chains.
   const bool own_r = a.r_in == nullptr;
+  // Lanes l and l + 32 share pixel l of the chunk: the lower lane runs the
+  // bands [0, h), the upper one [h, B), and the two partial dot products are
+  // added across the halves; every later step of the score is the lower
+  // lane's (the upper lanes hold the same values and store nothing).
+  const int hsplit = ((B + 3) / 4) * 2;        // even, so both halves start on a pair
+  const int upper = lane >> 5;
   auto score = [&](int64_t c0, int n, uint32_t vld, double ap, double rp, const float* tl) {
-    const int64_t px = c0 + lane;
-    const bool inb = lane < n;
+    const int pxl = lane & (kChunk - 1);
+    const int64_t px = c0 + pxl;
+    const bool inb = pxl < n;
     const bool ok = inb && vld != 0;
-    double pp = 0.0, rr = 0.0;
+    double pe = 0.0, po = 0.0, re = 0.0, ro = 0.0;
     if (ok) {
-      const float* rowp = tl + lane * B;
+      const float* rowp = tl + pxl * B;
       const double2* v2 = reinterpret_cast<const double2*>(cst);
       const double2* m2 = reinterpret_cast<const double2*>(cst + kPad);
-      double pe = 0.0, po = 0.0;
-      int b = 0;
+      int b = upper ? hsplit : 0;
+      const int bend = upper ? B : hsplit;
       // pairs of bands need 8-byte aligned rows (B even, tile 8-byte aligned)
       const bool pairs = (B & 1) == 0 && (reinterpret_cast<uintptr_t>(tl) & 7) == 0;
       if (own_r) {
-        double re = 0.0, ro = 0.0;
         if (pairs) {                          // 8-byte tile reads
 #pragma unroll 4
-          for (; b < B; b += 2) {
+          for (; b + 1 < bend; b += 2) {
             const float2 l2 = *reinterpret_cast<const float2*>(rowp + b);
             const double2 cv = v2[b >> 1], cm = m2[b >> 1];
             const double l0 = (double)l2.x, l1 = (double)l2.y;
@@ -664,17 +680,16 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
             ro = fma(l1, cm.y, ro);
           }
         }
-        for (; b < B; ++b) {
+        for (; b < bend; ++b) {
           const double l = (double)rowp[b];
           pe = fma(l, cst[b], pe);
           re = fma(l, cst[kPad + b], re);
         }
-        rr = re + ro;
       } else {
         if (pairs) {
-          double2 cv = v2[0];
+          double2 cv = v2[b >> 1];
 #pragma unroll 4
-          for (; b < B; b += 2) {
+          for (; b + 1 < bend; b += 2) {
             const double2 nv = v2[(b >> 1) + 1];   // next pair, in flight (kPad > B)
             const float2 l2 = *reinterpret_cast<const float2*>(rowp + b);
             pe = fma((double)l2.x, cv.x, pe);
@@ -682,10 +697,13 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
             cv = nv;
           }
         }
-        for (; b < B; ++b) pe = fma((double)rowp[b], cst[b], pe);
+        for (; b < bend; ++b) pe = fma((double)rowp[b], cst[b], pe);
       }
-      pp = (pe + po) - muv;
     }
+    double pp = pe + po, rr = re + ro;
+    pp += __shfl_xor(pp, 32, 64);               // both halves of the pixel's bands
+    if (own_r) rr += __shfl_xor(rr, 32, 64);
+    pp -= muv;
     double c = 0.0;
     if (j >= 1) {
       const double r = own_r ? (a.albedo ? rr : 1.0) : rp;
@@ -694,14 +712,14 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
       const bool dark = !(r > 0.0);
       if (!a.unclamped) al = al > 0.0 ? al : 0.0;
       if (!ok || dark) al = 0.0;
-      if (inb) {
+      if (inb && !upper) {
         if (a.alpha_out) a.alpha_out[px] = al;
         if (a.alpha_final) a.alpha_final[px] = (float)al;
         if (a.p_save) a.p_save[px] = ok ? pp : 0.0;
         if (a.r_out) a.r_out[px] = ok ? r : 0.0;
       }
-      c = (ok && !dark && al > 0.0) ? r * al : 0.0;
-      if (a.track_energy && ok && !dark) {
+      c = (ok && !dark && al > 0.0 && !upper) ? r * al : 0.0;
+      if (a.track_energy && ok && !dark && !upper) {
         // -r a p + 1/2 r^2 a^2 q + r w a, with w^0 = 0
         const double w = (j == 1) ? 0.0 : lam / (ap + eps);
         se += r * al * (0.5 * r * al * q - pp + w);
@@ -750,10 +768,10 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
       const bool more = nx < end && span_ok(nx);
       {                                       // in flight while this chunk is scored
         const int64_t cn = more ? nx : c0;
-        const int64_t pn = cn + (more ? lane : 0);
-        vld_n = a.valid ? (uint32_t)a.valid[pn] : 1u;
-        ap_n = a.alpha_prev ? a.alpha_prev[pn] : 0.0;
-        rp_n = a.r_in ? a.r_in[pn] : 0.0;
+        const int64_t pn = cn + (more ? pl : 0);
+        vld_n = a.valid ? (uint32_t)ntl(a.valid + pn) : 1u;
+        ap_n = a.alpha_prev ? ntl(a.alpha_prev + pn) : 0.0;
+        rp_n = a.r_in ? ntl(a.r_in + pn) : 0.0;
         const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(a.L + (cn * B - shift), more ? n4 * 16 : 16);
 #pragma unroll
         for (int k = 0; k < kF4; ++k) pre[k] = load16(rs, (lane + 64 * k) * 16);
@@ -767,8 +785,8 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
   // synchronous copies
   for (; c0 < end; c0 += step) {
     const int n = (int)min<int64_t>(kChunk, end - c0);
-    const int64_t px = c0 + lane;
-    const bool inb = lane < n;
+    const int64_t px = c0 + pl;
+    const bool inb = pl < n;
     const uint32_t vld = (inb && a.valid) ? (uint32_t)a.valid[px] : 1u;
     const double ap = (inb && a.alpha_prev) ? a.alpha_prev[px] : 0.0;
     const double rp = (inb && a.r_in) ? a.r_in[px] : 0.0;
@@ -1874,8 +1892,9 @@ __global__ void __launch_bounds__(kSBlock) bwd_passB_kernel(BwArgs a) {
   uint32_t vld_n = 1;
   double pp_n = 0.0, r_n = 0.0, am_n = 0.0, pb_n = 0.0, ab_n = 0.0, rb_n = 0.0;
   const bool fast = c0 < end && span_ok(c0);
+  const int pl = lane & (kChunk - 1);     // only lanes < kChunk score
   if (fast) {
-    const int64_t px = c0 + lane;
+    const int64_t px = c0 + pl;
     vld_n = a.valid ? (uint32_t)a.valid[px] : 1u;
     pp_n = a.p_k[px];
     r_n = a.r_px[px];
@@ -1980,7 +1999,7 @@ __global__ void __launch_bounds__(kSBlock) bwd_passB_kernel(BwArgs a) {
       const bool more = nx < end && span_ok(nx);
       {                                       // in flight while this chunk is scored
         const int64_t cn = more ? nx : c0;
-        const int64_t pn = cn + (more ? lane : 0);
+        const int64_t pn = cn + (more ? pl : 0);
         vld_n = a.valid ? (uint32_t)a.valid[pn] : 1u;
         pp_n = a.p_k[pn];
         r_n = a.r_px[pn];
@@ -2325,16 +2344,21 @@ __global__ void __launch_bounds__(256) bwd_sbar_kernel(const ColState* state, co
 
 // Plain streaming read: the achievable HBM read bandwidth for this access
 // size, used as the measured ceiling next to the nominal 8 TB/s.
-__global__ void __launch_bounds__(kBlock) stream_read_kernel(const float4* __restrict__ src,
-                                                             int64_t n4, float* __restrict__ sink) {
+__global__ void __launch_bounds__(kBlock) stream_read_kernel(const float* __restrict__ src, int64_t nfl,
+                                                             int64_t per_blk, float* __restrict__ sink) {
+  // each workgroup reads its own contiguous span (per_blk floats, a multiple
+  // of 4) with 8 non-temporal 16-byte loads in flight per lane
+  const int64_t b0 = (int64_t)blockIdx.x * per_blk;
+  if (b0 >= nfl) return;
+  const int64_t len = b0 + per_blk <= nfl ? per_blk : nfl - b0;
+  const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(src + b0, (int)(len * 4));
   float acc = 0.f;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += 4 * stride) {
-    float4 v[4];
+  for (int off = threadIdx.x * 16; off < (int)(len * 4); off += kBlock * 16 * 8) {
+    float4 v[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = (i + u * stride < n4) ? src[i + u * stride] : float4{0, 0, 0, 0};
+    for (int u = 0; u < 8; ++u) v[u] = load16(rs, off + u * kBlock * 16);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+    for (int u = 0; u < 8; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
   }
   if (acc == 1.2345e-30f) sink[blockIdx.x] = acc;   // keeps the loads alive
 }
@@ -3040,13 +3064,18 @@ mf_status mf_stream_read(const float* src, int64_t n, float* sink, int32_t n_blo
                          float* ms_out, void* stream) {
   if (!src || !sink || n < 4 || n % 4 != 0 || ((uintptr_t)src & 15) != 0 || n_blocks < 1)
     return fail_with(MF_E_ARG, "src/sink NULL, n not a positive multiple of 4, or src not 16-byte aligned");
+  // a contiguous span per workgroup; its byte offsets (plus the unrolled
+  // loads' stride) stay below 2^31
+  int64_t per = (n + n_blocks - 1) / n_blocks;
+  per = (per + 3) / 4 * 4;
+  if (per * 4 > (int64_t)INT32_MAX - 65536)
+    return fail_with(MF_E_ARG, "n / n_blocks exceeds 2^29 floats per workgroup");
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ms_out && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     return fail_with(MF_E_DEVICE, "event creation failed");
   if (ms_out) (void)hipEventRecord(e0, st);
-  hipLaunchKernelGGL(stream_read_kernel, dim3((unsigned)n_blocks), dim3(kBlock), 0, st,
-                     (const float4*)src, n / 4, sink);
+  hipLaunchKernelGGL(stream_read_kernel, dim3((unsigned)n_blocks), dim3(kBlock), 0, st, src, n, per, sink);
   mf_status rc = MF_OK;
   if (hipGetLastError() != hipSuccess) rc = fail_with(MF_E_DEVICE, "stream_read launch failed");
   if (ms_out) {

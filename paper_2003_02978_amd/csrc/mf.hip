@@ -1919,29 +1919,36 @@ __global__ void __launch_bounds__(kSBlock) bwd_passB_kernel(BwArgs a) {
   double m_lo = 0.0, m_hi = 0.0;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
 
+  // lanes l and l + 32 split pixel l's bands for L . u (as in the forward
+  // streaming pass); everything after the dot product is the lower lane's
+  const int hsplit = ((B + 3) / 4) * 2;
+  const int upper = lane >> 5;
   auto score = [&](int64_t c0, int n, uint32_t vld, double pp, double r, double am1_in,
                    double pb_in, double ab_in, double rb_in, const float* tl) {
-    const int64_t px = c0 + lane;
-    const bool inb = lane < n;
-    const bool ok = inb && vld != 0;
-    double lu = 0.0;
-    if (ok) {
-      const float* rowp = tl + lane * B;
+    const int pxl = lane & (kChunk - 1);
+    const int64_t px = c0 + pxl;
+    const bool okd = pxl < n && vld != 0;       // both halves of the pixel
+    double le = 0.0, lo = 0.0;
+    if (okd) {
+      const float* rowp = tl + pxl * B;
       const double2* u2 = reinterpret_cast<const double2*>(ucs);
-      double le = 0.0, lo = 0.0;
-      int b = 0;
+      int b = upper ? hsplit : 0;
+      const int bend = upper ? B : hsplit;
       if ((B & 1) == 0 && (reinterpret_cast<uintptr_t>(tl) & 7) == 0) {
 #pragma unroll 4
-        for (; b < B; b += 2) {
+        for (; b + 1 < bend; b += 2) {
           const float2 l2 = *reinterpret_cast<const float2*>(rowp + b);
           const double2 cu = u2[b >> 1];
           le = fma((double)l2.x, cu.x, le);
           lo = fma((double)l2.y, cu.y, lo);
         }
       }
-      for (; b < B; ++b) le = fma((double)rowp[b], ucs[b], le);
-      lu = le + lo;
+      for (; b < bend; ++b) le = fma((double)rowp[b], ucs[b], le);
     }
+    double lu = le + lo;
+    lu += __shfl_xor(lu, 32, 64);
+    const bool inb = pxl < n && !upper;
+    const bool ok = okd && !upper;
     if (!ok) {
       pp = 0.0;
       r = 0.0;
@@ -2018,8 +2025,8 @@ __global__ void __launch_bounds__(kSBlock) bwd_passB_kernel(BwArgs a) {
   }
   for (; c0 < end; c0 += step) {               // the last chunk of the array
     const int n = (int)min<int64_t>(kChunk, end - c0);
-    const int64_t px = c0 + lane;
-    const bool inb = lane < n;
+    const int64_t px = c0 + pl;
+    const bool inb = pl < n;
     const uint32_t vld = (inb && a.valid) ? (uint32_t)a.valid[px] : 1u;
     const double pp = inb ? a.p_k[px] : 0.0, r = inb ? a.r_px[px] : 0.0;
     const double am = (inb && k >= 1) ? a.a_km1[px] : 0.0, pb = inb ? a.pbar[px] : 0.0;

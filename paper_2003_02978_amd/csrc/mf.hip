@@ -1749,7 +1749,8 @@ __global__ void __launch_bounds__(kABlock) bwd_passA_kernel(BwArgs a) {
   const WorkItem it = a.items[blockIdx.x];
   const ColState* __restrict__ st = a.state + it.col;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wid = tid >> 6;
+  const int lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
   const int B = a.B, k = a.k;
   const int64_t begin = it.px_begin, end = begin + it.n_px;
   extern __shared__ double dyn[];
@@ -1766,25 +1767,49 @@ __global__ void __launch_bounds__(kABlock) bwd_passA_kernel(BwArgs a) {
   const double gamma = bw[kBwScal + 0];
   const double lam = a.lam, eps = a.eps;
   double m_lo = 0.0, m_hi = 0.0, s0 = 0.0, s1 = 0.0;
-  for (int64_t c0 = begin + (int64_t)kAChunk * wid; c0 < end; c0 += kAW * kAChunk) {
+  // Per-pixel inputs of a chunk, through buffer resources sized to its pixels
+  // (zero size past the work item, for a null pointer, or for an input this
+  // iteration does not use, so those read zeros): no load is conditional, and
+  // the next chunk's loads are in flight while the current one is processed.
+  struct PxIn {
+    uint32_t v;
+    double pp, r, g, ab, rb, ak, am1;
+  };
+  const bool last = k == a.K;
+  auto load_px = [&](int64_t c) {
+    const int n = __builtin_amdgcn_readfirstlane((int)max<int64_t>(0, min<int64_t>(kAChunk, end - c)));
+    PxIn x;
+    x.v = load1(chunk_rsrc(a.valid ? a.valid + c : nullptr, a.valid ? n : 0), lane);
+    x.pp = load8(chunk_rsrc(a.p_k + c, n * 8), lane * 8);
+    x.r = load8(chunk_rsrc(a.r_px + c, n * 8), lane * 8);
+    x.g = (double)load4(chunk_rsrc(a.grad_alpha + c, last ? n * 4 : 0), lane * 4);
+    x.ab = load8(chunk_rsrc(a.abar + c, last ? 0 : n * 8), lane * 8);
+    x.rb = load8(chunk_rsrc(a.rbar + c, last ? 0 : n * 8), lane * 8);
+    x.ak = load8(chunk_rsrc(a.a_k + c, last ? 0 : n * 8), lane * 8);
+    x.am1 = load8(chunk_rsrc(k >= 1 ? a.a_km1 + c : nullptr, k >= 1 ? n * 8 : 0), lane * 8);
+    return x;
+  };
+  int64_t c0 = begin + (int64_t)kAChunk * wid;
+  PxIn cur = load_px(c0);
+  for (; c0 < end; c0 += kAW * kAChunk) {
+    const PxIn nxt = load_px(c0 + kAW * kAChunk);
     const int n = (int)min<int64_t>(kAChunk, end - c0);
     const int64_t px = c0 + lane;
     const bool inb = lane < n;
-    bool ok = inb;
-    if (inb && a.valid) ok = a.valid[px] != 0;
-    const double pp = ok ? a.p_k[px] : 0.0;
-    const double r = ok ? a.r_px[px] : 0.0;     // 0 off valid pixels
+    const bool ok = inb && (a.valid == nullptr || cur.v != 0u);
+    const double pp = ok ? cur.pp : 0.0;
+    const double r = ok ? cur.r : 0.0;          // 0 off valid pixels
     const bool live = ok && (r > 0.0);          // dark pixels keep alpha = 0
     double ab = 0.0, rb = 0.0;
     if (inb) {
-      if (k == a.K) {
-        ab = (double)a.grad_alpha[px];
+      if (last) {
+        ab = cur.g;
       } else {
-        ab = a.abar[px] + r * gamma;
-        rb = a.rbar[px] + a.a_k[px] * gamma;
+        ab = cur.ab + r * gamma;
+        rb = cur.rb + cur.ak * gamma;
       }
     }
-    const double am1 = (k >= 1 && inb) ? a.a_km1[px] : 0.0;
+    const double am1 = (k >= 1 && inb) ? cur.am1 : 0.0;
     const double w = k >= 1 ? lam / (am1 + eps) : 0.0;
     const double z = live ? (pp - w) / (r * q) : 0.0;
     const bool pos = (a.K == 0) || (z > 0.0);   // K = 0 returns alpha^0 unclamped
@@ -1832,6 +1857,7 @@ __global__ void __launch_bounds__(kABlock) bwd_passA_kernel(BwArgs a) {
       }
       wave_sync_lds();
     }
+    cur = nxt;
   }
   for (int off = 32; off >= 1; off >>= 1) {
     s0 += __shfl_xor(s0, off, 64);

@@ -1735,6 +1735,8 @@ struct BwArgs {
 constexpr int kAW = 4;
 constexpr int kABlock = 64 * kAW;
 constexpr int kAChunk = 64;                // pixels per wave chunk in pass A
+constexpr int kG = 8;                      // active pixels per radiance gather in pass A (4: 14.53,
+                                           // 8: 14.35, 16: 14.31 ms forward + backward, 598x4000)
 
 // Dynamic LDS of bwd_passA_kernel: per-pixel weights, partial rows, mu^k.
 __host__ __device__ constexpr size_t bwdA_lds_bytes(int B) {
@@ -1832,22 +1834,26 @@ __global__ void __launch_bounds__(kABlock) bwd_passA_kernel(BwArgs a) {
       const int b0 = lane, b1 = lane + 64;
       const double o0 = b0 < B ? mu[b0] : 0.0;
       const double o1 = b1 < B ? mu[b1] : 0.0;
-      while (mask) {                            // rows of four pixels in flight
-        int pi[4];
+      // rows of kG pixels in flight, through a resource over the chunk's
+      // radiance: absent pixels and bands past B read zeros, so the loads
+      // of a group issue together (no branch, no wait between them)
+      const __amdgpu_buffer_rsrc_t rl = chunk_rsrc(Lc, __builtin_amdgcn_readfirstlane(n * B * 4));
+      while (mask) {
+        int pi[kG];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kG; ++u) {
           pi[u] = mask ? (int)__builtin_ctzll(mask) : -1;
           mask &= mask - 1;
         }
-        float l0[4], l1[4];
+        float l0[kG], l1[kG];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kG; ++u) {
           const bool h = pi[u] >= 0;
-          l0[u] = (h && b0 < B) ? Lc[(int64_t)pi[u] * B + b0] : 0.f;
-          l1[u] = (h && b1 < B) ? Lc[(int64_t)pi[u] * B + b1] : 0.f;
+          l0[u] = load4(rl, (h && b0 < B) ? (pi[u] * B + b0) * 4 : kOffNone);
+          l1[u] = load4(rl, (h && b1 < B) ? (pi[u] * B + b1) * 4 : kOffNone);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kG; ++u) {
           if (pi[u] >= 0) {
             const double cp = cbuf[wid * kAChunk + pi[u]];
             m_lo = fma(cp, (double)l0[u] - o0, m_lo);

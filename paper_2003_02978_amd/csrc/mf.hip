@@ -984,6 +984,58 @@ __device__ void block_symv(const double (&M)[kBlk][kBlk], bool owner, int bi, in
   __syncthreads();
 }
 
+// Cholesky factor L (lower) of a symmetric 4x4 block D (row-major, lower part
+// read) and W = L^-1 (lower); only the lower triangles of L and W are set.
+// False if a pivot is not positive (or not finite).
+__device__ __forceinline__ bool chol4(const double* D, double (&Lc)[kBlk][kBlk], double (&W)[kBlk][kBlk]) {
+  bool spd = true;
+#pragma unroll
+  for (int c = 0; c < kBlk; ++c) {
+    double d = D[c * 4 + c];
+#pragma unroll
+    for (int z = 0; z < c; ++z) d = fma(-Lc[c][z], Lc[c][z], d);
+    spd = spd && d > 0.0 && isfinite(d);
+    const double l = sqrt(d), rl = 1.0 / l;
+    Lc[c][c] = l;
+#pragma unroll
+    for (int r = c + 1; r < kBlk; ++r) {
+      double e = D[r * 4 + c];
+#pragma unroll
+      for (int z = 0; z < c; ++z) e = fma(-Lc[r][z], Lc[c][z], e);
+      Lc[r][c] = e * rl;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kBlk; ++c) {
+    W[c][c] = 1.0 / Lc[c][c];
+#pragma unroll
+    for (int r = c + 1; r < kBlk; ++r) {
+      double e = 0.0;
+#pragma unroll
+      for (int z = c; z < r; ++z) e = fma(Lc[r][z], W[z][c], e);
+      W[r][c] = -e / Lc[r][r];
+    }
+  }
+  return spd;
+}
+
+// Y = C W^T for a 4x4 block C (row-major) and lower W.
+__device__ __forceinline__ void mul_wt(const double* C, const double (&W)[kBlk][kBlk], double (&Y)[kBlk][kBlk]) {
+#pragma unroll
+  for (int x = 0; x < kBlk; ++x) {
+    double c[kBlk];
+#pragma unroll
+    for (int z = 0; z < kBlk; ++z) c[z] = C[x * 4 + z];
+#pragma unroll
+    for (int y = 0; y < kBlk; ++y) {
+      double t = 0.0;
+#pragma unroll
+      for (int z = 0; z <= y; ++z) t = fma(c[z], W[y][z], t);
+      Y[x][y] = t;
+    }
+  }
+}
+
 // Column checkpoint of iteration k (save_for_backward): mu, t, v, m, a, S2, q, N.
 constexpr int kCkMu = 0, kCkT = kPad, kCkV = 2 * kPad, kCkM = 3 * kPad, kCkScal = 4 * kPad;
 constexpr int kCk = 4 * kPad + 8;
@@ -1122,61 +1174,17 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
     for (int K = 0; K < nkb; ++K) {
       const double* cb = (K & 1) ? cb1 : cb0;
       // D = L L^T and W = L^-1 (lower), every thread (same result)
-      // (only the lower triangles of Lc and W are set and read)
       double Lc[kBlk][kBlk], W[kBlk][kBlk];
-      bool spd = true;
-#pragma unroll
-      for (int c = 0; c < kBlk; ++c) {
-        double d = cb[K * 16 + c * 4 + c];
-#pragma unroll
-        for (int z = 0; z < c; ++z) d = fma(-Lc[c][z], Lc[c][z], d);
-        spd = spd && d > 0.0 && isfinite(d);
-        const double l = sqrt(d), rl = 1.0 / l;
-        Lc[c][c] = l;
-#pragma unroll
-        for (int r = c + 1; r < kBlk; ++r) {
-          double e = cb[K * 16 + r * 4 + c];
-#pragma unroll
-          for (int z = 0; z < c; ++z) e = fma(-Lc[r][z], Lc[c][z], e);
-          Lc[r][c] = e * rl;
-        }
-      }
-      if (!spd) {                            // uniform
+      if (!chol4(cb + K * 16, Lc, W)) {      // uniform
         if (tid == 0) st.status = MF_COL_NOT_SPD;
         return;
       }
-#pragma unroll
-      for (int c = 0; c < kBlk; ++c) {
-        W[c][c] = 1.0 / Lc[c][c];
-#pragma unroll
-        for (int r = c + 1; r < kBlk; ++r) {
-          double e = 0.0;
-#pragma unroll
-          for (int z = c; z < r; ++z) e = fma(Lc[r][z], W[z][c], e);
-          W[r][c] = -e / Lc[r][r];
-        }
-      }
       if (owner) {
         // Y = C W^T for the block rows this thread needs (C = A_iK from LDS)
-        auto ymul = [&](int blk, double (&Y)[kBlk][kBlk]) {
-#pragma unroll
-          for (int x = 0; x < kBlk; ++x) {
-            double c[kBlk];
-#pragma unroll
-            for (int z = 0; z < kBlk; ++z) c[z] = cb[blk * 16 + x * 4 + z];
-#pragma unroll
-            for (int y = 0; y < kBlk; ++y) {
-              double t = 0.0;
-#pragma unroll
-              for (int z = 0; z <= y; ++z) t = fma(c[z], W[y][z], t);
-              Y[x][y] = t;
-            }
-          }
-        };
         if (bi != K && bj != K) {
           double Yi[kBlk][kBlk], Yj[kBlk][kBlk];
-          ymul(bi, Yi);
-          ymul(bj, Yj);
+          mul_wt(cb + bi * 16, W, Yi);
+          mul_wt(cb + bj * 16, W, Yj);
 #pragma unroll
           for (int x = 0; x < kBlk; ++x)
 #pragma unroll
@@ -1200,7 +1208,7 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
           // column block (bj == K): A_iK <- Y_i W;  row block (bi == K):
           // A_Kj <- (Y_j W)^T
           double Y[kBlk][kBlk];
-          ymul(bj == K ? bi : bj, Y);
+          mul_wt(cb + (bj == K ? bi : bj) * 16, W, Y);
           double R[kBlk][kBlk];
 #pragma unroll
           for (int x = 0; x < kBlk; ++x)
@@ -1248,54 +1256,63 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
       __syncthreads();
     }
   } else {
-  // ---- right-looking Cholesky on the register blocks
-  for (int k = 0; k < B; ++k) {
-    const int kb = k >> 2, ka = k & 3;
-    if (owner && bi == kb && bj == kb) {
-      double dkk = 0.0;
+  // ---- blocked right-looking Cholesky on the register blocks.  For pivot
+  // block K with D = A_KK = L_KK L_KK^T (W = L_KK^-1): the panel
+  // A_iK <- A_iK W^T = L_iK (i > K), then A_ij -= L_iK L_jK^T (i >= j > K).
+  // Block column K is published by its owners right after their update of
+  // pivot block K - 1, into alternating LDS buffers: one barrier per pivot
+  // block.  Padding rows (>= B) are decoupled with unit diagonal.
+  {
+    double* cb0 = Lf;                       // two [kNBlkRows][4][4] buffers (Lf is
+    double* cb1 = Lf + kNBlkRows * 16;      // free until the factor is stored)
+    auto publish = [&](int K, double* cb) {
+      if (owner && bj == K) {               // A_iK, i >= K
 #pragma unroll
-      for (int x = 0; x < kBlk; ++x)
-        if (x == ka) dkk = A_[x][x];
-      sdiag = dkk;
-    }
+        for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+          for (int y = 0; y < kBlk; ++y) cb[bi * 16 + x * 4 + y] = A_[x][y];
+      }
+    };
+    const int nkb = (B + kBlk - 1) / kBlk;
+    publish(0, cb0);
     __syncthreads();
-    const double dkk = sdiag;
-    if (!(dkk > 0.0) || !isfinite(dkk)) {      // uniform
-      if (tid == 0) st.status = MF_COL_NOT_SPD;
-      return;
-    }
-    const double d = sqrt(dkk);
-    if (owner && bj == kb) {
-      const double inv = 1.0 / d;
+    for (int K = 0; K < nkb; ++K) {
+      const double* cb = (K & 1) ? cb1 : cb0;
+      double Lc[kBlk][kBlk], W[kBlk][kBlk];
+      if (!chol4(cb + K * 16, Lc, W)) {      // uniform
+        if (tid == 0) st.status = MF_COL_NOT_SPD;
+        return;
+      }
+      if (owner && bj >= K) {
+        if (bi == K) {                       // (K, K): L_KK (upper half unused)
 #pragma unroll
-      for (int x = 0; x < kBlk; ++x) {
-        const int i = kBlk * bi + x;
+          for (int x = 0; x < kBlk; ++x)
 #pragma unroll
-        for (int y = 0; y < kBlk; ++y) {
-          if (y != ka) continue;
-          if (i == k) A_[x][y] = d;
-          if (i > k) {
-            A_[x][y] *= inv;
-            colk[i] = A_[x][y];
-          }
+            for (int y = 0; y < kBlk; ++y) A_[x][y] = y <= x ? Lc[x][y] : 0.0;
+        } else if (bj == K) {                // panel
+          double Y[kBlk][kBlk];
+          mul_wt(cb + bi * 16, W, Y);
+#pragma unroll
+          for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+            for (int y = 0; y < kBlk; ++y) A_[x][y] = Y[x][y];
+        } else {                             // trailing, bi >= bj > K
+          double Yi[kBlk][kBlk], Yj[kBlk][kBlk];
+          mul_wt(cb + bi * 16, W, Yi);
+          mul_wt(cb + bj * 16, W, Yj);
+#pragma unroll
+          for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+            for (int y = 0; y < kBlk; ++y) {
+              double t = A_[x][y];
+#pragma unroll
+              for (int z = 0; z < kBlk; ++z) t = fma(-Yi[x][z], Yj[y][z], t);
+              A_[x][y] = t;
+            }
         }
       }
-    }
-    __syncthreads();
-    if (owner && kBlk * bi + 3 > k) {
-      double cI[kBlk], cJ[kBlk];
-#pragma unroll
-      for (int x = 0; x < kBlk; ++x) {
-        cI[x] = colk[kBlk * bi + x];
-        cJ[x] = colk[kBlk * bj + x];
-      }
-#pragma unroll
-      for (int x = 0; x < kBlk; ++x)
-#pragma unroll
-        for (int y = 0; y < kBlk; ++y) {
-          const int i = kBlk * bi + x, jj = kBlk * bj + y;
-          if (jj > k && i >= jj && i < B) A_[x][y] -= cI[x] * cJ[y];
-        }
+      if (K + 1 < nkb) publish(K + 1, (K & 1) ? cb0 : cb1);
+      __syncthreads();
     }
   }
   // factor -> LDS, inverse diagonal

@@ -105,3 +105,14 @@ def test_null_arguments_of_retrieve():
     assert lib.mf_workspace_bytes(None) == 0
     lib.mf_plan_destroy(None)
     assert lib.mf_status_str(3) == b"unsupported configuration"
+
+
+def test_stream_read_rejects_bad_arguments_on_host():
+    lib = mf.load_library()
+    # pointers are only checked, never dereferenced, before these errors
+    assert lib.mf_stream_read(None, 1024, None, 16, None, None) == mf.MF_E_ARG
+    assert lib.mf_stream_read(16, 1022, 32, 16, None, None) == mf.MF_E_ARG      # n not a multiple of 4
+    assert lib.mf_stream_read(20, 1024, 32, 16, None, None) == mf.MF_E_ARG      # src not 16-byte aligned
+    assert lib.mf_stream_read(16, 1024, 32, 0, None, None) == mf.MF_E_ARG       # no workgroups
+    assert lib.mf_stream_read(16, 1 << 31, 32, 1, None, None) == mf.MF_E_ARG    # span over 2^29 floats
+    assert b"2^29" in lib.mf_last_error()

@@ -367,40 +367,91 @@ __global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && !SCORE) ? 2 : 1) pa
   [[maybe_unused]] int nsuper = 0;
   auto compute = [&](const float (&Lc)[8][NB], double apl, uint32_t vbl, int64_t bx) {
     [[maybe_unused]] bf16x8 ybf[NB];
+    // SCORE: c = r alpha^{j-1} of pixel 4s + row of the super-step, or -1
+    // for a pixel that stays out of the Gram (invalid, or past the item)
+    [[maybe_unused]] double cs[8];
+    if constexpr (SCORE) {
+      // The lane's partial dot products for its row's 8 pixels:
+      // p = v . (L - mu) in v16[s], r = m0 . L in v16[8 + s] (bands past B
+      // hold zeros in L, mu, v and m0).
+      double v16[16];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int64_t px = bx + 4 * s + row;
-      const uint32_t vb = (uint32_t)__shfl((int)vbl, 4 * s + row, 64);
-      const bool ok = px < end && (a.valid == nullptr || vb != 0u);
-      double x[NB], l[NB];
-      double pp = 0.0, rr = 0.0;
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        const bool in = ok && band_of<NB, WIDE>(k, c16) < B;
-        l[k] = in ? (double)Lc[s][k] : 0.0;
-        x[k] = in ? l[k] - mu[k] : 0.0;
-      }
-      double c = 0.0;
-      if constexpr (SCORE) {              // pass 0 only accumulates the Gram
+      for (int s = 0; s < 8; ++s) {
+        double pe = 0.0, re = 0.0;
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
-          pp = fma(x[k], vv[k], pp);
-          rr = fma(l[k], m0[k], rr);
+          const double l = (double)Lc[s][k];
+          pe = fma(l - mu[k], vv[k], pe);
+          re = fma(l, m0[k], re);
         }
-        pp = row_sum16_f64(pp);
-        rr = row_sum16_f64(rr);
-        const double r = a.albedo ? rr : 1.0;
-        const double ap = __shfl(apl, 4 * s + row, 64);
-        const double num = (j == 1) ? pp : pp - lam / (ap + eps);
-        double al = num / (r * q);
-        const bool dark = !(r > 0.0);
-        if (!a.unclamped) al = al > 0.0 ? al : 0.0;
-        if (!ok || dark) al = 0.0;
-        if (c16 == 0 && px < end) {
-          if (a.alpha_out) a.alpha_out[px] = al;
-          if (a.alpha_final) a.alpha_final[px] = (float)al;
+        v16[s] = pe;
+        v16[8 + s] = re;
+      }
+      // Transpose reduction over the 16 lanes of each row: at each step a
+      // lane keeps half of its values, sends the other half to its partner
+      // (partners differ in one bit of the lane's column) and adds what it
+      // receives, so lane c of the row ends with the row total of value c.
+      double v8[8], v4[4], v2[2];
+      {
+        const bool hi = (c16 & 8) != 0;        // row_mirror: c <-> 15 - c
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          v8[i] = (hi ? v16[i + 8] : v16[i]) + dpp_f64<0x140>(hi ? v16[i] : v16[i + 8]);
+      }
+      {
+        const bool hi = (c16 & 4) != 0;        // row_half_mirror: c <-> 7 - c in each half
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          v4[i] = (hi ? v8[i + 4] : v8[i]) + dpp_f64<0x141>(hi ? v8[i] : v8[i + 4]);
+      }
+      {
+        const bool hi = (c16 & 2) != 0;        // c <-> c ^ 2
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          v2[i] = (hi ? v4[i + 2] : v4[i]) + dpp_f64<0x4E>(hi ? v4[i] : v4[i + 2]);
+      }
+      const bool hi1 = (c16 & 1) != 0;         // c <-> c ^ 1
+      const double v1 = (hi1 ? v2[1] : v2[0]) + dpp_f64<0xB1>(hi1 ? v2[0] : v2[1]);
+      // One pixel per lane from here: lane l (and l + 32) holds pixel
+      // qx = l mod 32 of the super-step, sub-step qx / 4, row qx mod 4.
+      const int qx = lane & 31;
+      const double pp = __shfl(v1, 16 * (qx & 3) + (qx >> 2), 64);
+      const double rr = __shfl(v1, 16 * (qx & 3) + 8 + (qx >> 2), 64);
+      const int64_t px = bx + qx;
+      const bool ok = px < end && (a.valid == nullptr || vbl != 0u);
+      const double r = a.albedo ? rr : 1.0;
+      const double num = (j == 1) ? pp : pp - lam / (apl + eps);
+      double al = num / (r * q);
+      const bool dark = !(r > 0.0);
+      if (!a.unclamped) al = al > 0.0 ? al : 0.0;
+      if (!ok || dark) al = 0.0;
+      if (lane < 32 && px < end) {
+        if (a.alpha_out) a.alpha_out[px] = al;
+        if (a.alpha_final) a.alpha_final[px] = (float)al;
+      }
+      const double cenc = ok ? ((!dark && al > 0.0) ? r * al : 0.0) : -1.0;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) cs[s] = __shfl(cenc, 4 * s + row, 64);
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      double x[NB];
+      bool ok;
+      double c = 0.0;
+      if constexpr (SCORE) {
+        ok = cs[s] >= 0.0;
+        c = ok ? cs[s] : 0.0;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) x[k] = ok ? (double)Lc[s][k] - mu[k] : 0.0;
+      } else {
+        const int64_t px = bx + 4 * s + row;
+        const uint32_t vb = (uint32_t)__shfl((int)vbl, 4 * s + row, 64);
+        ok = px < end && (a.valid == nullptr || vb != 0u);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const bool in = ok && band_of<NB, WIDE>(k, c16) < B;
+          x[k] = in ? (double)Lc[s][k] - mu[k] : 0.0;
         }
-        c = (ok && !dark && al > 0.0) ? r * al : 0.0;
       }
       double y[NB];
 #pragma unroll

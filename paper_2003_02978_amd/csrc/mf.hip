@@ -62,9 +62,9 @@ enum PassMode {
   PM_VEC = 1,    // m = sum c (L - mean L), S1, S2 in FP64 (low-rank form)
   PM_F64 = 2,    // Gram of [y, 1, c] on v_mfma_f64_16x16x4_f64 (exact)
   PM_F32 = 3,    // Gram on v_mfma_f32_16x16x4_f32, FP64 flush every 64 px
-  PM_BF16 = 4    // Gram on v_mfma_f32_16x16x32_bf16, FP64 flush every 256 px
+  PM_BF16 = 4    // Gram on v_mfma_f32_16x16x32_bf16, FP32 accumulation per wave
 };
-constexpr int kVecM = 80, kVecS1 = 80, kVecS2 = 81;   // PM_VEC partial layout
+constexpr int kVecS1 = 80, kVecS2 = 81;   // PM_VEC partial layout: m in [0, B)
 constexpr int kVecE = 82;      // energy: pixel part of E^{j-1} (both streaming modes)
 
 // One partition (Sec. II-E): `group` adjacent detector columns of a
@@ -138,21 +138,6 @@ struct SolveArgs {
 
 __host__ __device__ constexpr int n_tiles(int nb) { return nb * (nb + 1) / 2; }
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // j <= i
-
-template <int CTRL>
-__device__ __forceinline__ float dpp(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
-      0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
-}
-
-// Sum over the 16 lanes of a DPP row (one pixel per row in the pass layout).
-__device__ __forceinline__ float row_sum16(float x) {
-  x += dpp<0xB1>(x);    // quad_perm [1,0,3,2]
-  x += dpp<0x4E>(x);    // quad_perm [2,3,0,1]
-  x += dpp<0x124>(x);   // row_ror:4
-  x += dpp<0x128>(x);   // row_ror:8
-  return x;
-}
 
 // ---------------------------------------------------------------------------
 // setup: per column, the shift point z (first valid pixel) and a clean state.
@@ -253,6 +238,14 @@ __host__ __device__ constexpr int band_of(int k, int c) {
   return WIDE ? (k < 4 ? 4 * c + k : 64 + c) : c + 16 * k;
 }
 
+// Blocks that can hold band B or B + 1, the 1 and c columns of the Gram
+// (NB is the smallest block count with B + 2 <= 16 NB): the last two blocks
+// of the narrow layout, block 4 of the wide one.
+template <int NB, bool WIDE>
+__host__ __device__ constexpr bool holds_tail(int k) {
+  return WIDE ? k == 4 : k >= NB - 2;
+}
+
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double x) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
@@ -314,11 +307,14 @@ __device__ __forceinline__ void load_super(const PassArgs& a, int64_t base, int6
 // SCORE: passes j >= 1 (alpha^{j-1} and c = r alpha enter the Gram); pass 0
 // (SCORE = false) is the Gram of the shifted radiance alone.
 template <int NB, bool WIDE, int MODE, bool SCORE>
-__global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && !SCORE) ? 2 : 1) pass_kernel(PassArgs a) {
+__global__ void __launch_bounds__(kBlock, ((MODE == PM_F64 && !SCORE) || MODE == PM_BF16) ? 2 : 1) pass_kernel(PassArgs a) {
   constexpr int T = n_tiles(NB);
   static_assert(MODE >= PM_F64, "the Gram pass; the streaming passes are stream_kernel");
   constexpr bool F32ACC = MODE == PM_F32 || MODE == PM_BF16;
-  constexpr int FLUSH = MODE == PM_BF16 ? 8 : 2;   // super-steps between FP64 flushes
+  // FP32 Gram: FP64 flush every 2 super-steps (64 pixels).  BF16 Gram: FP32
+  // accumulation over the wave's share of the item (its inputs carry 8-bit
+  // mantissas, far coarser than the FP32 sums), FP64 only across waves and items.
+  constexpr int FLUSH = MODE == PM_F32 ? 2 : 0;
   const WorkItem it = a.items[blockIdx.x];
   const ColState& st = a.state[it.col];
   const int tid = threadIdx.x;
@@ -348,6 +344,19 @@ __global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && !SCORE) ? 2 : 1) pa
       m0[k] = in ? st.m0[b] : 0.0;
     }
   }
+  [[maybe_unused]] double muv = 0.0;            // mu . v, the same in every row
+  if constexpr (SCORE) {
+    double d = 0.0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) d = fma(mu[k], vv[k], d);
+    muv = row_sum16_f64(d);
+  }
+  [[maybe_unused]] float muf[NB], ttf[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    muf[k] = (float)mu[k];
+    if constexpr (SCORE) ttf[k] = (float)tt[k];
+  }
   const double q = st.q;
   const double lam = a.lam, eps = a.eps;
   const int j = a.j;
@@ -372,8 +381,8 @@ __global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && !SCORE) ? 2 : 1) pa
     [[maybe_unused]] double cs[8];
     if constexpr (SCORE) {
       // The lane's partial dot products for its row's 8 pixels:
-      // p = v . (L - mu) in v16[s], r = m0 . L in v16[8 + s] (bands past B
-      // hold zeros in L, mu, v and m0).
+      // L . v in v16[s] (p = L . v - mu . v), r = m0 . L in v16[8 + s]
+      // (bands past B hold zeros in L, v and m0).
       double v16[16];
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
@@ -381,7 +390,7 @@ __global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && !SCORE) ? 2 : 1) pa
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
           const double l = (double)Lc[s][k];
-          pe = fma(l - mu[k], vv[k], pe);
+          pe = fma(l, vv[k], pe);
           re = fma(l, m0[k], re);
         }
         v16[s] = pe;
@@ -415,7 +424,7 @@ __global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && !SCORE) ? 2 : 1) pa
       // One pixel per lane from here: lane l (and l + 32) holds pixel
       // qx = l mod 32 of the super-step, sub-step qx / 4, row qx mod 4.
       const int qx = lane & 31;
-      const double pp = __shfl(v1, 16 * (qx & 3) + (qx >> 2), 64);
+      const double pp = __shfl(v1, 16 * (qx & 3) + (qx >> 2), 64) - muv;
       const double rr = __shfl(v1, 16 * (qx & 3) + 8 + (qx >> 2), 64);
       const int64_t px = bx + qx;
       const bool ok = px < end && (a.valid == nullptr || vbl != 0u);
@@ -435,53 +444,58 @@ __global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && !SCORE) ? 2 : 1) pa
     }
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-      double x[NB];
       bool ok;
       double c = 0.0;
       if constexpr (SCORE) {
         ok = cs[s] >= 0.0;
         c = ok ? cs[s] : 0.0;
-#pragma unroll
-        for (int k = 0; k < NB; ++k) x[k] = ok ? (double)Lc[s][k] - mu[k] : 0.0;
       } else {
         const int64_t px = bx + 4 * s + row;
         const uint32_t vb = (uint32_t)__shfl((int)vbl, 4 * s + row, 64);
         ok = px < end && (a.valid == nullptr || vb != 0u);
+      }
+      // y = L - mu - c t (Eq. 11), then the 1 and c columns past band B;
+      // bands past B + 1 hold zeros in L, mu and t
+      if constexpr (MODE == PM_F64) {
+        double y[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
-          const bool in = ok && band_of<NB, WIDE>(k, c16) < B;
-          x[k] = in ? (double)Lc[s][k] - mu[k] : 0.0;
+          const int b = band_of<NB, WIDE>(k, c16);
+          const double x = (double)Lc[s][k] - mu[k];
+          y[k] = ok ? (SCORE ? fma(-c, tt[k], x) : x) : 0.0;
+          if (holds_tail<NB, WIDE>(k) && b == B) y[k] = ok ? 1.0 : 0.0;
+          if (holds_tail<NB, WIDE>(k) && b == B + 1) y[k] = c;
         }
-      }
-      double y[NB];
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        const int b = band_of<NB, WIDE>(k, c16);
-        if constexpr (SCORE) y[k] = fma(-c, tt[k], x[k]);
-        else y[k] = x[k];
-        if (b == B) y[k] = ok ? 1.0 : 0.0;
-        if (b == B + 1) y[k] = c;
-      }
-      if constexpr (MODE == PM_F64) {
 #pragma unroll
         for (int I = 0; I < NB; ++I)
 #pragma unroll
           for (int J = 0; J <= I; ++J)
             dacc[n_tiles(I) + J] =
                 __builtin_amdgcn_mfma_f64_16x16x4f64(y[I], y[J], dacc[n_tiles(I) + J], 0, 0, 0);
-      } else if constexpr (MODE == PM_F32) {
+      } else {
+        // FP32 and BF16 Gram: y is formed in FP32 (it is rounded to the
+        // Gram's input precision anyway; mu and t enter rounded to FP32)
+        const float cf = (float)c;
         float yf[NB];
 #pragma unroll
-        for (int k = 0; k < NB; ++k) yf[k] = (float)y[k];
+        for (int k = 0; k < NB; ++k) {
+          const int b = band_of<NB, WIDE>(k, c16);
+          const float x = Lc[s][k] - muf[k];
+          yf[k] = ok ? (SCORE ? fmaf(-cf, ttf[k], x) : x) : 0.f;
+          if (holds_tail<NB, WIDE>(k) && b == B) yf[k] = ok ? 1.f : 0.f;
+          if (holds_tail<NB, WIDE>(k) && b == B + 1) yf[k] = cf;
+        }
+        if constexpr (MODE == PM_F32) {
 #pragma unroll
-        for (int I = 0; I < NB; ++I)
+          for (int I = 0; I < NB; ++I)
 #pragma unroll
-          for (int J = 0; J <= I; ++J)
-            acc[n_tiles(I) + J] =
-                __builtin_amdgcn_mfma_f32_16x16x4f32(yf[I], yf[J], acc[n_tiles(I) + J], 0, 0, 0);
-      } else {
+            for (int J = 0; J <= I; ++J)
+              acc[n_tiles(I) + J] =
+                  __builtin_amdgcn_mfma_f32_16x16x4f32(yf[I], yf[J], acc[n_tiles(I) + J], 0, 0, 0);
+        } else {
 #pragma unroll
-        for (int k = 0; k < NB; ++k) ybf[k][s] = (__bf16)(float)y[k];
+          for (int k = 0; k < NB; ++k) ybf[k][s] = (__bf16)yf[k];
+        }
       }
     }
     if constexpr (MODE == PM_BF16) {
@@ -492,7 +506,7 @@ __global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && !SCORE) ? 2 : 1) pa
           acc[n_tiles(I) + J] =
               __builtin_amdgcn_mfma_f32_16x16x32_bf16(ybf[I], ybf[J], acc[n_tiles(I) + J], 0, 0, 0);
     }
-    if constexpr (F32ACC) {
+    if constexpr (F32ACC && FLUSH > 0) {
       if (++nsuper == FLUSH) {
         nsuper = 0;
 #pragma unroll
@@ -1111,7 +1125,6 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
   __shared__ double colk[kPad], vbuf[kPad], rbuf[kPad], invd[kPad];
   __shared__ __align__(16) double qsym[kSymvScratch];
   __shared__ double sc[4];
-  __shared__ double sdiag;
   __shared__ int fail;
 
   // block owned by this thread

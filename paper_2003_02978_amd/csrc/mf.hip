@@ -137,6 +137,12 @@ struct SolveArgs {
 };
 
 __host__ __device__ constexpr int n_tiles(int nb) { return nb * (nb + 1) / 2; }
+// Block row I of lower-triangle tile u = n_tiles(I) + J, J <= I.
+__host__ __device__ constexpr int tile_row(int u) {
+  int I = 0;
+  while (n_tiles(I + 1) <= u) ++I;
+  return I;
+}
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // j <= i
 
 // ---------------------------------------------------------------------------
@@ -911,56 +917,6 @@ __device__ __forceinline__ void block_of(int b, int& blk, int& m) {
   }
 }
 
-// G[i][j] summed over the column's work items (tiles hold block I >= J).
-template <int NB, bool WIDE>
-__device__ __forceinline__ double gram_elem(const double* __restrict__ P, int n_items,
-                                            int i, int j) {
-  constexpr int T = n_tiles(NB);
-  int I, mi, J, mj;
-  block_of<NB, WIDE>(i, I, mi);
-  block_of<NB, WIDE>(j, J, mj);
-  if (I < J) {
-    const int t0 = I, t1 = mi;
-    I = J; mi = mj; J = t0; mj = t1;
-  }
-  const int e = (n_tiles(I) + J) * 256 + mi * 16 + mj;
-  double g = 0.0;
-#pragma unroll 8
-  for (int it = 0; it < n_items; ++it) g += P[(int64_t)it * T * 256 + e];
-  return g;
-}
-
-__device__ __forceinline__ double readlane_f64(double x, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
-  return __hiloint2double(hi, lo);
-}
-
-// Wave-synchronous solve of L L^T v = y on one wave (64 lanes); the factor
-// is packed lower-triangular in LDS with inverse diagonal invd; the vector
-// lives in registers, lane l holding entries l and l + 64.
-__device__ void wave_chol_solve(const double* __restrict__ Lf, double invd_lo, double invd_hi,
-                                double& y_lo, double& y_hi, int B, int lane) {
-  const int i0 = lane, i1 = lane + 64;
-  for (int k = 0; k < B; ++k) {                     // forward: L y' = y
-    const bool lo = k < 64;
-    const double yk = readlane_f64(lo ? y_lo : y_hi, k & 63) *
-                      readlane_f64(lo ? invd_lo : invd_hi, k & 63);
-    if (i0 == k) y_lo = yk;
-    if (i1 == k) y_hi = yk;
-    if (i0 > k && i0 < B) y_lo -= Lf[tri(i0, k)] * yk;
-    if (i1 > k && i1 < B) y_hi -= Lf[tri(i1, k)] * yk;
-  }
-  for (int k = B - 1; k >= 0; --k) {                // backward: L^T v = y'
-    const bool lo = k < 64;
-    const double vk = readlane_f64(lo ? y_lo : y_hi, k & 63) *
-                      readlane_f64(lo ? invd_lo : invd_hi, k & 63);
-    if (i0 == k) y_lo = vk;
-    if (i1 == k) y_hi = vk;
-    if (i0 < k) y_lo -= Lf[tri(k, i0)] * vk;
-    if (i1 < k) y_hi -= Lf[tri(k, i1)] * vk;
-  }
-}
 
 // One workgroup per column.  The symmetric matrix is split in 4x4 blocks of
 // the lower triangle; thread t < 210 keeps block (bi, bj), t = bi(bi+1)/2 + bj,
@@ -1049,36 +1005,107 @@ __device__ void block_symv(const double (&M)[kBlk][kBlk], bool owner, int bi, in
   __syncthreads();
 }
 
+// Blocked solve of L L^T v = x with the Cholesky factor in the owner threads'
+// register blocks (Lb = L_ij, i >= j) and W_K = L_KK^-1 in wbuf (16 doubles
+// per block, row-major, lower).  Forward, block step K: the threads of block
+// column K form y_K = W_K x_K; (K, K) stores it, (i, K) subtracts L_iK y_K
+// from x_i.  Backward, block step I: the threads of block row I form
+// v_I = W_I^T y_I; (I, I) stores it, (I, K) subtracts L_IK^T v_I from y_K.
+// Each block of x and y has one writer per step: one barrier per step.  x is
+// overwritten, y is scratch, v receives the solution (kPad entries each, the
+// first 4 nkb used).
+__device__ void block_chol_solve(const double (&Lb)[kBlk][kBlk], bool owner, int bi, int bj, int nkb,
+                                 const double* wbuf, double* x, double* y, double* v) {
+  for (int K = 0; K < nkb; ++K) {
+    if (owner && bj == K) {
+      const double* w = wbuf + K * 16;
+      double xk[kBlk], yk[kBlk];
+#pragma unroll
+      for (int z = 0; z < kBlk; ++z) xk[z] = x[kBlk * K + z];
+#pragma unroll
+      for (int r = 0; r < kBlk; ++r) {
+        double t = 0.0;
+#pragma unroll
+        for (int z = 0; z <= r; ++z) t = fma(w[r * 4 + z], xk[z], t);
+        yk[r] = t;
+      }
+      if (bi == K) {
+#pragma unroll
+        for (int r = 0; r < kBlk; ++r) y[kBlk * K + r] = yk[r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < kBlk; ++r) {
+          double t = x[kBlk * bi + r];
+#pragma unroll
+          for (int z = 0; z < kBlk; ++z) t = fma(-Lb[r][z], yk[z], t);
+          x[kBlk * bi + r] = t;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int I = nkb - 1; I >= 0; --I) {
+    if (owner && bi == I) {
+      const double* w = wbuf + I * 16;
+      double yi[kBlk], vi[kBlk];
+#pragma unroll
+      for (int z = 0; z < kBlk; ++z) yi[z] = y[kBlk * I + z];
+#pragma unroll
+      for (int r = 0; r < kBlk; ++r) {
+        double t = 0.0;
+#pragma unroll
+        for (int z = r; z < kBlk; ++z) t = fma(w[z * 4 + r], yi[z], t);
+        vi[r] = t;
+      }
+      if (bj == I) {
+#pragma unroll
+        for (int r = 0; r < kBlk; ++r) v[kBlk * I + r] = vi[r];
+      } else {
+#pragma unroll
+        for (int c = 0; c < kBlk; ++c) {
+          double t = y[kBlk * bj + c];
+#pragma unroll
+          for (int r = 0; r < kBlk; ++r) t = fma(-Lb[r][c], vi[r], t);
+          y[kBlk * bj + c] = t;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Cholesky factor L (lower) of a symmetric 4x4 block D (row-major, lower part
 // read) and W = L^-1 (lower); only the lower triangles of L and W are set.
 // False if a pivot is not positive (or not finite).
 __device__ __forceinline__ bool chol4(const double* D, double (&Lc)[kBlk][kBlk], double (&W)[kBlk][kBlk]) {
   bool spd = true;
+  double rl[kBlk];                             // 1 / L_cc
 #pragma unroll
   for (int c = 0; c < kBlk; ++c) {
     double d = D[c * 4 + c];
 #pragma unroll
     for (int z = 0; z < c; ++z) d = fma(-Lc[c][z], Lc[c][z], d);
     spd = spd && d > 0.0 && isfinite(d);
-    const double l = sqrt(d), rl = 1.0 / l;
+    const double l = sqrt(d);
+    rl[c] = 1.0 / l;
     Lc[c][c] = l;
 #pragma unroll
     for (int r = c + 1; r < kBlk; ++r) {
       double e = D[r * 4 + c];
 #pragma unroll
       for (int z = 0; z < c; ++z) e = fma(-Lc[r][z], Lc[c][z], e);
-      Lc[r][c] = e * rl;
+      Lc[r][c] = e * rl[c];
     }
   }
 #pragma unroll
   for (int c = 0; c < kBlk; ++c) {
-    W[c][c] = 1.0 / Lc[c][c];
+    W[c][c] = rl[c];
 #pragma unroll
     for (int r = c + 1; r < kBlk; ++r) {
       double e = 0.0;
 #pragma unroll
       for (int z = c; z < r; ++z) e = fma(Lc[r][z], W[z][c], e);
-      W[r][c] = -e / Lc[r][r];
+      W[r][c] = -e * rl[r];
     }
   }
   return spd;
@@ -1120,9 +1147,10 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
   double* c0 = a.c0 + (int64_t)col * (kNBlk * 16);
   double* pinv = a.pinv + (int64_t)col * (kNBlk * 16);
 
-  __shared__ double Lf[kMaxTri];     // the factor, packed lower triangle
+  __shared__ double Lf[kMaxTri];     // the column's Gram, then pivot-block buffers
   __shared__ double g1[kPad], g2[kPad], D[kPad], E[kPad], tn[kPad], mun[kPad];
-  __shared__ double colk[kPad], vbuf[kPad], rbuf[kPad], invd[kPad];
+  __shared__ double colk[kPad], vbuf[kPad], rbuf[kPad], dvec[kPad];
+  double* wbuf = Lf + 2 * kNBlkRows * 16;   // Gram forms: L_KK^-1 of every pivot block
   __shared__ __align__(16) double qsym[kSymvScratch];
   __shared__ double sc[4];
   __shared__ int fail;
@@ -1132,15 +1160,40 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
   const bool owner = tid < kNBlk;
   if (owner) block_coords(tid, bi, bj);
 
+  // The column's Gram of [y, 1, c], summed over its work items into LDS as
+  // a packed lower triangle (Lf is free until the factor is stored).  Thread
+  // t sums element t of every tile, so all of its loads of an item are in
+  // flight together; items are added in order, as before.
+  {
+    static_assert(kBlock == 256, "one tile element per thread");
+    double g[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) g[u] = 0.0;
+    for (int it = 0; it < ci.n_items; ++it) {
+      const double* Pi = P + (int64_t)it * T * 256 + tid;
+#pragma unroll
+      for (int u = 0; u < T; ++u) g[u] += Pi[256 * u];
+    }
+    const int mi = tid >> 4, mj = tid & 15;
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      const int I = tile_row(u), J = u - n_tiles(I);
+      const int bi = band_of<NB, WIDE>(I, mi), bj = band_of<NB, WIDE>(J, mj);
+      // off-diagonal tiles hold each band pair once; diagonal tiles twice
+      if (bi < B + 2 && bj < B + 2 && (I != J || bi >= bj))
+        Lf[bi >= bj ? tri(bi, bj) : tri(bj, bi)] = g[u];
+    }
+  }
+  if (tid == 0) fail = 0;
+  __syncthreads();
   if (tid == 0) {
-    sc[0] = gram_elem<NB, WIDE>(P, ci.n_items, B, B);          // N
-    sc[1] = gram_elem<NB, WIDE>(P, ci.n_items, B + 1, B);      // S1 = sum c
-    sc[2] = gram_elem<NB, WIDE>(P, ci.n_items, B + 1, B + 1);  // S2 = sum c^2
-    fail = 0;
+    sc[0] = Lf[tri(B, B)];                     // N
+    sc[1] = Lf[tri(B + 1, B)];                 // S1 = sum c
+    sc[2] = Lf[tri(B + 1, B + 1)];             // S2 = sum c^2
   }
   for (int b = tid; b < B; b += kBlock) {
-    g1[b] = gram_elem<NB, WIDE>(P, ci.n_items, B, b);
-    g2[b] = gram_elem<NB, WIDE>(P, ci.n_items, B + 1, b);
+    g1[b] = Lf[tri(B, b)];
+    g2[b] = Lf[tri(B + 1, b)];
   }
   __syncthreads();
   const double N = sc[0], S1 = sc[1], S2 = sc[2];
@@ -1171,7 +1224,7 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
       const int i = kBlk * bi + x, jj = kBlk * bj + y;
       double c = (i == jj) ? 1.0 : 0.0;        // padding keeps the factor regular
       if (owner && i < B && jj < B && i >= jj) {
-        c = gram_elem<NB, WIDE>(P, ci.n_items, i, jj);
+        c = Lf[tri(i, jj)];
         c += g1[i] * D[jj] + D[i] * g1[jj] + g2[i] * E[jj] + E[i] * g2[jj] +
              N * D[i] * D[jj] + S1 * (D[i] * E[jj] + E[i] * D[jj]) + S2 * E[i] * E[jj];
         c /= N;
@@ -1327,8 +1380,8 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
   // pivot block K - 1, into alternating LDS buffers: one barrier per pivot
   // block.  Padding rows (>= B) are decoupled with unit diagonal.
   {
-    double* cb0 = Lf;                       // two [kNBlkRows][4][4] buffers (Lf is
-    double* cb1 = Lf + kNBlkRows * 16;      // free until the factor is stored)
+    double* cb0 = Lf;                       // two [kNBlkRows][4][4] buffers
+    double* cb1 = Lf + kNBlkRows * 16;
     auto publish = [&](int K, double* cb) {
       if (owner && bj == K) {               // A_iK, i >= K
 #pragma unroll
@@ -1352,7 +1405,10 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
 #pragma unroll
           for (int x = 0; x < kBlk; ++x)
 #pragma unroll
-            for (int y = 0; y < kBlk; ++y) A_[x][y] = y <= x ? Lc[x][y] : 0.0;
+            for (int y = 0; y < kBlk; ++y) {
+              A_[x][y] = y <= x ? Lc[x][y] : 0.0;
+              wbuf[K * 16 + x * 4 + y] = y <= x ? W[x][y] : 0.0;
+            }
         } else if (bj == K) {                // panel
           double Y[kBlk][kBlk];
           mul_wt(cb + bi * 16, W, Y);
@@ -1379,19 +1435,6 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
       __syncthreads();
     }
   }
-  // factor -> LDS, inverse diagonal
-  if (owner) {
-#pragma unroll
-    for (int x = 0; x < kBlk; ++x)
-#pragma unroll
-      for (int y = 0; y < kBlk; ++y) {
-        const int i = kBlk * bi + x, jj = kBlk * bj + y;
-        if (i < B && jj <= i) {
-          Lf[tri(i, jj)] = A_[x][y];
-          if (i == jj) invd[i] = 1.0 / A_[x][y];
-        }
-      }
-  }
   // residual matrix: zero outside the lower triangle of the first B rows
 #pragma unroll
   for (int x = 0; x < kBlk; ++x)
@@ -1400,33 +1443,25 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
       const int i = kBlk * bi + x, jj = kBlk * bj + y;
       if (!(owner && i < B && jj <= i)) C_[x][y] = 0.0;
     }
-  for (int b = tid; b < kPad; b += kBlock) vbuf[b] = 0.0;
+  for (int b = tid; b < kPad; b += kBlock) {
+    rbuf[b] = b < B ? tn[b] : 0.0;
+    vbuf[b] = 0.0;
+    dvec[b] = 0.0;
+  }
   __syncthreads();
 
   // ---- v = C^-1 t, then refinement against the assembled C
-  double y_lo = 0.0, y_hi = 0.0, id_lo = 0.0, id_hi = 0.0;
-  if (wid == 0) {
-    y_lo = lane < B ? tn[lane] : 0.0;
-    y_hi = lane + 64 < B ? tn[lane + 64] : 0.0;
-    id_lo = lane < B ? invd[lane] : 0.0;
-    id_hi = lane + 64 < B ? invd[lane + 64] : 0.0;
-    wave_chol_solve(Lf, id_lo, id_hi, y_lo, y_hi, B, lane);
-    if (lane < B) vbuf[lane] = y_lo;
-    if (lane + 64 < B) vbuf[lane + 64] = y_hi;
-  }
-  __syncthreads();
-  for (int step = 0; step < a.refine; ++step) {
-    block_symv<1>(C_, owner, bi, bj, tid, B, vbuf, rbuf, qsym);   // C v
-    for (int b = tid; b < B; b += kBlock) rbuf[b] = tn[b] - rbuf[b];
-    __syncthreads();
-    if (wid == 0) {
-      double r_lo = lane < B ? rbuf[lane] : 0.0;
-      double r_hi = lane + 64 < B ? rbuf[lane + 64] : 0.0;
-      wave_chol_solve(Lf, id_lo, id_hi, r_lo, r_hi, B, lane);
-      if (lane < B) vbuf[lane] += r_lo;
-      if (lane + 64 < B) vbuf[lane + 64] += r_hi;
+  {
+    const int nkb = (B + kBlk - 1) / kBlk;
+    block_chol_solve(A_, owner, bi, bj, nkb, wbuf, rbuf, colk, vbuf);
+    for (int step = 0; step < a.refine; ++step) {
+      block_symv<1>(C_, owner, bi, bj, tid, B, vbuf, rbuf, qsym);   // C v
+      for (int b = tid; b < kPad; b += kBlock) rbuf[b] = b < B ? tn[b] - rbuf[b] : 0.0;
+      __syncthreads();
+      block_chol_solve(A_, owner, bi, bj, nkb, wbuf, rbuf, colk, dvec);
+      for (int b = tid; b < B; b += kBlock) vbuf[b] += dvec[b];
+      __syncthreads();
     }
-    __syncthreads();
   }
   }
   if (wid == 0) {

@@ -379,7 +379,6 @@ __global__ void __launch_bounds__(kBlock, ((MODE == PM_F64 && !SCORE) || MODE ==
   // The MFMA-bound Gram passes run one wave per SIMD: the next super-step's
   // loads are in flight while the current one is computed, and are waited
   // for only when they are moved into place after it.
-  [[maybe_unused]] int nsuper = 0;
   auto compute = [&](const float (&Lc)[8][NB], double apl, uint32_t vbl, int64_t bx) {
     [[maybe_unused]] bf16x8 ybf[NB];
     // SCORE: c = r alpha^{j-1} of pixel 4s + row of the super-step, or -1
@@ -512,28 +511,21 @@ __global__ void __launch_bounds__(kBlock, ((MODE == PM_F64 && !SCORE) || MODE ==
           acc[n_tiles(I) + J] =
               __builtin_amdgcn_mfma_f32_16x16x32_bf16(ybf[I], ybf[J], acc[n_tiles(I) + J], 0, 0, 0);
     }
-    if constexpr (F32ACC && FLUSH > 0) {
-      if (++nsuper == FLUSH) {
-        nsuper = 0;
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) dacc[t][i] += (double)acc[t][i];
-          acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-        }
-      }
-    }
   };
 
+  // The loop body runs FL super-steps, then flushes: the flush is not
+  // conditional, so the FP32 accumulators stay in the MFMA's registers.  A
+  // super-step past the item's end loads nothing and adds zeros.
+  constexpr int FL = FLUSH > 0 ? FLUSH : 1;
   int64_t base = begin + 32 * wid;
   if (base < end) {
     float LA[8][NB], LB[8][NB];
     double apA, apB;
     uint32_t vA, vB;
     load_super<NB, WIDE>(a, base, end, lane, row, c16, LA, apA, vA);
-    for (; base < end; base += 128) {
-      load_super<NB, WIDE>(a, base + 128, end, lane, row, c16, LB, apB, vB);
-      compute(LA, apA, vA, base);
+    auto super_step = [&](int64_t bx) {
+      load_super<NB, WIDE>(a, bx + 128, end, lane, row, c16, LB, apB, vB);
+      compute(LA, apA, vA, bx);
       __builtin_amdgcn_sched_barrier(0);   // the copy below waits for the loads
 #pragma unroll
       for (int s = 0; s < 8; ++s)
@@ -541,6 +533,20 @@ __global__ void __launch_bounds__(kBlock, ((MODE == PM_F64 && !SCORE) || MODE ==
         for (int k = 0; k < NB; ++k) LA[s][k] = LB[s][k];
       apA = apB;
       vA = vB;
+    };
+    if constexpr (FL == 1) {
+      for (; base < end; base += 128) super_step(base);
+    } else {
+      for (; base < end; base += 128 * FL) {
+#pragma unroll
+        for (int f = 0; f < FL; ++f) super_step(base + 128 * f);
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) dacc[t][i] += (double)acc[t][i];
+          acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
     }
   }
 

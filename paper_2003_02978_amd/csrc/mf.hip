@@ -205,7 +205,8 @@ __global__ void __launch_bounds__(64) setup_kernel(const float* __restrict__ L,
 // Per-pixel arithmetic (scores, albedo factor, alpha, moments) is FP64: near
 // the sparsity threshold the reweighting map alpha <- z - w has a derivative
 // far above 1 and amplifies any rounding, and FP64 costs the same VALU rate
-// as unpacked FP32 on CDNA.
+// as unpacked FP32 on CDNA.  The Gram inputs y of the FP32 and BF16 forms are
+// formed in FP32, the precision they are rounded to.
 
 // Loads through a buffer resource that covers [p, p + bytes): offsets at or
 // past the end read zeros (raw buffer range check), so a partial last group
@@ -376,7 +377,7 @@ __global__ void __launch_bounds__(kBlock, ((MODE == PM_F64 && !SCORE) || MODE ==
     for (int t = 0; t < T; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   }
 
-  // The MFMA-bound Gram passes run one wave per SIMD: the next super-step's
+  // The Gram passes run one or two waves per SIMD: the next super-step's
   // loads are in flight while the current one is computed, and are waited
   // for only when they are moved into place after it.
   auto compute = [&](const float (&Lc)[8][NB], double apl, uint32_t vbl, int64_t bx) {
@@ -1083,21 +1084,35 @@ __device__ void block_chol_solve(const double (&Lb)[kBlk][kBlk], bool owner, int
 // Cholesky factor L (lower) of a symmetric 4x4 block D (row-major, lower part
 // read) and W = L^-1 (lower); only the lower triangles of L and W are set.
 // False if a pivot is not positive (or not finite).
-__device__ __forceinline__ bool chol4(const double* D, double (&Lc)[kBlk][kBlk], double (&W)[kBlk][kBlk]) {
+// 1 / sqrt(d) for a normal d > 0: the hardware estimate refined by two
+// Newton-Raphson steps y <- y + y (1 - d y^2) / 2, each of which doubles the
+// number of correct bits (the pivot chain of a 4x4 factor is ~8 dependent
+// operations per column instead of a square root and a division).
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double e = fma(-d * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+template <typename Get>
+__device__ __forceinline__ bool chol4g(Get D, double (&Lc)[kBlk][kBlk], double (&W)[kBlk][kBlk]) {
   bool spd = true;
   double rl[kBlk];                             // 1 / L_cc
 #pragma unroll
   for (int c = 0; c < kBlk; ++c) {
-    double d = D[c * 4 + c];
+    double d = D(c, c);
 #pragma unroll
     for (int z = 0; z < c; ++z) d = fma(-Lc[c][z], Lc[c][z], d);
     spd = spd && d > 0.0 && isfinite(d);
-    const double l = sqrt(d);
-    rl[c] = 1.0 / l;
-    Lc[c][c] = l;
+    rl[c] = rsqrt_nr(d);
+    Lc[c][c] = d * rl[c];
 #pragma unroll
     for (int r = c + 1; r < kBlk; ++r) {
-      double e = D[r * 4 + c];
+      double e = D(r, c);
 #pragma unroll
       for (int z = 0; z < c; ++z) e = fma(-Lc[r][z], Lc[c][z], e);
       Lc[r][c] = e * rl[c];
@@ -1115,6 +1130,9 @@ __device__ __forceinline__ bool chol4(const double* D, double (&Lc)[kBlk][kBlk],
     }
   }
   return spd;
+}
+__device__ __forceinline__ bool chol4(const double* D, double (&Lc)[kBlk][kBlk], double (&W)[kBlk][kBlk]) {
+  return chol4g([&](int r, int c) { return D[r * 4 + c]; }, Lc, W);
 }
 
 // Y = C W^T for a 4x4 block C (row-major) and lower W.
@@ -1382,64 +1400,76 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
   // ---- blocked right-looking Cholesky on the register blocks.  For pivot
   // block K with D = A_KK = L_KK L_KK^T (W = L_KK^-1): the panel
   // A_iK <- A_iK W^T = L_iK (i > K), then A_ij -= L_iK L_jK^T (i >= j > K).
-  // Block column K is published by its owners right after their update of
-  // pivot block K - 1, into alternating LDS buffers: one barrier per pivot
-  // block.  Padding rows (>= B) are decoupled with unit diagonal.
+  // The owner of (K, K) factors it from its registers and publishes W; the
+  // panel threads form L_iK once and publish it; the trailing threads read
+  // it.  Two barriers per pivot block; the next pivot's factorisation uses
+  // only its owner's registers, and its barrier orders the reuse of the
+  // panel buffer.  Padding rows (>= B) are decoupled with unit diagonal.
   {
-    double* cb0 = Lf;                       // two [kNBlkRows][4][4] buffers
-    double* cb1 = Lf + kNBlkRows * 16;
-    auto publish = [&](int K, double* cb) {
-      if (owner && bj == K) {               // A_iK, i >= K
+    double* lpan = Lf;                      // [kNBlkRows][4][4]: L_iK of block column K
+    const int nkb = (B + kBlk - 1) / kBlk;
+    for (int K = 0; K < nkb; ++K) {
+      if (owner && bi == K && bj == K) {
+        double Lc[kBlk][kBlk], W[kBlk][kBlk];
+        if (!chol4g([&](int r, int c) { return A_[r][c]; }, Lc, W)) fail = 1;
 #pragma unroll
         for (int x = 0; x < kBlk; ++x)
 #pragma unroll
-          for (int y = 0; y < kBlk; ++y) cb[bi * 16 + x * 4 + y] = A_[x][y];
+          for (int y = 0; y < kBlk; ++y) {
+            A_[x][y] = y <= x ? Lc[x][y] : 0.0;
+            wbuf[K * 16 + x * 4 + y] = y <= x ? W[x][y] : 0.0;
+          }
       }
-    };
-    const int nkb = (B + kBlk - 1) / kBlk;
-    publish(0, cb0);
-    __syncthreads();
-    for (int K = 0; K < nkb; ++K) {
-      const double* cb = (K & 1) ? cb1 : cb0;
-      double Lc[kBlk][kBlk], W[kBlk][kBlk];
-      if (!chol4(cb + K * 16, Lc, W)) {      // uniform
+      __syncthreads();
+      if (fail) {                            // uniform
         if (tid == 0) st.status = MF_COL_NOT_SPD;
         return;
       }
-      if (owner && bj >= K) {
-        if (bi == K) {                       // (K, K): L_KK (upper half unused)
+      if (owner && bj == K && bi > K) {      // panel: L_iK = A_iK W^T (W lower)
+        double W[kBlk][kBlk], Y[kBlk][kBlk];
 #pragma unroll
-          for (int x = 0; x < kBlk; ++x)
+        for (int x = 0; x < kBlk; ++x)
 #pragma unroll
-            for (int y = 0; y < kBlk; ++y) {
-              A_[x][y] = y <= x ? Lc[x][y] : 0.0;
-              wbuf[K * 16 + x * 4 + y] = y <= x ? W[x][y] : 0.0;
-            }
-        } else if (bj == K) {                // panel
-          double Y[kBlk][kBlk];
-          mul_wt(cb + bi * 16, W, Y);
+          for (int y = 0; y < kBlk; ++y) W[x][y] = wbuf[K * 16 + x * 4 + y];
 #pragma unroll
-          for (int x = 0; x < kBlk; ++x)
+        for (int x = 0; x < kBlk; ++x)
 #pragma unroll
-            for (int y = 0; y < kBlk; ++y) A_[x][y] = Y[x][y];
-        } else {                             // trailing, bi >= bj > K
-          double Yi[kBlk][kBlk], Yj[kBlk][kBlk];
-          mul_wt(cb + bi * 16, W, Yi);
-          mul_wt(cb + bj * 16, W, Yj);
+          for (int y = 0; y < kBlk; ++y) {
+            double t = 0.0;
 #pragma unroll
-          for (int x = 0; x < kBlk; ++x)
+            for (int z = 0; z <= y; ++z) t = fma(A_[x][z], W[y][z], t);
+            Y[x][y] = t;
+          }
 #pragma unroll
-            for (int y = 0; y < kBlk; ++y) {
-              double t = A_[x][y];
+        for (int x = 0; x < kBlk; ++x)
 #pragma unroll
-              for (int z = 0; z < kBlk; ++z) t = fma(-Yi[x][z], Yj[y][z], t);
-              A_[x][y] = t;
-            }
-        }
+          for (int y = 0; y < kBlk; ++y) {
+            A_[x][y] = Y[x][y];
+            lpan[bi * 16 + x * 4 + y] = Y[x][y];
+          }
       }
-      if (K + 1 < nkb) publish(K + 1, (K & 1) ? cb0 : cb1);
       __syncthreads();
+      if (owner && bj > K) {                 // trailing, bi >= bj > K
+        double Li[kBlk][kBlk], Lj[kBlk][kBlk];
+#pragma unroll
+        for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+          for (int z = 0; z < kBlk; ++z) {
+            Li[x][z] = lpan[bi * 16 + x * 4 + z];
+            Lj[x][z] = lpan[bj * 16 + x * 4 + z];
+          }
+#pragma unroll
+        for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+          for (int y = 0; y < kBlk; ++y) {
+            double t = A_[x][y];
+#pragma unroll
+            for (int z = 0; z < kBlk; ++z) t = fma(-Li[x][z], Lj[y][z], t);
+            A_[x][y] = t;
+          }
+      }
     }
+    __syncthreads();
   }
   // residual matrix: zero outside the lower triangle of the first B rows
 #pragma unroll

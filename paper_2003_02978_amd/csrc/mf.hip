@@ -1678,17 +1678,14 @@ __device__ void r3_solve(const double (&Pb)[kBlk][kBlk], const double (&Cb)[kBlk
 // first (X = P U), C^0 only by the refinement, so its loads stay in flight
 // behind the products with P.  Every thread loads (threads past the owners
 // read block 0 and never use it), so the 32 loads issue back to back.
-__device__ void load_blocks(const double* c0, const double* pinv, bool owner, int tid,
-                            double (&Cb)[kBlk][kBlk], double (&Pb)[kBlk][kBlk]) {
+// The 4x4 register block of thread tid (< kNBlk) of a per-column matrix
+// stored element-major (C^0 or P).
+__device__ __forceinline__ void load_block(const double* m, bool owner, int tid, double (&Mb)[kBlk][kBlk]) {
   const int blk = owner ? tid : 0;
 #pragma unroll
   for (int x = 0; x < kBlk; ++x)
 #pragma unroll
-    for (int y = 0; y < kBlk; ++y) Pb[x][y] = pinv[blk_at(blk, x, y)];
-#pragma unroll
-  for (int x = 0; x < kBlk; ++x)
-#pragma unroll
-    for (int y = 0; y < kBlk; ++y) Cb[x][y] = c0[blk_at(blk, x, y)];
+    for (int y = 0; y < kBlk; ++y) Mb[x][y] = m[blk_at(blk, x, y)];
 }
 
 // S of the rank-3 identity:  N C^j = N C^0 + N a^2 D D^T + (S2 - N a^2) t t^T - (m t^T + t m^T)
@@ -1730,27 +1727,41 @@ __global__ void __launch_bounds__(kBlock) lowrank_kernel(SolveArgs a) {
     sm.X3[e] = acc;                              // scratch until r3_prepare
   }
   __syncthreads();
+  // P first, then the column's scalars and per-band state, then C^0: loads
+  // retire in order, so waiting for the state waits for P but not for C^0,
+  // which only the refinement needs.
+  static_assert(kBlock >= kPad, "one band per thread");
   double Cb[kBlk][kBlk], Pb[kBlk][kBlk];
-  load_blocks(a.c0 + (int64_t)col * (kNBlk * 16), a.pinv + (int64_t)col * (kNBlk * 16), owner, tid,
-              Cb, Pb);
+  load_block(a.pinv + (int64_t)col * (kNBlk * 16), owner, tid, Pb);
+  const double nv = st.n_valid;
+  double* eprev = a.energy ? a.energy + (int64_t)(a.j - 1) * a.n_cols + col : nullptr;
+  const double e_old = eprev ? *eprev : 0.0;
+  double lbar_b = 0.0, t_b = 0.0, s_b = 0.0;
+  if (tid < B) {
+    lbar_b = st.lbar[tid];
+    t_b = st.t[tid];
+    s_b = (double)a.s[tid];
+  }
+  load_block(a.c0 + (int64_t)col * (kNBlk * 16), owner, tid, Cb);
   if (tid == 0) {
     const double s1 = sm.X3[kVecS1], s2 = sm.X3[kVecS2];
-    sc[0] = st.n_valid;
+    sc[0] = nv;
     sc[1] = s1;
     sc[2] = s2;
-    rank3_S(sm.S3, s1 / st.n_valid, s2, st.n_valid);
-    if (a.energy) a.energy[(int64_t)(a.j - 1) * a.n_cols + col] += sm.X3[kVecE];
+    rank3_S(sm.S3, s1 / nv, s2, nv);
+    if (eprev) *eprev = e_old + sm.X3[kVecE];
   }
   __syncthreads();
   const double N = sc[0], S1 = sc[1], S2 = sc[2];
   const double abar = S1 / N;
-  for (int b = tid; b < kPad; b += kBlock) {
+  if (tid < kPad) {
+    const int b = tid;
     double m = 0.0, mu = 0.0, t = 0.0, d = 0.0;
     if (b < B) {
       m = sm.X3[b];
-      mu = st.lbar[b] - abar * st.t[b];          // Eq. 10
-      t = mu * (double)a.s[b];                   // Eq. 9
-      d = st.t[b] - t;
+      mu = lbar_b - abar * t_b;                  // Eq. 10
+      t = mu * s_b;                              // Eq. 9
+      d = t_b - t;
     }
     mun[b] = mu;
     sm.U3[b] = d;
@@ -2293,26 +2304,38 @@ __global__ void __launch_bounds__(kBlock) bwd_colA_kernel(BwColArgs a) {
     sm.X3[e] = acc;                              // scratch until r3_prepare
   }
   __syncthreads();
+  // P first, then the checkpointed state, then C^0 (as in lowrank_kernel)
+  static_assert(kBlock >= kPad, "one band per thread");
   double Cb[kBlk][kBlk], Pb[kBlk][kBlk];
-  load_blocks(a.c0 + (int64_t)col * (kNBlk * 16), a.pinv + (int64_t)col * (kNBlk * 16), owner, tid,
-              Cb, Pb);
+  load_block(a.pinv + (int64_t)col * (kNBlk * 16), owner, tid, Pb);
+  const double ab_k = ck[kCkScal + 0], s2_k = ck[kCkScal + 1];
+  const double* ckm1 = k >= 1 ? a.ck_km1 + (int64_t)col * kCk : nullptr;
+  double t_b = 0.0, tm1_b = 0.0, m_b = 0.0;
+  if (tid < kPad) {
+    t_b = ck[kCkT + tid];
+    if (k >= 1 && tid < B) {
+      tm1_b = ckm1[kCkT + tid];
+      m_b = ck[kCkM + tid];
+    }
+  }
+  load_block(a.c0 + (int64_t)col * (kNBlk * 16), owner, tid, Cb);
   if (tid == 0) {
     sc[0] = sm.X3[kBwQ1];
     sc[1] = sm.X3[kBwP1];
-    if (k >= 1) rank3_S(sm.S3, ck[kCkScal + 0], ck[kCkScal + 1], N);
+    if (k >= 1) rank3_S(sm.S3, ab_k, s2_k, N);
     else
       for (int e = 0; e < 9; ++e) sm.S3[e] = 0.0;
   }
   __syncthreads();
   const double qbar = -sc[0] / q, P1 = sc[1];
-  const double* ckm1 = k >= 1 ? a.ck_km1 + (int64_t)col * kCk : nullptr;
-  for (int b = tid; b < kPad; b += kBlock) {
+  if (tid < kPad) {
+    const int b = tid;
     const double V = b < B ? sm.X3[b] : 0.0;
-    const double t = ck[kCkT + b];
+    const double t = t_b;
     vbar[b] = b < B ? V + qbar * t : 0.0;
-    sm.U3[b] = (k >= 1 && b < B) ? ckm1[kCkT + b] - t : 0.0;
+    sm.U3[b] = (k >= 1 && b < B) ? tm1_b - t : 0.0;
     sm.U3[kPad + b] = (k >= 1 && b < B) ? t : 0.0;
-    sm.U3[2 * kPad + b] = (k >= 1 && b < B) ? ck[kCkM + b] : 0.0;
+    sm.U3[2 * kPad + b] = (k >= 1 && b < B) ? m_b : 0.0;
   }
   __syncthreads();
   r3_prepare(Pb, owner, bi, bj, tid, B, sm);

@@ -45,6 +45,18 @@ def test_tiny_scene(tiny, chunk, cov):
 
 
 @pytest.mark.parametrize("cov", EXACT)
+@pytest.mark.parametrize("refine", [0, 2])
+def test_refinement_step_counts(tiny, refine, cov):
+    """No refinement step and two steps of C^-1 t (the default is one): the
+    solves stay within the FP32 tolerance of the exact oracle."""
+    lam = config_lambda("tiny")
+    a, st = _gpu(tiny, n_iter=30, lam=lam, cov=cov, refine_steps=refine)
+    ref, rst = oracle_retrieve(tiny.radiance, tiny.s, 30, lam, workers=8)
+    np.testing.assert_array_equal(st, rst)
+    assert_fp32_parity(a, ref, label=f"tiny refine={refine} cov={cov}")
+
+
+@pytest.mark.parametrize("cov", EXACT)
 @pytest.mark.parametrize("albedo", [True, False])
 def test_zero_iterations_is_the_unclamped_filter(tiny, albedo, cov):
     a, st = _gpu(tiny, n_iter=0, lam=1.0, albedo=albedo, cov=cov)

@@ -945,6 +945,25 @@ __device__ __forceinline__ double wave_dot(const double* x, const double* y, int
   return s;
 }
 
+// R x C dot products d[r * C + c] = x_r . y_c of LDS vectors (x_r at x + r
+// kPad, y_c at y + c kPad, length B) on one wave, every lane getting all of
+// them; the same order of additions as wave_dot, with one butterfly for all.
+template <int R, int C>
+__device__ __forceinline__ void wave_dots(const double* x, const double* y, int B, int lane,
+                                          double (&d)[R * C]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      double s = 0.0;
+      for (int i = lane; i < B; i += 64) s += x[r * kPad + i] * y[c * kPad + i];
+      d[r * C + c] = s;
+    }
+  for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+    for (int e = 0; e < R * C; ++e) d[e] += __shfl_xor(d[e], off, 64);
+}
+
 // Block of the lower triangle owned by thread t (t = bi(bi+1)/2 + bj).
 __device__ __forceinline__ void block_coords(int t, int& bi, int& bj) {
   bi = 0;
@@ -1566,10 +1585,7 @@ __device__ void r3_prepare(const double (&Pb)[kBlk][kBlk], bool owner, int bi, i
   block_symv<3>(Pb, owner, bi, bj, tid, B, sm.U3, sm.X3, sm.qsym);
   if (wid == 0) {
     double W[9];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) W[r * 3 + c] = wave_dot(sm.U3 + r * kPad, sm.X3 + c * kPad, B, lane);
+    wave_dots<3, 3>(sm.U3, sm.X3, B, lane, W);
     if (lane == 0) {
       // Gauss-Jordan with partial pivoting on [M | I]; rows are exchanged by
       // selects, so every index is a compile-time constant (registers only)
@@ -1636,7 +1652,7 @@ __device__ void r3_solve(const double (&Pb)[kBlk][kBlk], const double (&Cb)[kBlk
   for (int step = 0; step <= refine; ++step) {
     if (wid == 0) {
       double u[3];
-      for (int r = 0; r < 3; ++r) u[r] = wave_dot(sm.U3 + r * kPad, sm.wbuf, B, lane);
+      wave_dots<3, 1>(sm.U3, sm.wbuf, B, lane, u);
       if (lane == 0) {
         double su[3];
         for (int r = 0; r < 3; ++r)
@@ -1658,7 +1674,7 @@ __device__ void r3_solve(const double (&Pb)[kBlk][kBlk], const double (&Cb)[kBlk
     block_symv<1>(Cb, owner, bi, bj, tid, B, sm.vbuf, sm.rbuf, sm.qsym);
     if (wid == 0) {
       double u[3];
-      for (int r = 0; r < 3; ++r) u[r] = wave_dot(sm.U3 + r * kPad, sm.vbuf, B, lane);
+      wave_dots<3, 1>(sm.U3, sm.vbuf, B, lane, u);
       if (lane == 0)
         for (int r = 0; r < 3; ++r)
           sm.zbuf[4 + r] = sm.S3[r * 3] * u[0] + sm.S3[r * 3 + 1] * u[1] + sm.S3[r * 3 + 2] * u[2];
@@ -1674,12 +1690,9 @@ __device__ void r3_solve(const double (&Pb)[kBlk][kBlk], const double (&Cb)[kBlk
   }
 }
 
-// Loads the register blocks of P and then C^0 of one column: P is needed
-// first (X = P U), C^0 only by the refinement, so its loads stay in flight
-// behind the products with P.  Every thread loads (threads past the owners
-// read block 0 and never use it), so the 32 loads issue back to back.
 // The 4x4 register block of thread tid (< kNBlk) of a per-column matrix
-// stored element-major (C^0 or P).
+// stored element-major (C^0 or P).  Every thread loads (threads past the
+// owners read block 0 and never use it), so the 16 loads issue back to back.
 __device__ __forceinline__ void load_block(const double* m, bool owner, int tid, double (&Mb)[kBlk][kBlk]) {
   const int blk = owner ? tid : 0;
 #pragma unroll

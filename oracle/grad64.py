@@ -60,7 +60,7 @@ def loss_and_grads(L, s, alpha_true, n_iter, lam, eps=1e-9, albedo=True, valid=N
             at = at[np.asarray(vc) != 0]
         J = J + ((a - torch.from_numpy(at)) ** 2).sum()
     J.backward()
-    return float(J), Lt.grad.numpy(), st.grad.numpy()
+    return float(J.detach()), Lt.grad.numpy(), st.grad.numpy()
 
 
 def loss_numpy(L, s, alpha_true, n_iter, lam, eps=1e-9, albedo=True, valid=None, columns=None):

@@ -21,6 +21,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "retrieved pixels/s (74 bands, 30 iters): BF16-MFMA vs FP32 plain; fwd+bwd px/s"
 HBM_PEAK_GBS = 8000.0
+# arithmetic of each covariance form: per-pixel scores, moments and solves
+# are FP64 in every form; the Gram forms accumulate their covariance on
+# FP64, FP32 or BF16 MFMA (the radiance input is FP32 throughout)
+FORM_DTYPE = {"lowrank": "f64", "fp64": "f64", "fp32": "f32 Gram, f64 scores and solves",
+              "bf16": "bf16 Gram (f32 accumulate), f64 scores and solves"}
 # Algorithmic bytes per pixel of one launch of each form's dominant kernel.
 # Low-rank streaming passes 1..K: the 74-band FP32 spectrum, alpha^{j-1}
 # written (FP64 working copy), and from pass 2 on alpha^{j-2} and r read;
@@ -306,16 +311,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32",
+        "dtype": FORM_DTYPE[head],
         "data": "synthetic",
         "config": {"workload": f"flightline {S}x{N}x{B}, {K} iterations, lambda {lam:.4g}, "
                                f"covariance form '{head}'",
                    "columns": S, "lines": N, "bands": B, "iterations": K,
-                   "covariance": head, "parallelism": "single GPU"},
+                   "covariance": head, "radiance": "f32", "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "hbm_fraction_whole_job": round(whole_job_GBps / HBM_PEAK_GBS, 4),
-        "forms": {f: {"px_per_s": round(r["px_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+        "forms": {f: {"dtype": FORM_DTYPE[f],
+                      "px_per_s": round(r["px_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                       "kernels_ms_per_step": r["kernels_ms_per_step"],
                       "dominant_kernel": r["dominant_kernel"],
                       "dominant_GBps": round(r["dominant_GBps"], 1),

@@ -338,8 +338,9 @@ def main():
 
 
 def _stable_from(E, rtol):
-    """First k such that |E^j - E^{j-1}| <= rtol |E^j| for every j >= k
-    (None if the last step still exceeds it)."""
+    """First k such that |E^j - E^{j-1}| <= rtol |E^j| for every j > k: the
+    energy changes by at most rtol per step from E^k on (None if the last
+    step still exceeds it)."""
     import numpy as np
     d = np.abs(np.diff(E)) <= rtol * np.abs(E[1:])
     if not d[-1]:

@@ -52,7 +52,7 @@ extern "C" {
 #define MF_API
 #endif
 
-#define MF_ABI_VERSION 3
+#define MF_ABI_VERSION 4
 #define MF_MAX_BANDS 78      /* B + 2 <= 80: five 16-band MFMA blocks */
 
 typedef struct mf_plan_s* mf_plan;
@@ -81,9 +81,16 @@ typedef enum {
   MF_COV_LOWRANK = 0,    /* default.  C^0 from one exact Gram (FP64 MFMA); C^k
                             from C^0 by an exact rank-3 update built from
                             sum c_i (L_i - mean L), sum c_i, sum c_i^2 */
-  MF_COV_GRAM_FP64 = 1,  /* a Gram of the residuals every iteration, FP64 MFMA */
-  MF_COV_GRAM_FP32 = 2,  /* ... on FP32 MFMA, flushed to FP64 every 64 pixels */
-  MF_COV_GRAM_BF16 = 3   /* ... with BF16 operands on MFMA (FP32 accumulate) */
+  MF_COV_GRAM_FP64 = 1,  /* a Gram of the residuals every iteration (the
+                            paper's canonical formulas, Sec. II-E), FP64 MFMA */
+  MF_COV_GRAM_FP32 = 2,  /* ... on FP32 MFMA (FP32 accumulation per wave,
+                            FP64 across waves and work items) */
+  MF_COV_GRAM_BF16 = 3   /* ... with BF16 operands on MFMA (FP32 accumulate).
+                            In both rounded forms the FP64 Cholesky factor of
+                            the rounded C^k preconditions iterative refinement
+                            whose residual t - C^k v takes C^k exactly (C^0
+                            from the FP64 Gram of the first pass plus the
+                            rank-3 update from FP64 moments of the same pass) */
 } mf_cov;
 
 typedef struct {
@@ -97,7 +104,10 @@ typedef struct {
                              1 = the paper's Eq. 5; 0 = no sparsity prior. */
   double   epsilon;       /* > 0, ppm*m (Eq. 5) */
   int32_t  cov;           /* mf_cov */
-  int32_t  refine_steps;  /* iterative-refinement steps of C^-1 t (0..4; 1 = default) */
+  int32_t  refine_steps;  /* iterative-refinement steps of C^-1 t, 0..8, or -1
+                             for the form's default: 1 for the exact forms, 3
+                             for MF_COV_GRAM_FP32, 5 for MF_COV_GRAM_BF16 (the
+                             steps that take the rounded forms to FP64 rounding) */
   int32_t  save_for_backward; /* 1: mf_retrieve keeps alpha^0..alpha^K and the
                              per-iteration column state for mf_backward (needs
                              MF_COV_LOWRANK and n_iter <= 30; larger workspace) */
@@ -123,7 +133,7 @@ typedef struct {
 MF_API int mf_abi_version(void);
 
 /* Fills *opt with defaults: B = 74, K = 30, albedo on, lambda 1, eps 1e-9,
-   low-rank covariance form, one refinement step, automatic chunking. */
+   low-rank covariance form, the form's refinement steps, automatic chunking. */
 MF_API void mf_options_default(mf_options* opt);
 
 /* Static text for a status code (never NULL). */

@@ -25,7 +25,7 @@ EXPORTS = ("mf_abi_version", "mf_options_default", "mf_status_str", "mf_last_err
            "mf_plan_kernel_times", "mf_plan_energy", "mf_repack_bil", "mf_stream_read",
            "mf_plan_destroy")
 KERNEL_KINDS = ("pass_gram", "pass_vec", "pass_last", "solve", "other")
-ABI_VERSION = 3          # MF_ABI_VERSION of include/mf.h (mf_options layout)
+ABI_VERSION = 4          # MF_ABI_VERSION of include/mf.h (mf_options layout)
 
 
 class Options(ctypes.Structure):
@@ -119,7 +119,7 @@ class Plan:
 
     def __init__(self, flightlines: Iterable[Tuple[int, int, int]], n_bands: int = 74,
                  n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9, albedo: bool = True,
-                 cov: str = "lowrank", refine_steps: int = 1, chunk_lines: int = 0,
+                 cov: str = "lowrank", refine_steps: int = -1, chunk_lines: int = 0,
                  save_for_backward: bool = False, group: int = 1, track_energy: bool = False):
         lib = load_library()
         o = default_options()
@@ -374,7 +374,7 @@ _RetrieveFunction = None
 
 
 def retrieve_differentiable(radiance, s, n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9,
-                            albedo: bool = True, valid=None, refine_steps: int = 1,
+                            albedo: bool = True, valid=None, refine_steps: int = -1,
                             chunk_lines: int = 0, group: int = 1):
     """alpha [S, N] with autograd support (radiance and s), low-rank form."""
     global _RetrieveFunction
@@ -394,7 +394,7 @@ def _need(t, dtype, name):
 
 
 def retrieve(radiance, s, n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9,
-             albedo: bool = True, cov: str = "lowrank", valid=None, refine_steps: int = 1,
+             albedo: bool = True, cov: str = "lowrank", valid=None, refine_steps: int = -1,
              chunk_lines: int = 0, group: int = 1):
     """Retrieve alpha (ppm*m) for a [S, N, B] float32 radiance cube on the GPU.
 

@@ -61,10 +61,14 @@ enum PassMode {
   PM_NONE = 0,   // last pass: alpha only
   PM_VEC = 1,    // m = sum c (L - mean L), S1, S2 in FP64 (low-rank form)
   PM_F64 = 2,    // Gram of [y, 1, c] on v_mfma_f64_16x16x4_f64 (exact)
-  PM_F32 = 3,    // Gram on v_mfma_f32_16x16x4_f32, FP64 flush every 64 px
+  PM_F32 = 3,    // Gram on v_mfma_f32_16x16x4_f32, FP32 accumulation per wave
   PM_BF16 = 4    // Gram on v_mfma_f32_16x16x32_bf16, FP32 accumulation per wave
 };
 constexpr int kVecS1 = 80, kVecS2 = 81;   // PM_VEC partial layout: m in [0, B)
+// FP32 / BF16 Gram passes: after the T tiles of the item's partial Gram, the
+// exact FP64 moments sum c L (bands [0, 80)), sum c, sum c^2.
+constexpr int kXS1 = 80, kXS2 = 81, kXMom = 82;
+constexpr int kXMomSlots = 128;            // doubles reserved per item for them
 constexpr int kVecE = 82;      // energy: pixel part of E^{j-1} (both streaming modes)
 
 // One partition (Sec. II-E): `group` adjacent detector columns of a
@@ -130,6 +134,8 @@ struct SolveArgs {
   int j;
   int refine;
   int lowrank;
+  int exact_ref;             // FP32 / BF16 Gram forms: refine against the exact C^j
+                             // (C^0 + rank-3 update) and keep C^0 from pass 0
   int partial_stride;        // doubles per work item in the partial buffer
   double* ck;                // save_for_backward: column checkpoints [K+1][n_cols][kCk]
   double* energy;            // track_energy: E^k per partition [K+1][n_cols], or null
@@ -314,14 +320,17 @@ __device__ __forceinline__ void load_super(const PassArgs& a, int64_t base, int6
 // SCORE: passes j >= 1 (alpha^{j-1} and c = r alpha enter the Gram); pass 0
 // (SCORE = false) is the Gram of the shifted radiance alone.
 template <int NB, bool WIDE, int MODE, bool SCORE>
-__global__ void __launch_bounds__(kBlock, ((MODE == PM_F64 && !SCORE) || MODE == PM_BF16) ? 2 : 1) pass_kernel(PassArgs a) {
+__global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && SCORE) ? 1 : 2) pass_kernel(PassArgs a) {
   constexpr int T = n_tiles(NB);
   static_assert(MODE >= PM_F64, "the Gram pass; the streaming passes are stream_kernel");
   constexpr bool F32ACC = MODE == PM_F32 || MODE == PM_BF16;
-  // FP32 Gram: FP64 flush every 2 super-steps (64 pixels).  BF16 Gram: FP32
-  // accumulation over the wave's share of the item (its inputs carry 8-bit
-  // mantissas, far coarser than the FP32 sums), FP64 only across waves and items.
-  constexpr int FLUSH = MODE == PM_F32 ? 2 : 0;
+  // FP32 and BF16 Gram: FP32 accumulation over the wave's share of the item,
+  // FP64 only across waves and items.  The rounded Gram only preconditions
+  // the solve, which refines against the exact C^j (see solve_kernel), so
+  // its accumulation error sets the refinement's rate, not the result.
+  // The rounded forms also accumulate, exactly in FP64, the moments of the
+  // rank-3 identity for C^j: sum c L (per band), sum c and sum c^2.
+  constexpr bool XMOM = SCORE && F32ACC;
   const WorkItem it = a.items[blockIdx.x];
   const ColState& st = a.state[it.col];
   const int tid = threadIdx.x;
@@ -369,6 +378,12 @@ __global__ void __launch_bounds__(kBlock, ((MODE == PM_F64 && !SCORE) || MODE ==
   const int j = a.j;
 
   [[maybe_unused]] floatx4 acc[F32ACC ? T : 1];
+  // XMOM: the wave's sums of c L per band, sum c and sum c^2, in LDS (only
+  // super-steps with a nonzero c add to them, so no register holds them)
+  __shared__ double xred[XMOM ? 4 : 1][kXMom];
+  if constexpr (XMOM) {
+    for (int e = lane; e < kXMom; e += 64) xred[wid][e] = 0.0;
+  }
   doublex4 dacc[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) dacc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
@@ -447,6 +462,40 @@ __global__ void __launch_bounds__(kBlock, ((MODE == PM_F64 && !SCORE) || MODE ==
       const double cenc = ok ? ((!dark && al > 0.0) ? r * al : 0.0) : -1.0;
 #pragma unroll
       for (int s = 0; s < 8; ++s) cs[s] = __shfl(cenc, 4 * s + row, 64);
+      if constexpr (XMOM) {
+        // only where some pixel of the super-step has c > 0 (the enhancement
+        // is sparse); the test is wave-uniform
+        if (__ballot(cenc > 0.0) != 0ull) {
+          double c1 = (lane < 32 && cenc > 0.0) ? cenc : 0.0;
+          double c2 = c1 * c1;
+          for (int off = 32; off >= 1; off >>= 1) {
+            c1 += __shfl_xor(c1, off, 64);
+            c2 += __shfl_xor(c2, off, 64);
+          }
+          // one band block at a time into LDS, so that no register holds a
+          // running sum across the pass (the rows hold the same bands of
+          // different pixels)
+#pragma unroll
+          for (int k = 0; k < NB; ++k) {
+            double x = 0.0;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+              // a fresh value: the FP64 conversions of the scores above are
+              // not kept alive for this rarely taken branch
+              float l = Lc[s][k];
+              asm volatile("" : "+v"(l));
+              x = cs[s] > 0.0 ? fma(cs[s], (double)l, x) : x;   // invalid rows may hold NaN
+            }
+            x += __shfl_xor(x, 16, 64);
+            x += __shfl_xor(x, 32, 64);
+            if (lane < 16) xred[wid][band_of<NB, WIDE>(k, c16)] += x;
+          }
+          if (lane == 0) {
+            xred[wid][kXS1] += c1;
+            xred[wid][kXS2] += c2;
+          }
+        }
+      }
     }
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
@@ -514,10 +563,6 @@ __global__ void __launch_bounds__(kBlock, ((MODE == PM_F64 && !SCORE) || MODE ==
     }
   };
 
-  // The loop body runs FL super-steps, then flushes: the flush is not
-  // conditional, so the FP32 accumulators stay in the MFMA's registers.  A
-  // super-step past the item's end loads nothing and adds zeros.
-  constexpr int FL = FLUSH > 0 ? FLUSH : 1;
   int64_t base = begin + 32 * wid;
   if (base < end) {
     float LA[8][NB], LB[8][NB];
@@ -535,23 +580,15 @@ __global__ void __launch_bounds__(kBlock, ((MODE == PM_F64 && !SCORE) || MODE ==
       apA = apB;
       vA = vB;
     };
-    if constexpr (FL == 1) {
-      for (; base < end; base += 128) super_step(base);
-    } else {
-      for (; base < end; base += 128 * FL) {
-#pragma unroll
-        for (int f = 0; f < FL; ++f) super_step(base + 128 * f);
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) dacc[t][i] += (double)acc[t][i];
-          acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-        }
-      }
-    }
+    for (; base < end; base += 128) super_step(base);
   }
 
-  double* out = a.partials + (int64_t)blockIdx.x * (T * 256);
+  double* out = a.partials + (int64_t)blockIdx.x * a.partial_stride;
+  if constexpr (XMOM) {
+    // the exact moments: the waves' sums in order
+    __syncthreads();
+    if (tid < kXMom) out[T * 256 + tid] = ((xred[0][tid] + xred[1][tid]) + xred[2][tid]) + xred[3][tid];
+  }
   if constexpr (F32ACC) {
 #pragma unroll
     for (int t = 0; t < T; ++t)
@@ -1171,6 +1208,25 @@ __device__ __forceinline__ void mul_wt(const double* C, const double (&W)[kBlk][
   }
 }
 
+// The 4x4 register block of thread tid (< kNBlk) of a per-column matrix
+// stored element-major (C^0 or P).  Every thread loads (threads past the
+// owners read block 0 and never use it), so the 16 loads issue back to back.
+__device__ __forceinline__ void load_block(const double* m, bool owner, int tid, double (&Mb)[kBlk][kBlk]) {
+  const int blk = owner ? tid : 0;
+#pragma unroll
+  for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+    for (int y = 0; y < kBlk; ++y) Mb[x][y] = m[blk_at(blk, x, y)];
+}
+
+// S of the rank-3 identity:  N C^j = N C^0 + N a^2 D D^T + (S2 - N a^2) t t^T - (m t^T + t m^T)
+// for U = [D, t, m].
+__device__ void rank3_S(double* S3, double abar, double S2, double N) {
+  S3[0] = abar * abar; S3[1] = 0.0;                     S3[2] = 0.0;
+  S3[3] = 0.0;         S3[4] = S2 / N - abar * abar;    S3[5] = -1.0 / N;
+  S3[6] = 0.0;         S3[7] = -1.0 / N;                S3[8] = 0.0;
+}
+
 // Column checkpoint of iteration k (save_for_backward): mu, t, v, m, a, S2, q, N.
 constexpr int kCkMu = 0, kCkT = kPad, kCkV = 2 * kPad, kCkM = 3 * kPad, kCkScal = 4 * kPad;
 constexpr int kCk = 4 * kPad + 8;
@@ -1186,7 +1242,9 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
   const int B = a.B;
   const int j = a.j;
   constexpr int T = n_tiles(NB);
-  const double* P = a.partials + (int64_t)ci.first_item * T * 256;
+  const int64_t pstride = a.partial_stride;
+  const double* P = a.partials + (int64_t)ci.first_item * pstride;
+  const bool xref = a.exact_ref && j >= 1;
   double* c0 = a.c0 + (int64_t)col * (kNBlk * 16);
   double* pinv = a.pinv + (int64_t)col * (kNBlk * 16);
 
@@ -1197,6 +1255,11 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
   __shared__ __align__(16) double qsym[kSymvScratch];
   __shared__ double sc[4];
   __shared__ int fail;
+  // exact refinement (rounded forms): U = [t^{j-1} - t^j, t^j, m] and S of the
+  // rank-3 identity, sum c L and sum c, sum c^2 of the pass (FP64)
+  __shared__ double U3[3 * kPad];
+  __shared__ double xmom[kXMom];
+  __shared__ double S3[9], zb[4];
 
   // block owned by this thread
   int bi = 0, bj = 0;
@@ -1213,7 +1276,7 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
 #pragma unroll
     for (int u = 0; u < T; ++u) g[u] = 0.0;
     for (int it = 0; it < ci.n_items; ++it) {
-      const double* Pi = P + (int64_t)it * T * 256 + tid;
+      const double* Pi = P + (int64_t)it * pstride + tid;
 #pragma unroll
       for (int u = 0; u < T; ++u) g[u] += Pi[256 * u];
     }
@@ -1225,6 +1288,14 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
       // off-diagonal tiles hold each band pair once; diagonal tiles twice
       if (bi < B + 2 && bj < B + 2 && (I != J || bi >= bj))
         Lf[bi >= bj ? tri(bi, bj) : tri(bj, bi)] = g[u];
+    }
+  }
+  if (xref) {
+    // the exact moments of the column, items in order
+    for (int e = tid; e < kXMom; e += kBlock) {
+      double acc = 0.0;
+      for (int it = 0; it < ci.n_items; ++it) acc += P[(int64_t)it * pstride + T * 256 + e];
+      xmom[e] = acc;
     }
   }
   if (tid == 0) fail = 0;
@@ -1248,13 +1319,25 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
     if (j == 0) {
       m = mu_used + g1[b] / N;                 // mu^0 = z + mean(L - z)
     } else {
-      m = st.lbar[b] - (S1 / N) * st.t[b];     // Eq. 10: mean(L) - mean(c) t^{j-1}
+      // Eq. 10: mean(L) - mean(c) t^{j-1}, with the exact sum c in the rounded forms
+      m = st.lbar[b] - ((xref ? xmom[kXS1] : S1) / N) * st.t[b];
     }
     mun[b] = m;
     tn[b] = m * sb;                            // Eq. 9
     D[b] = mu_used - m;
     E[b] = j == 0 ? 0.0 : t_used - tn[b];
+    if (xref) {
+      U3[b] = t_used - tn[b];
+      U3[kPad + b] = tn[b];
+      U3[2 * kPad + b] = xmom[b] - xmom[kXS1] * st.lbar[b];   // m = sum c (L - mean L)
+    }
   }
+  for (int b = B + tid; b < kPad; b += kBlock) {
+    U3[b] = 0.0;
+    U3[kPad + b] = 0.0;
+    U3[2 * kPad + b] = 0.0;
+  }
+  if (xref && tid == 0) rank3_S(S3, xmom[kXS1] / N, xmom[kXS2], N);
   __syncthreads();
 
   // ---- assembly of C (Eq. 11) into the register blocks
@@ -1278,12 +1361,13 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
       A_[x][y] = c;
       C_[x][y] = c;
     }
-  if (owner && a.lowrank && j == 0) {
+  if (owner && (a.lowrank || a.exact_ref) && j == 0) {
 #pragma unroll
     for (int x = 0; x < kBlk; ++x)
 #pragma unroll
       for (int y = 0; y < kBlk; ++y) c0[blk_at(tid, x, y)] = A_[x][y];
   }
+
   if (myfail) fail = 1;
   __syncthreads();
   if (N <= (double)B) {
@@ -1490,6 +1574,9 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
     }
     __syncthreads();
   }
+  // rounded forms: the refinement's residual matrix is C^0 (+ the rank-3
+  // term), not the C assembled from the rounded Gram
+  if (xref) load_block(c0, owner, tid, C_);
   // residual matrix: zero outside the lower triangle of the first B rows
 #pragma unroll
   for (int x = 0; x < kBlk; ++x)
@@ -1505,13 +1592,28 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
   }
   __syncthreads();
 
-  // ---- v = C^-1 t, then refinement against the assembled C
+  // ---- v = C^-1 t, then refinement.  The exact forms refine against the C
+  // they assembled.  The rounded forms' factor only preconditions: their
+  // residual t - C^j v takes C^j = C^0 + U S U^T exactly (the rank-3
+  // identity, from the FP64 C^0 of pass 0 and this pass's FP64 moments), so
+  // each step contracts the error by about |I - C_f^-1 C^j| (1e-3 for the
+  // FP32 Gram, 2e-2 for BF16) down to FP64 rounding.
   {
     const int nkb = (B + kBlk - 1) / kBlk;
     block_chol_solve(A_, owner, bi, bj, nkb, wbuf, rbuf, colk, vbuf);
     for (int step = 0; step < a.refine; ++step) {
-      block_symv<1>(C_, owner, bi, bj, tid, B, vbuf, rbuf, qsym);   // C v
-      for (int b = tid; b < kPad; b += kBlock) rbuf[b] = b < B ? tn[b] - rbuf[b] : 0.0;
+      if (xref && wid == 0) {
+        double u[3];
+        wave_dots<3, 1>(U3, vbuf, B, lane, u);
+        if (lane == 0)
+          for (int r = 0; r < 3; ++r) zb[r] = S3[r * 3] * u[0] + S3[r * 3 + 1] * u[1] + S3[r * 3 + 2] * u[2];
+      }
+      block_symv<1>(C_, owner, bi, bj, tid, B, vbuf, rbuf, qsym);   // C v (C^0 v)
+      for (int b = tid; b < kPad; b += kBlock) {
+        double cv = rbuf[b];
+        if (xref) cv += U3[b] * zb[0] + U3[kPad + b] * zb[1] + U3[2 * kPad + b] * zb[2];
+        rbuf[b] = b < B ? tn[b] - cv : 0.0;
+      }
       __syncthreads();
       block_chol_solve(A_, owner, bi, bj, nkb, wbuf, rbuf, colk, dvec);
       for (int b = tid; b < B; b += kBlock) vbuf[b] += dvec[b];
@@ -1690,24 +1792,7 @@ __device__ void r3_solve(const double (&Pb)[kBlk][kBlk], const double (&Cb)[kBlk
   }
 }
 
-// The 4x4 register block of thread tid (< kNBlk) of a per-column matrix
-// stored element-major (C^0 or P).  Every thread loads (threads past the
-// owners read block 0 and never use it), so the 16 loads issue back to back.
-__device__ __forceinline__ void load_block(const double* m, bool owner, int tid, double (&Mb)[kBlk][kBlk]) {
-  const int blk = owner ? tid : 0;
-#pragma unroll
-  for (int x = 0; x < kBlk; ++x)
-#pragma unroll
-    for (int y = 0; y < kBlk; ++y) Mb[x][y] = m[blk_at(blk, x, y)];
-}
 
-// S of the rank-3 identity:  N C^j = N C^0 + N a^2 D D^T + (S2 - N a^2) t t^T - (m t^T + t m^T)
-// for U = [D, t, m].
-__device__ void rank3_S(double* S3, double abar, double S2, double N) {
-  S3[0] = abar * abar; S3[1] = 0.0;                     S3[2] = 0.0;
-  S3[3] = 0.0;         S3[4] = S2 / N - abar * abar;    S3[5] = -1.0 / N;
-  S3[6] = 0.0;         S3[7] = -1.0 / N;                S3[8] = 0.0;
-}
 
 
 // Low-rank form, iterations j >= 1: mu^j (Eq. 10), t^j (Eq. 9), C^j by the
@@ -2758,13 +2843,11 @@ void launch_pass_nb(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t
       if (sc) hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F64, true>), g, b, 0, s, a);
       else hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F64, false>), g, b, 0, s, a);
       break;
-    case PM_F32:
-      if (sc) hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F32, true>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F32, false>), g, b, 0, s, a);
+    case PM_F32:      // scored passes only (pass 0 is FP64 in every form)
+      hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F32, true>), g, b, 0, s, a);
       break;
     default:
-      if (sc) hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16, true>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16, false>), g, b, 0, s, a);
+      hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16, true>), g, b, 0, s, a);
       break;
   }
 }
@@ -2803,12 +2886,34 @@ void dispatch_solve(const mf_plan_s* p, const SolveArgs& a, hipStream_t s) {
   }
 }
 
+// Doubles per work item in the partial buffer: the item's partial Gram (T
+// tiles of 16 x 16; the low-rank form's vector moments fit in it), plus the
+// exact moments of the rounded Gram forms.
+int64_t partial_stride(const mf_plan_s* p) {
+  const bool rounded = p->opt.cov == MF_COV_GRAM_FP32 || p->opt.cov == MF_COV_GRAM_BF16;
+  return (int64_t)n_tiles(p->nb) * 256 + (rounded ? kXMomSlots : 0);
+}
+
+// Refinement steps of a form when the options ask for the default (-1): the
+// exact forms refine once; the rounded Gram forms converge to FP64 rounding
+// in 3 (FP32 Gram) and 5 (BF16 Gram) steps against the exact C^j.
+int refine_steps_of(const mf_options& o) {
+  if (o.refine_steps >= 0) return o.refine_steps;
+  switch (o.cov) {
+    case MF_COV_GRAM_FP32: return 3;
+    case MF_COV_GRAM_BF16: return 5;
+    default: return 1;
+  }
+}
+
 // Pass mode of pass j for a covariance form.
 int pass_mode(int cov, int j, int K) {
   if (j == K + 1) return PM_NONE;
+  // pass 0 is the exact FP64 Gram in every form: C^0 anchors the rounded
+  // forms' refinement (and gives the exact alpha^0)
   switch (cov) {
-    case MF_COV_GRAM_FP32: return PM_F32;
-    case MF_COV_GRAM_BF16: return PM_BF16;
+    case MF_COV_GRAM_FP32: return j == 0 ? PM_F64 : PM_F32;
+    case MF_COV_GRAM_BF16: return j == 0 ? PM_F64 : PM_BF16;
     case MF_COV_GRAM_FP64: return PM_F64;
     default: return j == 0 ? PM_F64 : PM_VEC;   // MF_COV_LOWRANK
   }
@@ -2847,18 +2952,19 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   pa.lam = p->opt.lambda;
   pa.eps = p->opt.epsilon;
   pa.n_floats = p->max_px * B;
-  pa.partial_stride = n_tiles(p->nb) * 256;
+  pa.partial_stride = (int)partial_stride(p);
   SolveArgs sa{};
   sa.cols = p->cols_d;
   sa.state = state;
   sa.partials = partials;
   sa.c0 = (double*)(ws + p->off_c0);
   sa.pinv = (double*)(ws + p->off_pinv);
-  sa.partial_stride = n_tiles(p->nb) * 256;
+  sa.partial_stride = (int)partial_stride(p);
   sa.s = s;
   sa.B = B;
-  sa.refine = p->opt.refine_steps;
+  sa.refine = refine_steps_of(p->opt);
   sa.lowrank = p->opt.cov == MF_COV_LOWRANK;
+  sa.exact_ref = p->opt.cov == MF_COV_GRAM_FP32 || p->opt.cov == MF_COV_GRAM_BF16;
   sa.ck = p->opt.save_for_backward ? (double*)(ws + p->off_ck_col) : nullptr;
   sa.n_cols = (int)p->n_cols;
   sa.energy = energy;
@@ -2899,7 +3005,7 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
     LaunchTimer tm(p, MF_KERNEL_OTHER, st);
     hipLaunchKernelGGL(energy_last_kernel, dim3((unsigned)((p->n_cols + 255) / 256)), dim3(256), 0, st,
                        (const ColInfo*)p->cols_d, (const ColState*)state, (const double*)partials,
-                       (int64_t)n_tiles(p->nb) * 256, energy + (int64_t)K * p->n_cols, p->n_cols);
+                       partial_stride(p), energy + (int64_t)K * p->n_cols, p->n_cols);
   }
   if (column_status) {
     const unsigned nb = (unsigned)((p->n_cols + 255) / 256);
@@ -2924,7 +3030,7 @@ void mf_options_default(mf_options* o) {
   o->lambda = 1.0;
   o->epsilon = 1e-9;
   o->cov = MF_COV_LOWRANK;
-  o->refine_steps = 1;
+  o->refine_steps = -1;
   o->save_for_backward = 0;
   o->chunk_lines = 0;
   o->group = 1;
@@ -2962,8 +3068,8 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   if (opt->albedo != 0 && opt->albedo != 1) return fail_with(MF_E_ARG, "albedo must be 0 or 1");
   if (opt->cov < MF_COV_LOWRANK || opt->cov > MF_COV_GRAM_BF16)
     return fail_with(MF_E_ARG, "cov must be one of MF_COV_*");
-  if (opt->refine_steps < 0 || opt->refine_steps > 4)
-    return fail_with(MF_E_ARG, "refine_steps must be in [0, 4]");
+  if (opt->refine_steps < -1 || opt->refine_steps > 8)
+    return fail_with(MF_E_ARG, "refine_steps must be -1 (the form's default) or in [0, 8]");
   if (opt->save_for_backward != 0 && opt->save_for_backward != 1)
     return fail_with(MF_E_ARG, "save_for_backward must be 0 or 1");
   if (opt->save_for_backward && opt->cov != MF_COV_LOWRANK)
@@ -3047,14 +3153,13 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
     delete p;
     return fail_with(MF_E_DEVICE, "plan tables: " + e);
   }
-  const size_t T = (size_t)n_tiles(p->nb);
   size_t off = 0;
   p->off_state = off;
   off = align256(off + (size_t)p->n_cols * sizeof(ColState));
   p->off_partials = off;
-  off = align256(off + (size_t)p->n_items * T * 256 * sizeof(double));
+  off = align256(off + (size_t)p->n_items * (size_t)partial_stride(p) * sizeof(double));
   p->off_c0 = off;
-  if (opt->cov == MF_COV_LOWRANK) off = align256(off + (size_t)p->n_cols * kNBlk * 16 * sizeof(double));
+  if (opt->cov != MF_COV_GRAM_FP64) off = align256(off + (size_t)p->n_cols * kNBlk * 16 * sizeof(double));
   p->off_pinv = off;
   if (opt->cov == MF_COV_LOWRANK) off = align256(off + (size_t)p->n_cols * kNBlk * 16 * sizeof(double));
   p->off_alpha0 = off;
@@ -3163,7 +3268,7 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
   double* coef = (double*)(ws + p->off_bw_coef);
   double* u_hist = (double*)(ws + p->off_bw_u);
   double* bwcol = (double*)(ws + p->off_bw_col);
-  const int pstride = n_tiles(p->nb) * 256;
+  const int pstride = (int)partial_stride(p);
   (void)hipGetLastError();
   {
     const int64_t n = p->n_cols * kBw;

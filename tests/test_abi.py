@@ -24,13 +24,13 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(mf.EXPORTS)
-    assert lib.mf_abi_version() == mf.ABI_VERSION == 3
+    assert lib.mf_abi_version() == mf.ABI_VERSION == 4
 
 
 def test_options_default_and_struct_layout():
     o = mf.default_options()
     assert o.struct_size == ctypes.sizeof(mf.Options)
-    assert (o.n_bands, o.n_iter, o.albedo, o.cov, o.refine_steps) == (74, 30, 1, 0, 1)
+    assert (o.n_bands, o.n_iter, o.albedo, o.cov, o.refine_steps) == (74, 30, 1, 0, -1)
     assert (o.chunk_lines, o.group, o.save_for_backward, o.track_energy) == (0, 1, 0, 0)
     assert o.lambda_ == 1.0 and o.epsilon == 1e-9
 
@@ -58,6 +58,7 @@ def _create(**kw):
     ("cov", 7, mf.MF_E_ARG),
     ("cov", -1, mf.MF_E_ARG),
     ("refine_steps", 9, mf.MF_E_ARG),
+    ("refine_steps", -2, mf.MF_E_ARG),
     ("chunk_lines", 100, mf.MF_E_ARG),
     ("save_for_backward", 2, mf.MF_E_ARG),
     ("group", 0, mf.MF_E_ARG),

@@ -40,22 +40,18 @@ def test_band_counts_match_oracle(B, cov):
 
 
 @pytest.mark.parametrize("cov", ["fp32", "bf16"])
-@pytest.mark.parametrize("B", [9, 31, 63, 78])
-def test_band_counts_rounded_gram_forms_run(B, cov):
-    """The rounded Gram forms at other band counts: same statuses, finite
-    non-negative alpha, and the oracle's sparsity pattern on most pixels."""
+@pytest.mark.parametrize("B", BANDS)
+def test_band_counts_rounded_gram_forms(B, cov):
+    """The rounded Gram forms at every register layout: refined against the
+    exact C^k, they meet the same FP32 bar."""
     sc = _scene(B)
     L = torch.from_numpy(sc.radiance).to(DEV)
     s = torch.from_numpy(sc.s).to(DEV)
     a, st = mf.retrieve(L, s, n_iter=10, lam=2.0, cov=cov, chunk_lines=256)
     torch.cuda.synchronize()
-    a = a.cpu().numpy()
     ref, rst = oracle_retrieve(sc.radiance, sc.s, 10, 2.0)
     np.testing.assert_array_equal(st.cpu().numpy(), rst)
-    assert np.all(np.isfinite(a)) and np.all(a >= 0)
-    agree = float(((a > 0) == (ref > 0)).mean())
-    print(f"B={B} cov={cov}: pattern agreement {agree:.4f}", flush=True)
-    assert agree >= 0.97
+    assert_fp32_parity(a.cpu().numpy(), ref, label=f"B={B} cov={cov}")
 
 
 @pytest.mark.parametrize("B", [9, 31, 64, 78])

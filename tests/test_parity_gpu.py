@@ -31,9 +31,12 @@ def tiny():
 
 
 EXACT = ["lowrank", "fp64"]    # forms whose covariance is accumulated exactly
+# every form: the rounded Gram forms (FP32 and BF16 MFMA) refine against the
+# exact C^k and are held to the same FP32 bar
+FORMS = EXACT + ["fp32", "bf16"]
 
 
-@pytest.mark.parametrize("cov", EXACT)
+@pytest.mark.parametrize("cov", FORMS)
 @pytest.mark.parametrize("chunk", [0, 128])
 def test_tiny_scene(tiny, chunk, cov):
     lam = config_lambda("tiny")
@@ -47,8 +50,8 @@ def test_tiny_scene(tiny, chunk, cov):
 @pytest.mark.parametrize("cov", EXACT)
 @pytest.mark.parametrize("refine", [0, 2])
 def test_refinement_step_counts(tiny, refine, cov):
-    """No refinement step and two steps of C^-1 t (the default is one): the
-    solves stay within the FP32 tolerance of the exact oracle."""
+    """No refinement step and two steps of C^-1 t (the exact forms' default is
+    one): the solves stay within the FP32 tolerance of the exact oracle."""
     lam = config_lambda("tiny")
     a, st = _gpu(tiny, n_iter=30, lam=lam, cov=cov, refine_steps=refine)
     ref, rst = oracle_retrieve(tiny.radiance, tiny.s, 30, lam, workers=8)
@@ -56,7 +59,7 @@ def test_refinement_step_counts(tiny, refine, cov):
     assert_fp32_parity(a, ref, label=f"tiny refine={refine} cov={cov}")
 
 
-@pytest.mark.parametrize("cov", EXACT)
+@pytest.mark.parametrize("cov", FORMS)
 @pytest.mark.parametrize("albedo", [True, False])
 def test_zero_iterations_is_the_unclamped_filter(tiny, albedo, cov):
     a, st = _gpu(tiny, n_iter=0, lam=1.0, albedo=albedo, cov=cov)
@@ -65,7 +68,7 @@ def test_zero_iterations_is_the_unclamped_filter(tiny, albedo, cov):
     assert_fp32_parity(a, ref, iterative=False, label=f"K=0 albedo={albedo}")
 
 
-@pytest.mark.parametrize("cov", EXACT)
+@pytest.mark.parametrize("cov", FORMS)
 @pytest.mark.parametrize("lam,albedo,K", [(0.0, True, 5), (0.0, False, 5), (1.0, False, 12)])
 def test_variants(tiny, lam, albedo, K, cov):
     sub = make_scene(tiny_spec())
@@ -75,7 +78,7 @@ def test_variants(tiny, lam, albedo, K, cov):
     assert_fp32_parity(a, ref, label=f"lam={lam} albedo={albedo} K={K}")
 
 
-@pytest.mark.parametrize("cov", EXACT)
+@pytest.mark.parametrize("cov", FORMS)
 def test_ragged_lengths_and_many_items(cov):
     spec = SceneSpec(6, 1000, 74, 2, (500.0, 5000.0), (3.0, 30.0), seed=5)
     sc = make_scene(spec)
@@ -86,7 +89,7 @@ def test_ragged_lengths_and_many_items(cov):
         assert_fp32_parity(a, ref, label=f"ragged chunk={chunk}")
 
 
-@pytest.mark.parametrize("cov", EXACT)
+@pytest.mark.parametrize("cov", FORMS)
 def test_masks_skip_invalid_pixels(cov):
     spec = SceneSpec(8, 1500, 74, 3, (500.0, 5000.0), (3.0, 30.0), seed=9, mask_max_frac=0.2)
     sc = make_scene(spec)
@@ -98,7 +101,7 @@ def test_masks_skip_invalid_pixels(cov):
     assert_fp32_parity(a, ref, label="masked")
 
 
-@pytest.mark.parametrize("cov", EXACT + ["fp32"])
+@pytest.mark.parametrize("cov", FORMS)
 def test_degenerate_columns_get_status_and_zero(cov):
     spec = SceneSpec(4, 600, 74, 1, (500.0, 5000.0), (3.0, 30.0), seed=11, mask_max_frac=0.0)
     sc = make_scene(spec)
@@ -114,24 +117,27 @@ def test_degenerate_columns_get_status_and_zero(cov):
                         mf.MF_COL_FEW_PIXELS]
     np.testing.assert_array_equal(st, rst)
     assert np.all(a[[0, 1, 3]] == 0)
-    if cov in EXACT:
-        assert_fp32_parity(a[2:3], ref[2:3], label="degenerate, healthy column")
+    assert_fp32_parity(a[2:3], ref[2:3], label=f"degenerate, healthy column, cov={cov}")
 
 
-@pytest.mark.parametrize("cov,pattern_min,rmse_max", [("fp32", 0.999, 1.0), ("bf16", 0.99, 50.0)])
-def test_rounded_gram_forms_report_error(tiny, cov, pattern_min, rmse_max):
-    """The FP32- and BF16-MFMA Gram forms round the covariance; their error
-    against FP64 is reported and bounded loosely (it is not the FP32 bar)."""
+@pytest.mark.parametrize("cov", ["fp32", "bf16"])
+def test_rounded_forms_refinement_converges(tiny, cov):
+    """The rounded Gram forms refine against the exact C^k: the error against
+    the oracle after one step is larger than after the form's default steps,
+    which meet the FP32 bar (the step counts are the ones whose contraction,
+    about 1e-3 per step for the FP32 Gram and 2e-2 for BF16, reaches FP64
+    rounding)."""
     lam = config_lambda("tiny")
-    a, st = _gpu(tiny, n_iter=30, lam=lam, cov=cov)
     ref, _ = oracle_retrieve(tiny.radiance, tiny.s, 30, lam, workers=8)
-    rep = compare(a, ref)
-    print(f"{cov} Gram vs FP64:", rep, flush=True)
-    assert rep["pattern_agreement"] >= pattern_min
-    assert rep["rmse"] < rmse_max
+    a1, _ = _gpu(tiny, n_iter=30, lam=lam, cov=cov, refine_steps=1)
+    ad, _ = _gpu(tiny, n_iter=30, lam=lam, cov=cov)
+    r1, rd = compare(a1, ref), compare(ad, ref)
+    print(f"{cov}: one refinement step {r1}; default steps {rd}", flush=True)
+    assert rd["max_abs_err"] <= r1["max_abs_err"]
+    assert_fp32_parity(ad, ref, label=f"tiny cov={cov} default refinement")
 
 
-@pytest.mark.parametrize("cov", ["lowrank", "fp32"])
+@pytest.mark.parametrize("cov", FORMS)
 def test_deterministic_and_column_independent(tiny, cov):
     lam = config_lambda("tiny")
     a1, _ = _gpu(tiny, n_iter=30, lam=lam, cov=cov)
@@ -161,7 +167,7 @@ def flightline_sample(flightline):
     return cols, ref
 
 
-@pytest.mark.parametrize("cov", EXACT)
+@pytest.mark.parametrize("cov", FORMS)
 def test_full_flightline_sampled_columns(flightline, flightline_sample, cov):
     """598 x 8000 x 74, 30 iterations, the benchmark's launch configuration;
     columns through plumes and random columns are recomputed by the oracle."""
@@ -171,22 +177,7 @@ def test_full_flightline_sampled_columns(flightline, flightline_sample, cov):
     assert_fp32_parity(a[cols], ref, label=f"flightline cov={cov} cols {cols}")
 
 
-@pytest.mark.parametrize("cov,pattern_min,rmse_max", [("fp32", 0.9999, 1.0), ("bf16", 0.999, 50.0)])
-def test_full_flightline_rounded_forms(flightline, flightline_sample, cov, pattern_min, rmse_max):
-    """The FP32 and BF16 Gram forms at the benchmark's size and launch
-    configuration: error against the oracle on the sampled columns, bounded
-    loosely (rounded covariance; not the FP32 bar)."""
-    a, st = _gpu(flightline, n_iter=30, lam=config_lambda("flightline"), cov=cov)
-    assert np.all(st == 0)
-    cols, ref = flightline_sample
-    rep = compare(a[cols], ref)
-    print(f"flightline {cov} Gram vs FP64, cols {cols}:", rep, flush=True)
-    assert np.all(a >= 0)
-    assert rep["pattern_agreement"] >= pattern_min
-    assert rep["rmse"] < rmse_max
-
-
-@pytest.mark.parametrize("cov", EXACT)
+@pytest.mark.parametrize("cov", FORMS)
 @pytest.mark.parametrize("offset", [0, 1, 2])
 def test_odd_lines_and_unaligned_radiance(cov, offset):
     """Odd line counts put every other column on an 8-byte (not 16-byte)
@@ -207,7 +198,7 @@ def test_odd_lines_and_unaligned_radiance(cov, offset):
         assert_fp32_parity(a.cpu().numpy(), ref, label=f"odd lines offset={offset} chunk={chunk}")
 
 
-@pytest.mark.parametrize("cov", EXACT)
+@pytest.mark.parametrize("cov", FORMS)
 def test_detector_grouping(cov):
     """Partitions of g = 5 adjacent columns (the last takes the remaining 3)
     share one mean and covariance (Sec. II-E); masked pixels included."""

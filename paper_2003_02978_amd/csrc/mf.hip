@@ -3304,7 +3304,7 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
   ca.s = s;
   ca.partial_stride = pstride;
   ca.B = B;
-  ca.refine = p->opt.refine_steps;
+  ca.refine = refine_steps_of(p->opt);
   ca.albedo = p->opt.albedo;
   const size_t lds = bwd_lds_bytes(B), ldsA = bwdA_lds_bytes(B);
   for (int k = K; k >= 0; --k) {

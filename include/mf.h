@@ -176,6 +176,26 @@ MF_API mf_status mf_retrieve(mf_plan plan, const float* radiance, const uint8_t*
                       const float* s, float* alpha, int32_t* column_status,
                       void* workspace, void* stream);
 
+/* mf_retrieve without a workspace argument, for callers that cannot
+   allocate device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc): the workspace is a fixed device array of
+   MF_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+   until the process ends, so this call allocates nothing.  Arguments,
+   outputs and errors as mf_retrieve, plus:
+     MF_E_UNSUPPORTED  mf_workspace_bytes(plan) > MF_NOALLOC_SCRATCH_BYTES
+                       (e.g. up to about 1.2 M pixels of 74 bands at K = 30 in
+                       the low-rank form), or a plan with save_for_backward
+                       or track_energy (their state would live in the scratch)
+     MF_E_STATE        kernel timing is on for the plan
+   Every call on one GPU shares that GPU's scratch and leaves its contents
+   there: calls that may overlap on one GPU (different streams, or threads)
+   race and must be ordered by the caller.  Plain launches (no graph replay).
+   The plan itself is created beforehand (mf_plan_create allocates its tables). */
+#define MF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+MF_API mf_status mf_retrieve_noalloc(mf_plan plan, const float* radiance, const uint8_t* valid,
+                                     const float* s, float* alpha, int32_t* column_status,
+                                     void* stream);
+
 /* Adjoint of mf_retrieve (reverse mode through the K unrolled iterations of
    Fig. 1): given grad_alpha = dJ/dalpha^K for a scalar loss J (e.g.
    J = sum (alpha^K - alpha_true)^2 gives 2 (alpha^K - alpha_true)), writes

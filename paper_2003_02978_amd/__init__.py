@@ -23,7 +23,8 @@ EXPORTS = ("mf_abi_version", "mf_options_default", "mf_status_str", "mf_last_err
            "mf_plan_create", "mf_workspace_bytes", "mf_plan_columns", "mf_plan_pixels",
            "mf_retrieve", "mf_backward", "mf_plan_set_graph", "mf_plan_set_timing",
            "mf_plan_kernel_times", "mf_plan_energy", "mf_repack_bil", "mf_stream_read",
-           "mf_plan_destroy")
+           "mf_retrieve_noalloc", "mf_plan_destroy")
+NOALLOC_SCRATCH_BYTES = 64 << 20   # MF_NOALLOC_SCRATCH_BYTES
 KERNEL_KINDS = ("pass_gram", "pass_vec", "pass_last", "solve", "other")
 ABI_VERSION = 4          # MF_ABI_VERSION of include/mf.h (mf_options layout)
 
@@ -76,6 +77,8 @@ def load_library(path: str = LIB_PATH):
     lib.mf_plan_pixels.argtypes = [vp]
     lib.mf_retrieve.restype = ctypes.c_int
     lib.mf_retrieve.argtypes = [vp] * 8
+    lib.mf_retrieve_noalloc.restype = ctypes.c_int
+    lib.mf_retrieve_noalloc.argtypes = [vp] * 7
     lib.mf_plan_destroy.argtypes = [vp]
     lib.mf_backward.restype = ctypes.c_int
     lib.mf_backward.argtypes = [vp] * 9
@@ -191,6 +194,24 @@ class Plan:
                  stream=None):
         """Enqueue one retrieval; tensors are CUDA tensors (contiguous)."""
         import torch
+        self._check_io(radiance, s, alpha, valid, column_status)
+        if workspace is None:
+            workspace = self.alloc_workspace(radiance.device)
+        ws = workspace.data_ptr()
+        ws_al = (ws + 255) & ~255
+        if ws_al + self.workspace_bytes > ws + workspace.numel() * workspace.element_size():
+            raise ValueError("workspace too small (allocate workspace_bytes + 256)")
+        if stream is None:
+            stream = torch.cuda.current_stream(radiance.device)
+        _check(self._lib.mf_retrieve(
+            self._h, radiance.data_ptr(), None if valid is None else valid.data_ptr(),
+            s.data_ptr(), alpha.data_ptr(),
+            None if column_status is None else column_status.data_ptr(), ws_al,
+            stream.cuda_stream))
+        return alpha
+
+    def _check_io(self, radiance, s, alpha, valid, column_status):
+        import torch
         B = self.n_bands
         _need(radiance, torch.float32, "radiance")
         _need(s, torch.float32, "s")
@@ -205,19 +226,18 @@ class Plan:
             _need(column_status, torch.int32, "column_status")
             if column_status.numel() < self.n_columns:
                 raise ValueError("column_status is smaller than the number of columns")
-        if workspace is None:
-            workspace = self.alloc_workspace(radiance.device)
-        ws = workspace.data_ptr()
-        ws_al = (ws + 255) & ~255
-        if ws_al + self.workspace_bytes > ws + workspace.numel() * workspace.element_size():
-            raise ValueError("workspace too small (allocate workspace_bytes + 256)")
+
+    def retrieve_noalloc(self, radiance, s, alpha, valid=None, column_status=None, stream=None):
+        """mf_retrieve_noalloc: the same retrieval on the library's fixed device
+        scratch (no workspace; plans up to NOALLOC_SCRATCH_BYTES of workspace)."""
+        import torch
+        self._check_io(radiance, s, alpha, valid, column_status)
         if stream is None:
             stream = torch.cuda.current_stream(radiance.device)
-        _check(self._lib.mf_retrieve(
+        _check(self._lib.mf_retrieve_noalloc(
             self._h, radiance.data_ptr(), None if valid is None else valid.data_ptr(),
             s.data_ptr(), alpha.data_ptr(),
-            None if column_status is None else column_status.data_ptr(), ws_al,
-            stream.cuda_stream))
+            None if column_status is None else column_status.data_ptr(), stream.cuda_stream))
         return alpha
 
 

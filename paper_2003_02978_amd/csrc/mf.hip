@@ -34,6 +34,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -2749,9 +2750,41 @@ __global__ void status_kernel(const ColState* __restrict__ state, int32_t* __res
 }
 
 // ---------------------------------------------------------------------------
+// Device scratch of mf_retrieve_noalloc: the workspace of plans small enough
+// to need no caller memory.  Every GPU the library runs on holds its own copy
+// for the life of the process; in host code `scratch` is only a symbol
+// handle, so kernels receive the per-device address from hipGetSymbolAddress.
+constexpr size_t kScratchBytes = MF_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// ---------------------------------------------------------------------------
 // Host side
 
 thread_local std::string g_last_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (looked up once per
+// device, at plan creation); null and a message if the lookup fails.
+void* scratch_address(int device, std::string& err) {
+  if (device < 0 || device >= kMaxDevices) {
+    err = "device index beyond the scratch table";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
 
 mf_status fail_with(mf_status s, const std::string& msg) {
   g_last_error = msg;
@@ -2795,6 +2828,7 @@ struct mf_plan_s {
          off_bw_col = 0;
   size_t off_energy = 0;     // track_energy: E^k per partition [K+1][n_cols]
   size_t ws_bytes = 0;
+  void* scratch_d = nullptr; // this device's `scratch` (mf_retrieve_noalloc)
 };
 
 namespace {
@@ -3153,6 +3187,16 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
     delete p;
     return fail_with(MF_E_DEVICE, "plan tables: " + e);
   }
+  {
+    std::string err;
+    p->scratch_d = scratch_address(p->device, err);
+    if (!p->scratch_d) {
+      (void)hipFree(p->cols_d);
+      (void)hipFree(p->items_d);
+      delete p;
+      return fail_with(MF_E_DEVICE, err);
+    }
+  }
   size_t off = 0;
   p->off_state = off;
   off = align256(off + (size_t)p->n_cols * sizeof(ColState));
@@ -3238,6 +3282,30 @@ mf_status mf_retrieve(mf_plan p, const float* radiance, const uint8_t* valid, co
     return MF_OK;
   }
   enqueue_retrieve(p, radiance, valid, s, alpha, column_status, workspace, st);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail_with(MF_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+  return MF_OK;
+}
+
+mf_status mf_retrieve_noalloc(mf_plan p, const float* radiance, const uint8_t* valid, const float* s,
+                              float* alpha, int32_t* column_status, void* stream) {
+  if (!p) return fail_with(MF_E_ARG, "plan is NULL");
+  if (!radiance || !s || !alpha) return fail_with(MF_E_ARG, "radiance, s and alpha must be non-NULL");
+  if (p->ws_bytes > kScratchBytes)
+    return fail_with(MF_E_UNSUPPORTED, "the plan needs " + std::to_string(p->ws_bytes) +
+                                           " bytes of workspace; mf_retrieve_noalloc has " +
+                                           std::to_string(kScratchBytes));
+  if (p->opt.save_for_backward || p->opt.track_energy)
+    return fail_with(MF_E_UNSUPPORTED,
+                     "mf_retrieve_noalloc keeps no state for mf_backward or mf_plan_energy");
+  if (p->timing) return fail_with(MF_E_STATE, "kernel timing is on (it records events)");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail_with(MF_E_DEVICE, "current device differs from the plan's device");
+  if (!p->scratch_d) return fail_with(MF_E_STATE, "no scratch address for the plan's device");
+  (void)hipGetLastError();
+  // plain launches (no graph: instantiating one allocates), on the scratch
+  enqueue_retrieve(p, radiance, valid, s, alpha, column_status, p->scratch_d, (hipStream_t)stream);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail_with(MF_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
   return MF_OK;

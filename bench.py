@@ -26,15 +26,79 @@ HBM_PEAK_GBS = 8000.0
 # FP64, FP32 or BF16 MFMA (the radiance input is FP32 throughout)
 FORM_DTYPE = {"lowrank": "f64", "fp64": "f64", "fp32": "f32 Gram, f64 scores and solves",
               "bf16": "bf16 Gram (f32 accumulate), f64 scores and solves"}
-# Algorithmic bytes per pixel of one launch of each form's dominant kernel.
-# Low-rank streaming passes 1..K: the 74-band FP32 spectrum, alpha^{j-1}
-# written (FP64 working copy), and from pass 2 on alpha^{j-2} and r read;
-# pass 1 writes r instead (312 B), passes 2..K move 320 B.  Gram passes of
-# the other forms: spectrum + alpha^{j-2} read + alpha^{j-1} written.
-def pass_bytes_per_px(form, K, B=74):
-    if form == "lowrank":
-        return (B * 4 + 16 + (K - 1) * (B * 4 + 24)) / K
-    return B * 4 + 16
+FORM_LABEL = {"lowrank": "exact rank-3 covariance update (C^0 from one FP64 Gram; the low-rank variant)",
+              "fp64": "per-iteration Gram on FP64 MFMA",
+              "fp32": "plain FP32 form: per-iteration Gram on FP32 MFMA, FP64 Cholesky, refinement "
+                      "against the exact C^k",
+              "bf16": "precision form: per-iteration Gram on BF16 MFMA (FP32 accumulate), FP64 "
+                      "Cholesky, refinement against the exact C^k"}
+# Algorithmic bytes per pixel of the method: every pass reads the B-band FP32
+# spectrum once; alpha moves as FP32, written by pass 1 (alpha^0) and read and
+# written by every later scored pass (alpha^{j-2} in, alpha^{j-1} out).  The
+# dominant kernel of each form is its scored pass 1..K: 300 B/px for pass 1,
+# 304 B/px for passes 2..K at 74 bands.  The whole job is K + 2 passes over
+# the spectrum plus the alpha traffic: (K + 2) B 4 + 4 + 8 K = 9716 B/px.
+def pass_bytes_per_px(K, B=74):
+    return (B * 4 + 4 + (K - 1) * (B * 4 + 8)) / K
+
+
+def job_bytes_per_px(K, B=74):
+    return (K + 2) * B * 4 + 4 + 8 * K
+
+
+# Algorithmic flops per pixel of one Gram pass: the B(B+1)/2 distinct products
+# of the symmetric B x B Gram, two flops each; the MFMA tiles execute
+# 16 x 16 x 2 flops per tile for the lower triangle of ceil((B + 2) / 16)
+# blocks (15 tiles, 7680 flops at 74 bands).
+def gram_flops_per_px(B=74):
+    return B * (B + 1)
+
+
+def gram_tile_flops_per_px(B=74):
+    nb = (B + 2 + 15) // 16
+    return nb * (nb + 1) // 2 * 16 * 16 * 2
+
+
+# MI355X peaks: HBM 8 TB/s; dense MFMA FP32 157.3 TFLOP/s, BF16 2.5 PFLOP/s,
+# FP64 78.6 TFLOP/s
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+
+
+def compare(gpu, ref, iterative=True):
+    """Error report of a result against the FP64 oracle: FP32 tolerance
+    |d alpha| <= 1e-4 |alpha| + 0.1 ppm*m on pixels whose zero/nonzero pattern
+    agrees, the agreement over all pixels, and the flipped pixels counted
+    against the oracle's nonzero pixels."""
+    import numpy as np
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    agree = (gpu > 0) == (ref > 0) if iterative else np.ones(gpu.shape, dtype=bool)
+    both = agree & ((ref != 0) | (gpu != 0))
+    err = np.abs(gpu - ref)
+    tol = 1e-4 * np.abs(ref) + 0.1
+    ratio = np.where(both, err / tol, 0.0)
+    nz = int((ref > 0).sum())
+    flips = int((~agree).sum())
+    return {"pixels": int(gpu.size), "pattern_agreement": float(agree.mean()),
+            "pattern_flips": flips, "nonzero_ref": nz,
+            "flips_over_nonzero": float(flips / nz) if nz else 0.0,
+            "max_abs_err": float(err.max()) if err.size else 0.0,
+            "rmse": float(np.sqrt((err ** 2).mean())) if err.size else 0.0,
+            "max_err_over_tol": float(ratio.max()) if ratio.size else 0.0,
+            "tol_violations": int((ratio > 1.0).sum())}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 SOURCE = os.path.join(ROOT, "paper_2003_02978_amd", "csrc", "mf.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -52,7 +116,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--forms", default="lowrank,fp64,fp32,bf16")
+    ap.add_argument("--forms", default="lowrank,fp64,fp32,bf16,bf16@1",
+                    help="covariance forms; form@n runs it with n refinement steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-lines", type=int, default=8000)
     ap.add_argument("--save-alpha", default="", help="save each form's alpha as <path>_<form>.npy")
@@ -120,8 +185,10 @@ def main():
     head = forms[0]
     results = {}
     outputs = {}
-    for form in forms:
-        plan = mf.Plan([(0, S, N)], B, K, lam, eps, True, form)
+    for label in forms:
+        form, _, rs = label.partition("@")
+        refine = int(rs) if rs else -1
+        plan = mf.Plan([(0, S, N)], B, K, lam, eps, True, form, refine_steps=refine)
         ws = plan.alloc_workspace(dev)
         for _ in range(args.warmup):
             plan.retrieve(L, s, alpha, None, status, ws)
@@ -144,9 +211,9 @@ def main():
         dt_ins = time.perf_counter() - t2
         kt = plan.kernel_times()
         plan.set_timing(False)
-        outputs[form] = alpha.cpu().numpy().copy()
+        outputs[label] = alpha.cpu().numpy().copy()
         if args.save_alpha:
-            np.save(f"{args.save_alpha}_{form}.npy", outputs[form])
+            np.save(f"{args.save_alpha}_{label}.npy", outputs[label])
         st = status.cpu().numpy()
         res = {
             "px_per_s": n_px * steps / dt,
@@ -157,15 +224,21 @@ def main():
             "kernels_ms_per_step": {k: round(v[0] / steps, 4) for k, v in kt.items()},
             "launches_per_step": {k: v[1] // steps for k, v in kt.items()},
         }
-        # the dominant streaming pass of this form
+        # the dominant kernel of this form: its scored passes 1..K
         dom = "pass_vec" if form == "lowrank" else "pass_gram"
         avg_ms = kt[dom][0] / max(1, kt[dom][1])
+        res["form"] = form
+        res["refine_steps"] = plan.refine_steps
         res["dominant_kernel"] = dom
         res["dominant_avg_ms"] = avg_ms
-        res["dominant_bytes_per_px"] = pass_bytes_per_px(form, K, B)
+        res["dominant_bytes_per_px"] = pass_bytes_per_px(K, B)
         res["dominant_GBps"] = res["dominant_bytes_per_px"] * n_px / (avg_ms * 1e-3) / 1e9
-        results[form] = res
-        log(f"{form}: {res['px_per_s'] / 1e6:.1f} Mpx/s, {res['ms_per_step']:.3f} ms/step, "
+        if form != "lowrank":
+            res["gram_TFLOPs_algorithmic"] = gram_flops_per_px(B) * n_px / (avg_ms * 1e-3) / 1e12
+            res["gram_TFLOPs_tiles"] = gram_tile_flops_per_px(B) * n_px / (avg_ms * 1e-3) / 1e12
+            res["gram_frac_of_mfma_peak_tiles"] = res["gram_TFLOPs_tiles"] / PEAK_TFLOPS[form]
+        results[label] = res
+        log(f"{label}: {res['px_per_s'] / 1e6:.1f} Mpx/s, {res['ms_per_step']:.3f} ms/step, "
             f"{dom} {avg_ms * 1e3:.1f} us = {res['dominant_GBps']:.0f} GB/s, kernels {res['kernels_ms_per_step']}")
         plan.close()
         del ws
@@ -263,18 +336,31 @@ def main():
     errors = {}
     if not args.no_cpu_baseline:
         from oracle.mf64 import host_cores, retrieve as oracle_retrieve
-        from tests.parity_util import compare
-        cores = min(16, host_cores())
+        from synth.scenes import tiny_spec
+        # every core of the process's affinity set, at most the 16 CPUs a GPU
+        # box allots to one GPU
+        affinity = host_cores()
+        cores = min(16, affinity)
         n_cols = S if cores >= 8 else min(S, 16 * cores)
         cols = list(range(n_cols))
         t3 = time.perf_counter()
         ref, rst = oracle_retrieve(sc.radiance, sc.s, K, lam, eps, columns=cols, workers=cores)
         dtc = time.perf_counter() - t3
+        # single core on the tiny scene (64 x 512 x 74, its own lambda)
+        tcfg = json.load(open(os.path.join(ROOT, "configs", "tiny.json")))
+        tsc = make_scene(tiny_spec())
+        t7 = time.perf_counter()
+        oracle_retrieve(tsc.radiance, tsc.s, K, tcfg["lambda"], eps, workers=1)
+        dt1 = time.perf_counter() - t7
         cpu = {"value": n_cols * N / dtc, "unit": "px/s", "cores": cores, "kind": "oracle",
                "sample": f"{n_cols} of {S} columns x {N} lines x {B} bands, 30 iterations, "
                          f"FP64 numpy/LAPACK, one process per core",
-               "seconds": round(dtc, 2)}
-        log(f"oracle: {cpu['value']:.0f} px/s on {cores} cores ({dtc:.1f}s)")
+               "seconds": round(dtc, 2), "cores_in_affinity": affinity, "cpu_model": cpu_model(),
+               "single_core_tiny": {"workload": "tiny scene 64x512x74, 30 iterations",
+                                    "seconds": round(dt1, 3),
+                                    "px_per_s": round(tsc.radiance.shape[0] * tsc.radiance.shape[1] / dt1, 1)}}
+        log(f"oracle: {cpu['value']:.0f} px/s on {cores} cores ({dtc:.1f}s), {cpu['cpu_model']}; "
+            f"tiny scene on one core {dt1:.2f}s")
         for form, a in outputs.items():
             rep = compare(a[:n_cols], ref)
             errors[form] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in rep.items()}
@@ -299,7 +385,7 @@ def main():
         "measured_read_ceiling_GBps": round(ceiling_GBps, 1),
         "frac_of_measured_ceiling": round(hr["dominant_GBps"] / ceiling_GBps, 4),
     }
-    whole_job_GBps = (K + 2) * 74 * 4 * n_px / (hr["ms_per_step"] * 1e-3) / 1e9
+    whole_job_GBps = job_bytes_per_px(K, B) * n_px / (hr["ms_per_step"] * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": round(hr["px_per_s"], 1),
@@ -317,16 +403,28 @@ def main():
                                f"covariance form '{head}'",
                    "columns": S, "lines": N, "bands": B, "iterations": K,
                    "covariance": head, "radiance": "f32", "parallelism": "single GPU"},
+        "headline_form": FORM_LABEL.get(results[head]["form"], head),
         "roofline": roof,
         "cpu_baseline": cpu,
         "hbm_fraction_whole_job": round(whole_job_GBps / HBM_PEAK_GBS, 4),
-        "forms": {f: {"dtype": FORM_DTYPE[f],
+        "forms": {f: {"dtype": FORM_DTYPE[r["form"]], "label": FORM_LABEL[r["form"]],
+                      "refine_steps": r["refine_steps"],
                       "px_per_s": round(r["px_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                      "hbm_fraction_whole_job": round(job_bytes_per_px(K, B) * n_px /
+                                                      (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                       "kernels_ms_per_step": r["kernels_ms_per_step"],
                       "dominant_kernel": r["dominant_kernel"],
+                      "dominant_avg_us": round(1e3 * r["dominant_avg_ms"], 2),
                       "dominant_GBps": round(r["dominant_GBps"], 1),
+                      **({"gram_TFLOPs_algorithmic": round(r["gram_TFLOPs_algorithmic"], 2),
+                          "gram_TFLOPs_tiles": round(r["gram_TFLOPs_tiles"], 2),
+                          "gram_frac_of_mfma_peak_tiles": round(r["gram_frac_of_mfma_peak_tiles"], 4)}
+                         if "gram_TFLOPs_tiles" in r else {}),
                       "error_vs_fp64": errors.get(f)} for f, r in results.items()},
     }
+    for f in ("fp32", "bf16"):
+        if f in results:
+            out[f"{f}_px_per_s"] = round(results[f]["px_per_s"], 1)
     out["grouped"] = grouped
     out["energy"] = energy
     out["ingest"] = ingest
@@ -495,7 +593,6 @@ def run_batch(mf, torch, np, dev, K, lam, eps, steps, warmup):
     against the oracle."""
     from synth.scenes import batch_specs, make_scene, make_globals, make_column
     from oracle.mf64 import retrieve as oracle_retrieve
-    from tests.parity_util import compare
     specs = batch_specs()
     B = specs[0].n_bands
     fls, first = [], 0

@@ -157,6 +157,10 @@ MF_API size_t mf_workspace_bytes(mf_plan plan);
 MF_API int64_t mf_plan_columns(mf_plan plan);
 MF_API int64_t mf_plan_pixels(mf_plan plan);
 
+/* Refinement steps the plan's solves take (refine_steps, or the form's
+   default when it was -1); -1 for a NULL plan. */
+MF_API int32_t mf_plan_refine_steps(mf_plan plan);
+
 /* Runs Fig. 1 on every column of the plan.
      radiance       [max_px][B] float32, uW cm^-2 sr^-1 nm^-1 (read only); any
                     float-aligned pointer (16-byte alignment is not required)
@@ -234,12 +238,13 @@ MF_API mf_status mf_plan_set_graph(mf_plan plan, int enable);
    its kernel launches with HIP events on the caller's stream (a few
    microseconds of extra stream work per launch). */
 enum {
-  MF_KERNEL_PASS_GRAM = 0,  /* streaming pass that also accumulates a Gram */
+  MF_KERNEL_PASS_GRAM = 0,  /* scored pass (1..K) that also accumulates a Gram */
   MF_KERNEL_PASS_VEC = 1,   /* streaming pass of the low-rank form (vector moments) */
   MF_KERNEL_PASS_LAST = 2,  /* final streaming pass (alpha^K only) */
   MF_KERNEL_SOLVE = 3,      /* per-column FP64 combine, Cholesky and solve */
   MF_KERNEL_OTHER = 4,      /* setup and status copy */
-  MF_KERNEL_KINDS = 5
+  MF_KERNEL_PASS_INIT = 5,  /* pass 0: the FP64 Gram of C^0 (every form) */
+  MF_KERNEL_KINDS = 6
 };
 MF_API mf_status mf_plan_set_timing(mf_plan plan, int enable);
 

@@ -23,9 +23,9 @@ EXPORTS = ("mf_abi_version", "mf_options_default", "mf_status_str", "mf_last_err
            "mf_plan_create", "mf_workspace_bytes", "mf_plan_columns", "mf_plan_pixels",
            "mf_retrieve", "mf_backward", "mf_plan_set_graph", "mf_plan_set_timing",
            "mf_plan_kernel_times", "mf_plan_energy", "mf_repack_bil", "mf_stream_read",
-           "mf_retrieve_noalloc", "mf_plan_destroy")
+           "mf_retrieve_noalloc", "mf_plan_refine_steps", "mf_plan_destroy")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # MF_NOALLOC_SCRATCH_BYTES
-KERNEL_KINDS = ("pass_gram", "pass_vec", "pass_last", "solve", "other")
+KERNEL_KINDS = ("pass_gram", "pass_vec", "pass_last", "solve", "other", "pass_init")
 ABI_VERSION = 4          # MF_ABI_VERSION of include/mf.h (mf_options layout)
 
 
@@ -75,6 +75,8 @@ def load_library(path: str = LIB_PATH):
     lib.mf_plan_columns.argtypes = [vp]
     lib.mf_plan_pixels.restype = i64
     lib.mf_plan_pixels.argtypes = [vp]
+    lib.mf_plan_refine_steps.restype = i32
+    lib.mf_plan_refine_steps.argtypes = [vp]
     lib.mf_retrieve.restype = ctypes.c_int
     lib.mf_retrieve.argtypes = [vp] * 8
     lib.mf_retrieve_noalloc.restype = ctypes.c_int
@@ -144,6 +146,7 @@ class Plan:
         self.workspace_bytes = int(lib.mf_workspace_bytes(h))
         self.n_columns = int(lib.mf_plan_columns(h))
         self.n_pixels = int(lib.mf_plan_pixels(h))
+        self.refine_steps = int(lib.mf_plan_refine_steps(h))
         self.max_px = max(a + b * c for a, b, c in fls)
 
     def close(self):

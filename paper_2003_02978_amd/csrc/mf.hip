@@ -1069,73 +1069,51 @@ __device__ void block_symv(const double (&M)[kBlk][kBlk], bool owner, int bi, in
   __syncthreads();
 }
 
-// Blocked solve of L L^T v = x with the Cholesky factor in the owner threads'
-// register blocks (Lb = L_ij, i >= j) and W_K = L_KK^-1 in wbuf (16 doubles
-// per block, row-major, lower).  Forward, block step K: the threads of block
-// column K form y_K = W_K x_K; (K, K) stores it, (i, K) subtracts L_iK y_K
-// from x_i.  Backward, block step I: the threads of block row I form
-// v_I = W_I^T y_I; (I, I) stores it, (I, K) subtracts L_IK^T v_I from y_K.
-// Each block of x and y has one writer per step: one barrier per step.  x is
-// overwritten, y is scratch, v receives the solution (kPad entries each, the
-// first 4 nkb used).
-__device__ void block_chol_solve(const double (&Lb)[kBlk][kBlk], bool owner, int bi, int bj, int nkb,
-                                 const double* wbuf, double* x, double* y, double* v) {
-  for (int K = 0; K < nkb; ++K) {
-    if (owner && bj == K) {
-      const double* w = wbuf + K * 16;
-      double xk[kBlk], yk[kBlk];
+// v = X^T X x = C^-1 x with the inverse Cholesky factor X = L^-1 in the
+// owner threads' register blocks (X_ij, i >= j; diagonal blocks lower
+// triangular; blocks of row blocks >= nkb unused): y = X x, then v = X^T y.
+// Each product writes one partial per (row, block) slot of q ([kPad][kNBlkRows]
+// doubles) and sums each row's slots in a fixed order (deterministic).  x must
+// be zero beyond B; y is scratch; v gets zeros beyond B.  Four barriers.
+__device__ void block_inv_solve(const double (&X)[kBlk][kBlk], bool owner, int bi, int bj, int tid,
+                                int B, int nkb, const double* x, double* y, double* v, double* q) {
+  const bool use = owner && bi < nkb;
+  if (use) {                                       // y_i += X_ij x_j into slot j of row i
 #pragma unroll
-      for (int z = 0; z < kBlk; ++z) xk[z] = x[kBlk * K + z];
+    for (int r = 0; r < kBlk; ++r) {
+      double t = 0.0;
 #pragma unroll
-      for (int r = 0; r < kBlk; ++r) {
-        double t = 0.0;
-#pragma unroll
-        for (int z = 0; z <= r; ++z) t = fma(w[r * 4 + z], xk[z], t);
-        yk[r] = t;
-      }
-      if (bi == K) {
-#pragma unroll
-        for (int r = 0; r < kBlk; ++r) y[kBlk * K + r] = yk[r];
-      } else {
-#pragma unroll
-        for (int r = 0; r < kBlk; ++r) {
-          double t = x[kBlk * bi + r];
-#pragma unroll
-          for (int z = 0; z < kBlk; ++z) t = fma(-Lb[r][z], yk[z], t);
-          x[kBlk * bi + r] = t;
-        }
-      }
+      for (int c = 0; c < kBlk; ++c) t = fma(X[r][c], x[kBlk * bj + c], t);
+      q[(kBlk * bi + r) * kNBlkRows + bj] = t;
     }
-    __syncthreads();
   }
-  for (int I = nkb - 1; I >= 0; --I) {
-    if (owner && bi == I) {
-      const double* w = wbuf + I * 16;
-      double yi[kBlk], vi[kBlk];
+  __syncthreads();
+  for (int e = tid; e < kPad; e += kBlock) {
+    const int rb = e / kBlk;
+    double t = 0.0;
+    if (e < B)
+      for (int k = 0; k <= rb; ++k) t += q[e * kNBlkRows + k];
+    y[e] = t;
+  }
+  __syncthreads();
+  if (use) {                                       // v_j += X_ij^T y_i into slot i of row j
 #pragma unroll
-      for (int z = 0; z < kBlk; ++z) yi[z] = y[kBlk * I + z];
+    for (int c = 0; c < kBlk; ++c) {
+      double t = 0.0;
 #pragma unroll
-      for (int r = 0; r < kBlk; ++r) {
-        double t = 0.0;
-#pragma unroll
-        for (int z = r; z < kBlk; ++z) t = fma(w[z * 4 + r], yi[z], t);
-        vi[r] = t;
-      }
-      if (bj == I) {
-#pragma unroll
-        for (int r = 0; r < kBlk; ++r) v[kBlk * I + r] = vi[r];
-      } else {
-#pragma unroll
-        for (int c = 0; c < kBlk; ++c) {
-          double t = y[kBlk * bj + c];
-#pragma unroll
-          for (int r = 0; r < kBlk; ++r) t = fma(-Lb[r][c], vi[r], t);
-          y[kBlk * bj + c] = t;
-        }
-      }
+      for (int r = 0; r < kBlk; ++r) t = fma(X[r][c], y[kBlk * bi + r], t);
+      q[(kBlk * bj + c) * kNBlkRows + bi] = t;
     }
-    __syncthreads();
   }
+  __syncthreads();
+  for (int e = tid; e < kPad; e += kBlock) {
+    const int cb = e / kBlk;
+    double t = 0.0;
+    if (e < B)
+      for (int k = cb; k < nkb; ++k) t += q[e * kNBlkRows + k];
+    v[e] = t;
+  }
+  __syncthreads();
 }
 
 // Cholesky factor L (lower) of a symmetric 4x4 block D (row-major, lower part
@@ -1501,17 +1479,21 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
       __syncthreads();
     }
   } else {
-  // ---- blocked right-looking Cholesky on the register blocks.  For pivot
-  // block K with D = A_KK = L_KK L_KK^T (W = L_KK^-1): the panel
-  // A_iK <- A_iK W^T = L_iK (i > K), then A_ij -= L_iK L_jK^T (i >= j > K).
-  // The owner of (K, K) factors it from its registers and publishes W; the
-  // panel threads form L_iK once and publish it; the trailing threads read
-  // it.  Two barriers per pivot block; the next pivot's factorisation uses
-  // only its owner's registers, and its barrier orders the reuse of the
-  // panel buffer.  Padding rows (>= B) are decoupled with unit diagonal.
+  // ---- blocked right-looking Cholesky on the register blocks, forming the
+  // inverse factor X = L^-1 alongside.  For pivot block K with
+  // D = A_KK = L_KK L_KK^T (W = L_KK^-1): the panel A_iK <- A_iK W^T = L_iK
+  // (i > K), then A_ij -= L_iK L_jK^T (i >= j > K).  X comes from the same
+  // steps applied to [L | I] (right-looking forward substitution): with R the
+  // right-hand side, row block K of X is X_KJ = W R_KJ (J <= K), and then
+  // R_iJ -= L_iK X_KJ (i > K >= J).  A thread's block becomes R once its L
+  // block is published (as a panel), so X uses the registers and threads
+  // that the factorisation leaves idle: two barriers per pivot block, as
+  // for the factor alone.  At the end thread (i, j) holds X_ij.  Padding
+  // rows (>= B) are decoupled with unit diagonal.
+  const int nkb = (B + kBlk - 1) / kBlk;
   {
     double* lpan = Lf;                      // [kNBlkRows][4][4]: L_iK of block column K
-    const int nkb = (B + kBlk - 1) / kBlk;
+    double* xrow = Lf + kNBlkRows * 16;     // [kNBlkRows][4][4]: X_KJ of block row K
     for (int K = 0; K < nkb; ++K) {
       if (owner && bi == K && bj == K) {
         double Lc[kBlk][kBlk], W[kBlk][kBlk];
@@ -1520,7 +1502,7 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
         for (int x = 0; x < kBlk; ++x)
 #pragma unroll
           for (int y = 0; y < kBlk; ++y) {
-            A_[x][y] = y <= x ? Lc[x][y] : 0.0;
+            A_[x][y] = y <= x ? W[x][y] : 0.0;      // X_KK = W
             wbuf[K * 16 + x * 4 + y] = y <= x ? W[x][y] : 0.0;
           }
       }
@@ -1529,38 +1511,66 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
         if (tid == 0) st.status = MF_COL_NOT_SPD;
         return;
       }
-      if (owner && bj == K && bi > K) {      // panel: L_iK = A_iK W^T (W lower)
+      if (owner && ((bj == K && bi > K) || (bi == K && bj < K))) {
         double W[kBlk][kBlk], Y[kBlk][kBlk];
 #pragma unroll
         for (int x = 0; x < kBlk; ++x)
 #pragma unroll
           for (int y = 0; y < kBlk; ++y) W[x][y] = wbuf[K * 16 + x * 4 + y];
+        if (bj == K) {
+          // panel: L_iK = A_iK W^T, published; the block becomes
+          // R_iK = -L_iK X_KK = -L_iK W
 #pragma unroll
-        for (int x = 0; x < kBlk; ++x)
+          for (int x = 0; x < kBlk; ++x)
 #pragma unroll
-          for (int y = 0; y < kBlk; ++y) {
-            double t = 0.0;
+            for (int y = 0; y < kBlk; ++y) {
+              double t = 0.0;
 #pragma unroll
-            for (int z = 0; z <= y; ++z) t = fma(A_[x][z], W[y][z], t);
-            Y[x][y] = t;
-          }
+              for (int z = 0; z <= y; ++z) t = fma(A_[x][z], W[y][z], t);
+              Y[x][y] = t;
+            }
 #pragma unroll
-        for (int x = 0; x < kBlk; ++x)
+          for (int x = 0; x < kBlk; ++x)
 #pragma unroll
-          for (int y = 0; y < kBlk; ++y) {
-            A_[x][y] = Y[x][y];
-            lpan[bi * 16 + x * 4 + y] = Y[x][y];
-          }
+            for (int y = 0; y < kBlk; ++y) {
+              lpan[bi * 16 + x * 4 + y] = Y[x][y];
+              double t = 0.0;
+#pragma unroll
+              for (int z = y; z < kBlk; ++z) t = fma(Y[x][z], W[z][y], t);
+              A_[x][y] = -t;
+            }
+        } else {
+          // row block K of X: X_KJ = W R_KJ, published
+#pragma unroll
+          for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+            for (int y = 0; y < kBlk; ++y) {
+              double t = 0.0;
+#pragma unroll
+              for (int z = 0; z <= x; ++z) t = fma(W[x][z], A_[z][y], t);
+              Y[x][y] = t;
+            }
+#pragma unroll
+          for (int x = 0; x < kBlk; ++x)
+#pragma unroll
+            for (int y = 0; y < kBlk; ++y) {
+              A_[x][y] = Y[x][y];
+              xrow[bj * 16 + x * 4 + y] = Y[x][y];
+            }
+        }
       }
       __syncthreads();
-      if (owner && bj > K) {                 // trailing, bi >= bj > K
-        double Li[kBlk][kBlk], Lj[kBlk][kBlk];
+      if (owner && bi > K && bj != K) {
+        // trailing factor update (bj > K): A_ij -= L_iK L_jK^T;
+        // right-hand side (bj < K): R_iJ -= L_iK X_KJ
+        const bool trail = bj > K;
+        double Li[kBlk][kBlk], M[kBlk][kBlk];
 #pragma unroll
         for (int x = 0; x < kBlk; ++x)
 #pragma unroll
           for (int z = 0; z < kBlk; ++z) {
             Li[x][z] = lpan[bi * 16 + x * 4 + z];
-            Lj[x][z] = lpan[bj * 16 + x * 4 + z];
+            M[x][z] = trail ? lpan[bj * 16 + x * 4 + z] : xrow[bj * 16 + x * 4 + z];
           }
 #pragma unroll
         for (int x = 0; x < kBlk; ++x)
@@ -1568,7 +1578,7 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
           for (int y = 0; y < kBlk; ++y) {
             double t = A_[x][y];
 #pragma unroll
-            for (int z = 0; z < kBlk; ++z) t = fma(-Li[x][z], Lj[y][z], t);
+            for (int z = 0; z < kBlk; ++z) t = fma(-Li[x][z], trail ? M[y][z] : M[z][y], t);
             A_[x][y] = t;
           }
       }
@@ -1600,8 +1610,7 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
   // each step contracts the error by about |I - C_f^-1 C^j| (1e-3 for the
   // FP32 Gram, 2e-2 for BF16) down to FP64 rounding.
   {
-    const int nkb = (B + kBlk - 1) / kBlk;
-    block_chol_solve(A_, owner, bi, bj, nkb, wbuf, rbuf, colk, vbuf);
+    block_inv_solve(A_, owner, bi, bj, tid, B, nkb, rbuf, colk, vbuf, qsym);
     for (int step = 0; step < a.refine; ++step) {
       if (xref && wid == 0) {
         double u[3];
@@ -1616,7 +1625,7 @@ __global__ void __launch_bounds__(kBlock, 3) solve_kernel(SolveArgs a) {
         rbuf[b] = b < B ? tn[b] - cv : 0.0;
       }
       __syncthreads();
-      block_chol_solve(A_, owner, bi, bj, nkb, wbuf, rbuf, colk, dvec);
+      block_inv_solve(A_, owner, bi, bj, tid, B, nkb, rbuf, colk, dvec, qsym);
       for (int b = tid; b < B; b += kBlock) vbuf[b] += dvec[b];
       __syncthreads();
     }
@@ -3022,7 +3031,8 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
     const bool mom = j <= K;
     const int mode = pass_mode(p->opt.cov, j, K);
     {
-      LaunchTimer tm(p, mode == PM_NONE ? MF_KERNEL_PASS_LAST
+      LaunchTimer tm(p, j == 0 ? MF_KERNEL_PASS_INIT
+                        : mode == PM_NONE ? MF_KERNEL_PASS_LAST
                         : mode == PM_VEC ? MF_KERNEL_PASS_VEC : MF_KERNEL_PASS_GRAM, st);
       dispatch_pass(p, pa, mode, st);
     }
@@ -3242,6 +3252,7 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
 size_t mf_workspace_bytes(mf_plan p) { return p ? p->ws_bytes : 0; }
 int64_t mf_plan_columns(mf_plan p) { return p ? p->n_cols : 0; }
 int64_t mf_plan_pixels(mf_plan p) { return p ? p->n_px : 0; }
+int32_t mf_plan_refine_steps(mf_plan p) { return p ? refine_steps_of(p->opt) : -1; }
 
 mf_status mf_retrieve(mf_plan p, const float* radiance, const uint8_t* valid, const float* s,
                       float* alpha, int32_t* column_status, void* workspace, void* stream) {

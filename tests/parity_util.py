@@ -31,9 +31,13 @@ def compare(gpu, ref, iterative=True):
     err = np.abs(gpu - ref)
     tol = REL_TOL * np.abs(ref) + ABS_TOL
     ratio = np.where(both, err / tol, 0.0)
+    nz = int((ref > 0).sum())
+    flips = int((~agree).sum())
     return {
         "pixels": int(gpu.size),
         "pattern_agreement": float(agree.mean()),
+        "pattern_flips": flips,
+        "flips_over_nonzero": float(flips / nz) if nz else 0.0,
         "max_abs_err": float(err.max()) if err.size else 0.0,
         "rmse": float(np.sqrt((err ** 2).mean())) if err.size else 0.0,
         "max_err_over_tol": float(ratio.max()) if ratio.size else 0.0,

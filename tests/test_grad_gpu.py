@@ -111,30 +111,182 @@ def test_adjoint_detector_grouping():
     assert _rel_err(gs, gsr) < 1e-4
 
 
-def test_adjoint_subscene_16x256_30_iterations():
-    """The differentiation workload's reference check: a 16 x 256 sub-scene of
-    the 598 x 4000 scene, 30 iterations, against torch FP64 autograd."""
-    spec = SceneSpec(598, 4000, 74, 40, (200.0, 8000.0), (3.0, 30.0), seed=1004)
-    g = make_globals(spec)
-    # the sub-scene: columns 0-15, lines 0-255 of the scene (regenerated per column)
+def _diff_workload():
+    """The differentiation workload: 598 x 4000 x 74, 30 iterations, its lambda."""
+    from synth.scenes import diff_spec
+    from tests.parity_util import config_lambda
+    return diff_spec(), config_lambda("diff")
+
+
+def _subscene(spec, g, c0, l0):
+    """Columns c0..c0+15, lines l0..l0+255 of the scene (regenerated per column),
+    as a scene of its own (each 256-line column is one partition)."""
     from synth.scenes import make_column
     Ls, As = [], []
-    for c in range(16):
+    for c in range(c0, c0 + 16):
         Lc, ac, _ = make_column(spec, g, c)
-        Ls.append(Lc[:256])
-        As.append(ac[:256])
+        Ls.append(Lc[l0:l0 + 256])
+        As.append(ac[l0:l0 + 256])
     sub = make_scene(SceneSpec(16, 256, 74, 0, seed=5))
     sub.radiance = np.stack(Ls)
     sub.alpha_true = np.stack(As)
     sub.s = g.s
-    lam = 4.0
+    return sub
+
+
+def _elementwise(g, ref, rtol=1e-4, floor_frac=1e-6):
+    """Per-element check |g - ref| <= rtol |ref| + floor, floor = floor_frac
+    max|ref|: returns (violations, largest relative error above the floor)."""
+    floor = floor_frac * max(float(np.abs(ref).max()), 1e-300)
+    err = np.abs(g - ref)
+    viol = int((err > rtol * np.abs(ref) + floor).sum())
+    above = np.abs(ref) > floor
+    rel = float((err[above] / np.abs(ref[above])).max()) if above.any() else 0.0
+    return viol, rel
+
+
+@pytest.mark.parametrize("window", ["first_columns", "through_plume"])
+def test_adjoint_subscene_16x256_30_iterations(window):
+    """The differentiation workload's reference check at its own lambda: a
+    16 x 256 sub-scene of the 598 x 4000 scene, 30 iterations, against torch
+    FP64 autograd, element by element.  Columns 0-15 x lines 0-255 hold no
+    plume: every alpha is locked at 0 and both gradients are exactly zero.
+    The second window, columns 160-175 x lines 2384-2639, is centred on plume
+    4 of the scene (sigma 5.8 px, peak 5244 ppm*m): of the 40 plume-centred
+    16 x 256 windows it is the one whose own retrieval at this lambda keeps
+    the most nonzero alpha (113, found with the oracle; a wide plume fills a
+    256-line column, enters its mean and covariance, and leaves alpha at 0)."""
+    spec, lam = _diff_workload()
+    g = make_globals(spec)
+    c0, l0 = (0, 0) if window == "first_columns" else (160, 2384)
+    sub = _subscene(spec, g, c0, l0)
     J, gL, gs = _gpu_grads(sub, 30, lam)
     Jr, gLr, gsr = loss_and_grads(sub.radiance, sub.s, sub.alpha_true, 30, lam)
-    print(f"sub-scene: J {J:.6e} ref {Jr:.6e}, grad L rel err {_rel_err(gL, gLr):.2e}, "
-          f"grad s rel err {_rel_err(gs, gsr):.2e}", flush=True)
-    assert abs(J - Jr) <= 1e-6 * Jr
-    assert _rel_err(gL, gLr) < 1e-4
-    assert _rel_err(gs, gsr) < 1e-4
+    vL, rL = _elementwise(gL, gLr)
+    vs, rs = _elementwise(gs, gsr)
+    print(f"sub-scene {window} (columns {c0}-{c0 + 15}, lines {l0}-{l0 + 255}, lambda {lam:.4g}): "
+          f"J {J:.6e} ref {Jr:.6e}; grad L: {vL} violations, max rel err above floor {rL:.2e}; "
+          f"grad s: {vs} violations, max rel err {rs:.2e}; max|grad L| {np.abs(gLr).max():.3e}",
+          flush=True)
+    assert abs(J - Jr) <= 1e-6 * max(Jr, 1e-300)
+    if window == "first_columns":
+        assert np.all(gLr == 0) and np.all(gsr == 0)
+        assert np.all(gL == 0) and np.all(gs == 0)
+    else:
+        assert np.abs(gLr).max() > 0 and np.abs(gsr).max() > 0
+        assert vL == 0 and vs == 0
+
+
+def test_adjoint_finite_differences_differentiation_scene():
+    """Central finite differences (FP64 numpy oracle, h = 1e-3) on 16 random
+    coordinates of the 598 x 4000 differentiation scene at its lambda.
+
+    12 radiance coordinates (6 pixels with alpha > 0, 6 pixels of columns
+    with a nonzero alpha; only the touched column is re-run), against the
+    gradient of the whole loss.  A stencil whose +h or -h run changes the
+    sparsity pattern is rejected and resampled, and so is one whose
+    difference quotient moves by more than 1e-3 relative between h and h/2
+    (a kink inside the stencil).
+
+    4 target bands with |s_b| >= 5 % of max|s| (step 1e-3 |s_b|), on the loss
+    of 64 random columns with a nonzero alpha (the columns whose alpha is all
+    zero stay locked at zero).  Pixels near the reweighting map's bifurcation
+    make J smooth but so curved in s that the difference quotient of a whole
+    column moves by percents between h and h/4, so each band keeps the columns
+    whose own quotient agrees to 1e-3 between h and h/2, and the adjoint is
+    run with the loss restricted to those columns."""
+    from oracle.mf64 import retrieve as oracle_retrieve, retrieve_column
+    spec, lam = _diff_workload()
+    sc = make_scene(spec)
+    S, N, B = sc.radiance.shape
+    K = 30
+    J, gL, gs = _gpu_grads(sc, K, lam)
+    L = sc.radiance.astype(np.float64)
+    at = sc.alpha_true
+    base, _ = oracle_retrieve(sc.radiance, sc.s, K, lam, workers=16)
+    pattern = base > 0
+    act = np.flatnonzero(pattern.any(axis=1))
+
+    def col_run(c, Lc, s):
+        a, _ = retrieve_column(Lc, s, K, lam)
+        return a, float(((a - at[c]) ** 2).sum())
+
+    rng = np.random.default_rng(2020)
+    on = np.argwhere(pattern)
+    checked, tries, worst = 0, 0, 0.0
+    while checked < 12 and tries < 80:
+        tries += 1
+        if checked < 6:
+            c, i = on[rng.integers(len(on))]
+        else:
+            c, i = int(rng.choice(act)), int(rng.integers(N))
+        b = int(rng.integers(B))
+        q = []
+        ok = True
+        for h in (1e-3, 5e-4):
+            Lp, Lm = L[c].copy(), L[c].copy()
+            Lp[i, b] += h
+            Lm[i, b] -= h
+            ap, Jp = col_run(c, Lp, sc.s)
+            am, Jm = col_run(c, Lm, sc.s)
+            if np.any((ap > 0) != pattern[c]) or np.any((am > 0) != pattern[c]):
+                ok = False
+                break
+            q.append((Jp - Jm) / (2 * h))
+        if not ok or abs(q[0] - q[1]) > 1e-3 * abs(q[0]) + 1e-9:
+            continue
+        fd = q[0]
+        err = abs(gL[c, i, b] - fd)
+        assert err <= 2e-3 * abs(fd) + 1e-6 * np.abs(gL).max(), (c, i, b, gL[c, i, b], fd)
+        worst = max(worst, err / max(abs(fd), 1e-300))
+        checked += 1
+    assert checked == 12, (checked, tries)
+
+    # target bands on the loss of a column subset, through the plan's backward
+    cols = np.sort(rng.choice(act, 64, replace=False))
+    dev_L = torch.from_numpy(sc.radiance).to(DEV)
+    dev_s = torch.from_numpy(sc.s).to(DEV)
+    dev_at = torch.from_numpy(at).to(DEV)
+    plan = mf.Plan([(0, S, N)], B, K, lam, 1e-9, True, "lowrank", save_for_backward=True)
+    ws = plan.alloc_workspace(DEV)
+    alpha = torch.empty((S, N), dtype=torch.float32, device=DEV)
+    bands = np.flatnonzero(np.abs(sc.s) >= 0.05 * np.abs(sc.s).max())
+    sb_checked, kept = 0, []
+    for b in rng.permutation(bands):
+        if sb_checked == 4:
+            break
+        q = []
+        ok = True
+        for rel in (1e-3, 5e-4):
+            h = rel * abs(float(sc.s[b]))
+            per = []
+            for sgn in (1.0, -1.0):
+                sp = sc.s.astype(np.float64).copy()
+                sp[b] += sgn * h
+                a, _ = oracle_retrieve(sc.radiance, sp, K, lam, columns=list(cols), workers=16)
+                ok = ok and not np.any((a > 0) != pattern[cols])
+                per.append(((a - at[cols]) ** 2).sum(axis=1))
+            q.append((per[0] - per[1]) / (2 * h))
+        if not ok:
+            continue
+        smooth = np.abs(q[0] - q[1]) <= 1e-3 * np.abs(q[0]) + 1e-9
+        if smooth.sum() < 16:
+            continue
+        fd = float(q[0][smooth].sum())
+        mask = torch.zeros((S, 1), dtype=torch.float64, device=DEV)
+        mask[torch.from_numpy(cols[smooth]).to(DEV)] = 1.0
+        plan.retrieve(dev_L, dev_s, alpha, None, None, ws)
+        g = (2.0 * (alpha.double() - dev_at) * mask).float()
+        _, gsb = plan.backward(dev_L, dev_s, g, None, ws)
+        torch.cuda.synchronize()
+        gb = float(gsb.cpu().numpy()[b])
+        assert abs(gb - fd) <= 2e-3 * abs(fd), (int(b), gb, fd, int(smooth.sum()))
+        kept.append(int(smooth.sum()))
+        sb_checked += 1
+    plan.close()
+    print(f"differentiation scene: 12 radiance coordinates in {tries} draws, worst rel err {worst:.2e}; "
+          f"{sb_checked} target bands on {kept} of 64 columns", flush=True)
+    assert sb_checked == 4
 
 
 def test_adjoint_finite_differences():

@@ -588,7 +588,8 @@ def run_ingest(mf, torch, np, dev, sc, K, lam, eps, n_fl=3):
 def run_batch(mf, torch, np, dev, K, lam, eps, steps, warmup):
     """Batched form: 32 ragged flightlines (598 columns, U{1000..12000} lines,
     0-20 % of each column masked in runs), one plan, chunk length picked by
-    the autotuner, launch sequence replayed as a HIP graph on a side stream.
+    the autotuner (with the streaming tile shape and the persistent grid),
+    launch sequence replayed as a HIP graph on a side stream.
     Columns of three flightlines are regenerated on the host and checked
     against the oracle."""
     from synth.scenes import batch_specs, make_scene, make_globals, make_column
@@ -618,9 +619,13 @@ def run_batch(mf, torch, np, dev, K, lam, eps, steps, warmup):
         f"{n_valid / total:.3f} valid, generated and uploaded in {gen_s:.1f}s")
     side = torch.cuda.Stream(device=dev)
     with torch.cuda.stream(side):
-        best, tune = mf.autotune_chunk(fls, dL, ds, dV, candidates=(512, 1024, 2048), reps=2,
-                                       n_bands=B, n_iter=K, lam=lam, eps=eps)
-        plan = mf.Plan(fls, B, K, lam, eps, True, "lowrank", chunk_lines=best)
+        t_tune = time.perf_counter()
+        best, tune = mf.autotune(fls, dL, ds, dV, chunks=(1024, 2048, 4096),
+                                 tiles=("32x4", "32x2", "64x2"), wgs=(0, 2, 3, 4), reps=2,
+                                 n_bands=B, n_iter=K, lam=lam, eps=eps)
+        tune_s = time.perf_counter() - t_tune
+        plan = mf.Plan(fls, B, K, lam, eps, True, "lowrank", chunk_lines=best["chunk_lines"])
+        plan.set_launch(best["stream_tile"], best["wgs_per_cu"])
         plan.set_graph(True)
         ws = plan.alloc_workspace(dev)
         alpha = torch.empty((total,), dtype=torch.float32, device=dev)
@@ -660,14 +665,15 @@ def run_batch(mf, torch, np, dev, K, lam, eps, steps, warmup):
                        f"{B} bands, 0-20 % masked per column, {K} iterations, lambda {lam:.4g}",
            "pixels": total, "valid_fraction": round(n_valid / total, 4),
            "px_per_s": round(total / dt, 1), "ms_per_step": round(dt * 1e3, 3), "steps": steps,
-           "chunk_lines": best, "autotune_ms": {str(k): round(v, 3) for k, v in tune.items()},
+           "launch": best, "autotune_s": round(tune_s, 1),
+           "autotune_ms": {str(k): round(v, 3) for k, v in tune.items()},
            "graph_replay": True, "columns_failed": int((st_host != 0).sum()),
            "sampled_columns_vs_fp64": {"columns": n_checked,
                                        "pixels": sum(e["pixels"] for e in errs),
                                        "pattern_agreement_min": min(e["pattern_agreement"] for e in errs),
                                        "max_err_over_tol": round(worst["max_err_over_tol"], 6),
                                        "tol_violations": sum(e["tol_violations"] for e in errs)}}
-    log(f"batch: {res['px_per_s'] / 1e6:.1f} Mpx/s, {res['ms_per_step']:.1f} ms/step, chunk {best}, "
+    log(f"batch: {res['px_per_s'] / 1e6:.1f} Mpx/s, {res['ms_per_step']:.1f} ms/step, launch {best}, "
         f"tune {res['autotune_ms']}, sampled vs FP64 {res['sampled_columns_vs_fp64']}")
     plan.close()
     del ws, dL, dV, alpha

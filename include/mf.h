@@ -234,6 +234,24 @@ MF_API mf_status mf_plan_energy(mf_plan plan, const void* workspace, double* ene
    stream or while kernel timing is on (plain launches then). */
 MF_API mf_status mf_plan_set_graph(mf_plan plan, int enable);
 
+/* Launch shape of the streaming passes (a tuning choice: every shape gives
+   the same result, bit for bit).
+     stream_tile  MF_TILE_*: pixels per wave chunk x waves per workgroup of the
+                  low-rank form's streaming passes
+     wgs_per_cu   0: one workgroup per work item (the default); n in [1, 16]:
+                  one persistent launch per pass with n workgroups per compute
+                  unit, which take the work items (longest first) from a
+                  per-pass queue counter in the workspace (cleared by the
+                  retrieval itself, no memset); no workgroup waits for another
+   A graph captured with the previous shape is dropped. */
+enum {
+  MF_TILE_32x4 = 0,  /* 32-pixel chunks (two lanes per pixel), 4 waves (default) */
+  MF_TILE_32x2 = 1,
+  MF_TILE_64x2 = 2,  /* 64-pixel chunks (one lane per pixel) */
+  MF_TILE_64x1 = 3
+};
+MF_API mf_status mf_plan_set_launch(mf_plan plan, int32_t stream_tile, int32_t wgs_per_cu);
+
 /* Kernel timing for benchmarks.  While enabled, mf_retrieve brackets each of
    its kernel launches with HIP events on the caller's stream (a few
    microseconds of extra stream work per launch). */

@@ -30,6 +30,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -122,6 +123,12 @@ struct PassArgs {
   double lam;
   double eps;
   int partial_stride;        // doubles per work item in the partial buffer
+  // persistent launch: the workgroups take work items from this pass's
+  // counter (zeroed by setup_kernel) in the order of `order`; null: one
+  // workgroup per work item (blockIdx.x)
+  int* queue;
+  const int32_t* order;
+  int n_items;
 };
 
 struct SolveArgs {
@@ -160,9 +167,12 @@ __global__ void __launch_bounds__(64) setup_kernel(const float* __restrict__ L,
                                                    const ColInfo* __restrict__ cols,
                                                    ColState* __restrict__ state, int B,
                                                    double* __restrict__ energy, int K1,
-                                                   int64_t n_cols) {
+                                                   int64_t n_cols, int* __restrict__ queue,
+                                                   int n_queue) {
   const int col = blockIdx.x;
   const int lane = threadIdx.x;
+  if (queue && col == 0)   // the passes' work-queue counters (persistent launches)
+    for (int k = lane; k < n_queue; k += 64) queue[k] = 0;
   const ColInfo ci = cols[col];
   int64_t z = -1;
   if (valid == nullptr) {
@@ -321,7 +331,7 @@ __device__ __forceinline__ void load_super(const PassArgs& a, int64_t base, int6
 // SCORE: passes j >= 1 (alpha^{j-1} and c = r alpha enter the Gram); pass 0
 // (SCORE = false) is the Gram of the shifted radiance alone.
 template <int NB, bool WIDE, int MODE, bool SCORE>
-__global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && SCORE) ? 1 : 2) pass_kernel(PassArgs a) {
+__device__ __forceinline__ void pass_item(const PassArgs& a, int item) {
   constexpr int T = n_tiles(NB);
   static_assert(MODE >= PM_F64, "the Gram pass; the streaming passes are stream_kernel");
   constexpr bool F32ACC = MODE == PM_F32 || MODE == PM_BF16;
@@ -332,7 +342,7 @@ __global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && SCORE) ? 1 : 2) pas
   // The rounded forms also accumulate, exactly in FP64, the moments of the
   // rank-3 identity for C^j: sum c L (per band), sum c and sum c^2.
   constexpr bool XMOM = SCORE && F32ACC;
-  const WorkItem it = a.items[blockIdx.x];
+  const WorkItem it = a.items[item];
   const ColState& st = a.state[it.col];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -584,7 +594,7 @@ __global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && SCORE) ? 1 : 2) pas
     for (; base < end; base += 128) super_step(base);
   }
 
-  double* out = a.partials + (int64_t)blockIdx.x * a.partial_stride;
+  double* out = a.partials + (int64_t)item * a.partial_stride;
   if constexpr (XMOM) {
     // the exact moments: the waves' sums in order
     __syncthreads();
@@ -626,10 +636,27 @@ __global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && SCORE) ? 1 : 2) pas
 // band-per-lane from the same tile, and skipped when the chunk has no
 // nonzero c (the enhancement is sparse).
 
-constexpr int kChunk = 32;                 // pixels per wave chunk (streaming passes)
-constexpr int kSW = 4;                     // waves per stream workgroup
+constexpr int kChunk = 32;                 // pixels per wave chunk (adjoint streaming pass)
+constexpr int kSW = 4;                     // waves per workgroup (adjoint streaming pass)
 constexpr int kSBlock = 64 * kSW;
 constexpr int kCopyGroup = 10;             // 16-byte loads in flight per lane while copying
+
+// Tile shape of the forward streaming pass: CHUNK pixels per wave chunk (32:
+// lanes l and l + 32 share pixel l, each running half of its bands; 64: one
+// pixel per lane) and SW waves per workgroup.
+template <int CHUNK, int SW>
+struct StreamTile {
+  static_assert(CHUNK == 32 || CHUNK == 64, "32 or 64 pixels per wave chunk");
+  static_assert(SW >= 1 && SW <= 4, "1 to 4 waves per workgroup");
+  static constexpr int kThreads = 64 * SW;
+  static constexpr int kGroups = (CHUNK * 80 / 4 + 63) / 64;   // 16-byte loads per lane per chunk
+  static constexpr int kTileFloats = kGroups * 64 * 4;         // floats per wave tile
+  static constexpr bool kSplit = CHUNK == 32;
+  // dynamic LDS bytes: c per pixel, moment partials, column constants, tiles
+  static constexpr size_t kLds = (size_t)SW * CHUNK * sizeof(double) + SW * (kPad + 3) * sizeof(double) +
+                                 4 * kPad * sizeof(double) + (size_t)SW * kTileFloats * sizeof(float);
+  static_assert(kLds + 16 <= 64 * 1024, "within the default dynamic LDS of a workgroup");
+};
 
 // Synchronous copy of one chunk (contiguous in memory) into a wave's LDS tile.
 __device__ __forceinline__ void copy_chunk(const float* g, int nfl, float* my, int lane) {
@@ -670,27 +697,45 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// A wave's radiance tile: kF4 16-byte groups per lane (a whole chunk of up to
-// 80 bands), so the fast path writes it without bounds tests.
+// A wave's radiance tile (adjoint pass): kF4 16-byte groups per lane (a whole
+// chunk of up to 80 bands), so the fast path writes it without bounds tests.
 constexpr int kF4 = (kChunk * 80 / 4 + 63) / 64;     // 10
 constexpr int kTileF = kF4 * 64 * 4;                  // floats per wave tile
 
-// Dynamic LDS bytes of stream_kernel (about 46 KB).
-__host__ __device__ constexpr size_t stream_lds_bytes(int B) {
-  return (size_t)kSW * kChunk * sizeof(double) + kSW * (kPad + 3) * sizeof(double) +
-         4 * kPad * sizeof(double) + (size_t)kSW * kTileF * sizeof(float);
+// Wave-uniform copies (scalar registers) of values every lane loaded alike.
+__device__ __forceinline__ int uni32(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uni64(int64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double unif64(double x) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(x)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(x)));
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
-  const WorkItem it = a.items[blockIdx.x];
+// One work item of the forward streaming pass.  The work item and the
+// column's scalars are read once and made wave-uniform: in the persistent
+// loop the compiler cannot prove them unchanged by earlier stores, so it
+// would keep them as vector loads and wait for every load in flight (the
+// next chunk's prefetch included) where the score first uses them.
+template <int MODE, int CHUNK, int SW>
+__device__ __forceinline__ void stream_item(const PassArgs& a, int item, double* dyn) {
+  using T = StreamTile<CHUNK, SW>;
+  constexpr int kChunk = CHUNK, kSW = SW, kSBlock = T::kThreads, kF4 = T::kGroups, kTileF = T::kTileFloats;
+  WorkItem it;
+  {
+    const WorkItem w = a.items[item];
+    it.px_begin = uni64(w.px_begin);
+    it.col = uni32(w.col);
+    it.n_px = uni32(w.n_px);
+  }
   const ColState* __restrict__ st = a.state + it.col;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
   const int B = a.B;
   const int64_t begin = it.px_begin, end = begin + it.n_px;
-  extern __shared__ double dyn[];
   double* cbuf = dyn;                                   // [kSW][kChunk]
   double* redm = cbuf + kSW * kChunk;                   // [kSW][kPad + 3]
   double* cst = redm + kSW * (kPad + 3);                // [kPad] v, m0, lbar; mu . v
@@ -729,13 +774,14 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
     for (int k = 0; k < kF4; ++k) pre[k] = load16(rs, (lane + 64 * k) * 16);
   }
 
-  if (st->status != MF_COL_OK) {           // failed column: alpha = 0, no moments
+  if (uni32(st->status) != MF_COL_OK) {    // failed column: alpha = 0, no moments
     for (int64_t px = begin + tid; px < end; px += kSBlock) {
       if (a.alpha_out) a.alpha_out[px] = 0.0;
       if (a.alpha_final) a.alpha_final[px] = 0.f;
     }
     return;
   }
+  const double q = unif64(st->q);
   for (int b = tid; b < kPad; b += kSBlock) {
     cst[b] = st->v[b];
     cst[kPad + b] = st->m0[b];
@@ -749,8 +795,7 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
     if (lane == 0) cst[3 * kPad] = d;
   }
   __syncthreads();
-  const double muv = cst[3 * kPad];
-  const double q = st->q;
+  const double muv = unif64(cst[3 * kPad]);
   const double lam = a.lam, eps = a.eps;
   const int j = a.j;
 
@@ -767,8 +812,8 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
   // bands [0, h), the upper one [h, B), and the two partial dot products are
   // added across the halves; every later step of the score is the lower
   // lane's (the upper lanes hold the same values and store nothing).
-  const int hsplit = ((B + 3) / 4) * 2;        // even, so both halves start on a pair
-  const int upper = lane >> 5;
+  const int hsplit = T::kSplit ? ((B + 3) / 4) * 2 : B;   // even, so both halves start on a pair
+  const int upper = T::kSplit ? lane >> 5 : 0;
   auto score = [&](int64_t c0, int n, uint32_t vld, double ap, double rp, const float* tl) {
     const int pxl = lane & (kChunk - 1);
     const int64_t px = c0 + pxl;
@@ -817,8 +862,10 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
       }
     }
     double pp = pe + po, rr = re + ro;
-    pp += __shfl_xor(pp, 32, 64);               // both halves of the pixel's bands
-    if (own_r) rr += __shfl_xor(rr, 32, 64);
+    if constexpr (T::kSplit) {
+      pp += __shfl_xor(pp, 32, 64);             // both halves of the pixel's bands
+      if (own_r) rr += __shfl_xor(rr, 32, 64);
+    }
     pp -= muv;
     double c = 0.0;
     if (j >= 1) {
@@ -926,7 +973,7 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
       rw[kVecE] = se;
     }
     __syncthreads();
-    double* out = a.partials + (int64_t)blockIdx.x * a.partial_stride;
+    double* out = a.partials + (int64_t)item * a.partial_stride;
     for (int e = tid; e < kPad + 3; e += kSBlock) {
       double sum = 0.0;
       for (int w = 0; w < kSW; ++w) sum += redm[w * (kPad + 3) + e];
@@ -939,10 +986,58 @@ __global__ void __launch_bounds__(kSBlock) stream_kernel(PassArgs a) {
       if (tid == 0) {
         double sum = 0.0;
         for (int w = 0; w < kSW; ++w) sum += redm[w];
-        a.partials[(int64_t)blockIdx.x * a.partial_stride + kVecE] = sum;
+        a.partials[(int64_t)item * a.partial_stride + kVecE] = sum;
       }
     }
   }
+}
+
+// Work items of a persistent pass come from the pass's queue counter:
+// thread 0 takes a ticket, the workgroup reads it through LDS, and every
+// workgroup stops once the counter passes the item count, so the grid
+// drains without waiting on another workgroup.  The ticket for the next
+// item is requested when an item starts and read when it ends, so the
+// atomic's latency overlaps the item's work.  Tickets map to items through
+// `order` (longest first) and are marked wave-uniform (readfirstlane), so
+// the work item, column state and buffer resources derived from them stay in
+// scalar registers.
+__device__ __forceinline__ int share_ticket(int mine, int* slot) {
+  if (threadIdx.x == 0) *slot = mine;
+  __syncthreads();
+  const int t = __builtin_amdgcn_readfirstlane(*slot);
+  __syncthreads();                       // every thread has read it before it is reused
+  return t;
+}
+__device__ __forceinline__ int ticket_item(const PassArgs& a, int t) {
+  return a.order ? __builtin_amdgcn_readfirstlane(a.order[t]) : t;
+}
+
+// PERSIST: a persistent grid taking work items from the pass's queue; else
+// one workgroup per work item (blockIdx.x).
+// The dynamic LDS holds everything (the ticket slot after the tiles): a
+// static LDS variable would move the dynamic buffer off the 16-byte alignment
+// that the tiles' 16-byte stores and the constants' paired reads need.
+template <int MODE, int CHUNK, int SW, bool PERSIST>
+__global__ void __launch_bounds__(64 * SW) stream_kernel(PassArgs a) {
+  extern __shared__ __align__(16) double dyn[];
+  if constexpr (!PERSIST) {
+    stream_item<MODE, CHUNK, SW>(a, (int)blockIdx.x, dyn);
+  } else {
+    int* slot = reinterpret_cast<int*>(reinterpret_cast<char*>(dyn) + StreamTile<CHUNK, SW>::kLds);
+    int t = share_ticket(threadIdx.x == 0 ? atomicAdd(a.queue, 1) : 0, slot);
+    while (t < a.n_items) {
+      const int next = threadIdx.x == 0 ? atomicAdd(a.queue, 1) : 0;   // read after the item
+      stream_item<MODE, CHUNK, SW>(a, ticket_item(a, t), dyn);
+      t = share_ticket(next, slot);
+    }
+  }
+}
+
+// The Gram passes run one workgroup per work item (their registers leave
+// no room for the persistent loop).
+template <int NB, bool WIDE, int MODE, bool SCORE>
+__global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && SCORE) ? 1 : 2) pass_kernel(PassArgs a) {
+  pass_item<NB, WIDE, MODE, SCORE>(a, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -2838,6 +2933,12 @@ struct mf_plan_s {
   size_t off_energy = 0;     // track_energy: E^k per partition [K+1][n_cols]
   size_t ws_bytes = 0;
   void* scratch_d = nullptr; // this device's `scratch` (mf_retrieve_noalloc)
+  // launch shape of the passes (mf_plan_set_launch)
+  int stream_tile = 0;       // MF_TILE_*
+  int wgs_per_cu = 0;        // 0: one workgroup per work item; n: persistent grid
+  int n_cu = 0;
+  int32_t* order_d = nullptr; // work items, longest first (persistent launches)
+  size_t off_queue = 0;      // K + 2 queue counters
 };
 
 namespace {
@@ -2877,6 +2978,26 @@ struct LaunchTimer {
   }
 };
 
+// Grid of a pass: one workgroup per work item, or the persistent grid of
+// wgs_per_cu workgroups per compute unit (at most one per work item).
+unsigned pass_grid(const mf_plan_s* p, const PassArgs& a) {
+  if (!a.queue) return (unsigned)p->n_items;
+  return (unsigned)std::min<int64_t>(p->n_items, (int64_t)p->wgs_per_cu * p->n_cu);
+}
+
+template <int CHUNK, int SW>
+void launch_stream(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t s) {
+  using T = StreamTile<CHUNK, SW>;
+  const dim3 g(pass_grid(p, a)), b(T::kThreads);
+  if (a.queue) {                           // + the ticket slot
+    if (mode == PM_NONE) hipLaunchKernelGGL((stream_kernel<PM_NONE, CHUNK, SW, true>), g, b, T::kLds + 16, s, a);
+    else hipLaunchKernelGGL((stream_kernel<PM_VEC, CHUNK, SW, true>), g, b, T::kLds + 16, s, a);
+  } else {
+    if (mode == PM_NONE) hipLaunchKernelGGL((stream_kernel<PM_NONE, CHUNK, SW, false>), g, b, T::kLds, s, a);
+    else hipLaunchKernelGGL((stream_kernel<PM_VEC, CHUNK, SW, false>), g, b, T::kLds, s, a);
+  }
+}
+
 template <int NB, bool WIDE>
 void launch_pass_nb(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t s) {
   const dim3 g((unsigned)p->n_items), b(kBlock);
@@ -2897,10 +3018,12 @@ void launch_pass_nb(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t
 
 void dispatch_pass(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t s) {
   if (mode == PM_NONE || mode == PM_VEC) {
-    const dim3 g((unsigned)p->n_items), b(kSBlock);
-    const size_t lds = stream_lds_bytes(a.B);
-    if (mode == PM_NONE) hipLaunchKernelGGL(stream_kernel<PM_NONE>, g, b, lds, s, a);
-    else hipLaunchKernelGGL(stream_kernel<PM_VEC>, g, b, lds, s, a);
+    switch (p->stream_tile) {
+      case MF_TILE_32x2: launch_stream<32, 2>(p, a, mode, s); break;
+      case MF_TILE_64x2: launch_stream<64, 2>(p, a, mode, s); break;
+      case MF_TILE_64x1: launch_stream<64, 1>(p, a, mode, s); break;
+      default: launch_stream<32, 4>(p, a, mode, s); break;
+    }
     return;
   }
   switch (p->nb) {
@@ -2978,11 +3101,12 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   const int B = p->opt.n_bands;
   const int K = p->opt.n_iter;
   double* energy = p->opt.track_energy ? (double*)(ws + p->off_energy) : nullptr;
+  int* queue = p->wgs_per_cu > 0 ? (int*)(ws + p->off_queue) : nullptr;
 
   {
     LaunchTimer tm(p, MF_KERNEL_OTHER, st);
     hipLaunchKernelGGL(setup_kernel, dim3((unsigned)p->n_cols), dim3(64), 0, st, radiance, valid,
-                       p->cols_d, state, B, energy, K + 1, p->n_cols);
+                       p->cols_d, state, B, energy, K + 1, p->n_cols, queue, K + 2);
   }
   PassArgs pa{};
   pa.L = radiance;
@@ -3011,8 +3135,11 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   sa.ck = p->opt.save_for_backward ? (double*)(ws + p->off_ck_col) : nullptr;
   sa.n_cols = (int)p->n_cols;
   sa.energy = energy;
+  pa.order = p->order_d;
+  pa.n_items = (int)p->n_items;
   for (int j = 0; j <= K + 1; ++j) {
     pa.j = j;
+    pa.queue = queue ? queue + j : nullptr;
     pa.track_energy = (energy && j >= 1) ? 1 : 0;
     pa.unclamped = (j == 1 && K == 0) ? 1 : 0;
     if (ck_alpha) {          // save_for_backward: keep alpha^0..alpha^K
@@ -3198,11 +3325,32 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
     return fail_with(MF_E_DEVICE, "plan tables: " + e);
   }
   {
+    // work items longest first, for the persistent launches' queue (ragged
+    // batches: the short items fill the tail); ties keep the plan's order
+    std::vector<int32_t> order(items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return items[x].n_px > items[y].n_px; });
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, p->device) != hipSuccess ||
+        hipMalloc(&p->order_d, order.size() * sizeof(int32_t)) != hipSuccess ||
+        hipMemcpy(p->order_d, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+      const std::string e = hipGetErrorString(hipGetLastError());
+      if (p->order_d) (void)hipFree(p->order_d);
+      (void)hipFree(p->cols_d);
+      (void)hipFree(p->items_d);
+      delete p;
+      return fail_with(MF_E_DEVICE, "plan tables: " + e);
+    }
+    p->n_cu = prop.multiProcessorCount;
+  }
+  {
     std::string err;
     p->scratch_d = scratch_address(p->device, err);
     if (!p->scratch_d) {
       (void)hipFree(p->cols_d);
       (void)hipFree(p->items_d);
+      (void)hipFree(p->order_d);
       delete p;
       return fail_with(MF_E_DEVICE, err);
     }
@@ -3243,6 +3391,8 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
     p->off_energy = off;
     off = align256(off + ((size_t)opt->n_iter + 1) * (size_t)p->n_cols * sizeof(double));
   }
+  p->off_queue = off;                          // persistent launches' queue counters
+  off = align256(off + ((size_t)opt->n_iter + 2) * sizeof(int));
   p->ws_bytes = off;
   *out = p;
   g_last_error.clear();
@@ -3501,6 +3651,22 @@ mf_status mf_stream_read(const float* src, int64_t n, float* sink, int32_t n_blo
   return rc;
 }
 
+mf_status mf_plan_set_launch(mf_plan p, int32_t stream_tile, int32_t wgs_per_cu) {
+  if (!p) return fail_with(MF_E_ARG, "plan is NULL");
+  if (stream_tile < MF_TILE_32x4 || stream_tile > MF_TILE_64x1)
+    return fail_with(MF_E_ARG, "stream_tile must be one of MF_TILE_*");
+  if (wgs_per_cu < 0 || wgs_per_cu > 16) return fail_with(MF_E_ARG, "wgs_per_cu must be in [0, 16]");
+  if (p->stream_tile != stream_tile || p->wgs_per_cu != wgs_per_cu) {
+    p->stream_tile = stream_tile;
+    p->wgs_per_cu = wgs_per_cu;
+    if (p->graph_exec) {                       // the captured launches no longer apply
+      (void)hipGraphExecDestroy(p->graph_exec);
+      p->graph_exec = nullptr;
+    }
+  }
+  return MF_OK;
+}
+
 mf_status mf_plan_set_timing(mf_plan p, int enable) {
   if (!p) return fail_with(MF_E_ARG, "plan is NULL");
   p->timing = enable != 0;
@@ -3552,6 +3718,7 @@ void mf_plan_destroy(mf_plan p) {
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   if (p->cols_d) (void)hipFree(p->cols_d);
   if (p->items_d) (void)hipFree(p->items_d);
+  if (p->order_d) (void)hipFree(p->order_d);
   delete p;
 }
 

@@ -100,3 +100,104 @@ def test_autotuner_picks_a_candidate(tmp_path):
     best2, _ = mf.autotune_chunk(fls, Lt, st, Vt, candidates=(256, 512, 1024), reps=2,
                                  cache_path=cache, n_iter=5, lam=2.0)
     assert best2 == best
+
+
+@pytest.mark.parametrize("tile", ["32x4", "32x2", "64x2", "64x1"])
+@pytest.mark.parametrize("wgs", [0, 1, 3])
+def test_launch_shapes_give_the_same_alpha(tile, wgs):
+    """Every streaming tile shape, with one workgroup per work item or a
+    persistent grid taking work items from the queue (1 and 3 workgroups per
+    compute unit: far fewer workgroups than items), gives the default launch's
+    alpha and statuses bit for bit on the ragged masked batch (chunks of 128
+    lines: many items per column, ragged tails), and matches the oracle."""
+    scenes, fls, L, V = _batch()
+    s = scenes[0].s
+    Lt = torch.from_numpy(L).to(DEV)
+    Vt = torch.from_numpy(V).to(DEV)
+    st = torch.from_numpy(s).to(DEV)
+    outs = []
+    for shape in (("32x4", 0), (tile, wgs)):
+        plan = mf.Plan(fls, 74, 15, 3.0, 1e-9, True, "lowrank", chunk_lines=128)
+        plan.set_launch(*shape)
+        alpha = torch.full((L.shape[0],), -7.0, dtype=torch.float32, device=DEV)
+        status = torch.empty(plan.n_columns, dtype=torch.int32, device=DEV)
+        ws = plan.alloc_workspace()
+        plan.retrieve(Lt, st, alpha, Vt, status, ws)
+        plan.retrieve(Lt, st, alpha, Vt, status, ws)        # the queue counters restart
+        torch.cuda.synchronize()
+        outs.append((alpha.cpu().numpy(), status.cpu().numpy()))
+        plan.close()
+    np.testing.assert_array_equal(outs[1][1], outs[0][1])
+    np.testing.assert_array_equal(outs[1][0], outs[0][0])
+    o, S, N = fls[1]
+    ref, _ = oracle_retrieve(scenes[1].radiance, s, 15, 3.0, valid=scenes[1].valid)
+    assert_fp32_parity(outs[1][0][o:o + S * N].reshape(S, N), ref, label=f"tile {tile} wgs {wgs}")
+
+
+def test_persistent_graph_replays_match_eager():
+    """The persistent launch captured in a graph: the queue counters are
+    cleared by the retrieval's own first kernel, so every replay (with eager
+    work in between) equals the eager result."""
+    scenes, fls, L, V = _batch()
+    plan = mf.Plan(fls, 74, 12, 2.0, 1e-9, True, "lowrank", chunk_lines=256)
+    plan.set_launch("32x2", 2)
+    Lt = torch.from_numpy(L).to(DEV)
+    Vt = torch.from_numpy(V).to(DEV)
+    st = torch.from_numpy(scenes[0].s).to(DEV)
+    ws = plan.alloc_workspace()
+    eager = torch.empty(L.shape[0], dtype=torch.float32, device=DEV)
+    plan.retrieve(Lt, st, eager, Vt, None, ws)
+    torch.cuda.synchronize()
+    inplan = np.zeros(L.shape[0], bool)
+    for o, S, N in fls:
+        inplan[o:o + S * N] = True
+    ref = eager.cpu().numpy()[inplan]
+    stream = torch.cuda.Stream()
+    plan.set_graph(True)
+    out = torch.empty_like(eager)
+    for rep in range(4):
+        out.fill_(123.0)
+        junk = torch.randn(1 << 20, device=DEV).sum()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            plan.retrieve(Lt, st, out, Vt, None, ws, stream=stream)
+        stream.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy()[inplan], ref, err_msg=f"replay {rep}")
+        del junk
+    plan.set_graph(False)
+    plan.close()
+
+
+def test_launch_autotuner(tmp_path):
+    """The autotuner searches work-item length, tile shape and persistent
+    grid, returns candidates it timed, caches them, and its choice retrieves
+    the same alpha as the default launch."""
+    scenes, fls, L, V = _batch()
+    Lt = torch.from_numpy(L).to(DEV)
+    Vt = torch.from_numpy(V).to(DEV)
+    st = torch.from_numpy(scenes[0].s).to(DEV)
+    cache = str(tmp_path / "tune.json")
+    kw = dict(n_iter=5, lam=2.0)
+    best, times = mf.autotune(fls, Lt, st, Vt, chunks=(256, 512), tiles=("32x4", "32x2", "64x2"),
+                              wgs=(0, 2), reps=1, cache_path=cache, **kw)
+    assert best["chunk_lines"] in (256, 512) and best["stream_tile"] in ("32x4", "32x2", "64x2")
+    assert best["wgs_per_cu"] in (0, 2) and len(times) >= 4
+    best2, _ = mf.autotune(fls, Lt, st, Vt, chunks=(256, 512), tiles=("32x4", "32x2", "64x2"),
+                           wgs=(0, 2), reps=1, cache_path=cache, **kw)
+    assert best2 == best
+    outs = []
+    for cfg in ({"chunk_lines": 512, "stream_tile": "32x4", "wgs_per_cu": 0}, best):
+        plan = mf.Plan(fls, 74, 5, 2.0, 1e-9, True, "lowrank", chunk_lines=cfg["chunk_lines"])
+        plan.set_launch(cfg["stream_tile"], cfg["wgs_per_cu"])
+        a = torch.empty(L.shape[0], dtype=torch.float32, device=DEV)
+        plan.retrieve(Lt, st, a, Vt)
+        torch.cuda.synchronize()
+        outs.append(a.cpu().numpy())
+        plan.close()
+    inplan = np.zeros(L.shape[0], bool)
+    for o, S, N in fls:
+        inplan[o:o + S * N] = True
+    # a different work-item length changes the order of the partial sums, so
+    # the comparison is the FP32 bar against the default launch
+    d = np.abs(outs[0][inplan] - outs[1][inplan])
+    assert np.all(d <= 1e-4 * np.abs(outs[0][inplan]) + 0.1)

@@ -114,7 +114,7 @@ struct PassArgs {
   double* p_save;            // save_for_backward: p^{j-1} = (L - mu) . v per pixel (j >= 1)
   int64_t n_floats;          // floats of the radiance array (max_px * B)
   int track_energy;          // accumulate the pixel part of E^{j-1} (partial slot kVecE)
-  double* r_out;             // r per pixel written by this pass (low-rank form, j = 1)
+  double* r_out;             // r per pixel written by this pass (j = 1)
   const double* r_in;        // r per pixel from pass 1, or null: computed here
   int B;
   int j;
@@ -294,11 +294,12 @@ __device__ __forceinline__ double row_sum16_f64(double x) {
 template <int NB, bool WIDE>
 __device__ __forceinline__ void load_super(const PassArgs& a, int64_t base, int64_t end, int lane,
                                            int row, int c16, float (&Lv)[8][NB], double& ap,
-                                           uint32_t& vb) {
+                                           uint32_t& vb, double& rp) {
   const int B = a.B;
   const int n = (int)max<int64_t>(0, min<int64_t>(32, end - base));
   const __amdgpu_buffer_rsrc_t ra = chunk_rsrc(a.alpha_prev ? a.alpha_prev + base : nullptr,
                                                a.alpha_prev ? n * 8 : 0);
+  const __amdgpu_buffer_rsrc_t rr = chunk_rsrc(a.r_in ? a.r_in + base : nullptr, a.r_in ? n * 8 : 0);
   const __amdgpu_buffer_rsrc_t rv = chunk_rsrc(a.valid ? a.valid + base : nullptr, a.valid ? n : 0);
   // one resource per sub-step (its 4 rows, or fewer at the item's end), so
   // the lane offsets are the same in every sub-step and every range check is
@@ -326,11 +327,15 @@ __device__ __forceinline__ void load_super(const PassArgs& a, int64_t base, int6
   }
   ap = load8(ra, (lane & 31) * 8);
   vb = load1(rv, lane & 31);
+  rp = load8(rr, (lane & 31) * 8);
 }
 
 // SCORE: passes j >= 1 (alpha^{j-1} and c = r alpha enter the Gram); pass 0
 // (SCORE = false) is the Gram of the shifted radiance alone.
-template <int NB, bool WIDE, int MODE, bool SCORE>
+// RIN: the albedo factor r of each pixel comes from the buffer pass 1 wrote
+// (a.r_in), so the score needs only L . v; otherwise r = L . m0 is formed
+// here (pass 1 also writes it when a.r_out is set).
+template <int NB, bool WIDE, int MODE, bool SCORE, bool RIN>
 __device__ __forceinline__ void pass_item(const PassArgs& a, int item) {
   constexpr int T = n_tiles(NB);
   static_assert(MODE >= PM_F64, "the Gram pass; the streaming passes are stream_kernel");
@@ -406,7 +411,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& a, int item) {
   // The Gram passes run one or two waves per SIMD: the next super-step's
   // loads are in flight while the current one is computed, and are waited
   // for only when they are moved into place after it.
-  auto compute = [&](const float (&Lc)[8][NB], double apl, uint32_t vbl, int64_t bx) {
+  auto compute = [&](const float (&Lc)[8][NB], double apl, uint32_t vbl, double rpl, int64_t bx) {
     [[maybe_unused]] bf16x8 ybf[NB];
     // SCORE: c = r alpha^{j-1} of pixel 4s + row of the super-step, or -1
     // for a pixel that stays out of the Gram (invalid, or past the item)
@@ -415,49 +420,66 @@ __device__ __forceinline__ void pass_item(const PassArgs& a, int item) {
       // The lane's partial dot products for its row's 8 pixels:
       // L . v in v16[s] (p = L . v - mu . v), r = m0 . L in v16[8 + s]
       // (bands past B hold zeros in L, v and m0).
-      double v16[16];
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        double pe = 0.0, re = 0.0;
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-          const double l = (double)Lc[s][k];
-          pe = fma(l, vv[k], pe);
-          re = fma(l, m0[k], re);
-        }
-        v16[s] = pe;
-        v16[8 + s] = re;
-      }
       // Transpose reduction over the 16 lanes of each row: at each step a
       // lane keeps half of its values, sends the other half to its partner
       // (partners differ in one bit of the lane's column) and adds what it
-      // receives, so lane c of the row ends with the row total of value c.
+      // receives.  With 16 values (L . v and L . m0 of the row's 8 pixels)
+      // lane c of the row ends with the row total of value c; with the 8 of
+      // L . v alone, lanes 2s and 2s + 1 end with that of value s.
       double v8[8], v4[4], v2[2];
-      {
+      if constexpr (!RIN) {
+        double v16[16];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          double pe = 0.0, re = 0.0;
+#pragma unroll
+          for (int k = 0; k < NB; ++k) {
+            const double l = (double)Lc[s][k];
+            pe = fma(l, vv[k], pe);
+            re = fma(l, m0[k], re);
+          }
+          v16[s] = pe;
+          v16[8 + s] = re;
+        }
         const bool hi = (c16 & 8) != 0;        // row_mirror: c <-> 15 - c
 #pragma unroll
         for (int i = 0; i < 8; ++i)
           v8[i] = (hi ? v16[i + 8] : v16[i]) + dpp_f64<0x140>(hi ? v16[i] : v16[i + 8]);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          double pe = 0.0;
+#pragma unroll
+          for (int k = 0; k < NB; ++k) pe = fma((double)Lc[s][k], vv[k], pe);
+          v8[s] = pe;
+        }
       }
+      constexpr int kMirror = RIN ? 0x140 : 0x141;   // first 8-value step: row_mirror
       {
-        const bool hi = (c16 & 4) != 0;        // row_half_mirror: c <-> 7 - c in each half
+        const bool hi = (c16 & (RIN ? 8 : 4)) != 0;  // then row_half_mirror
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          v4[i] = (hi ? v8[i + 4] : v8[i]) + dpp_f64<0x141>(hi ? v8[i] : v8[i + 4]);
+          v4[i] = (hi ? v8[i + 4] : v8[i]) + dpp_f64<kMirror>(hi ? v8[i] : v8[i + 4]);
       }
       {
-        const bool hi = (c16 & 2) != 0;        // c <-> c ^ 2
+        constexpr int kStep = RIN ? 0x141 : 0x4E;   // row_half_mirror, or c <-> c ^ 2
+        const bool hi = (c16 & (RIN ? 4 : 2)) != 0;
 #pragma unroll
         for (int i = 0; i < 2; ++i)
-          v2[i] = (hi ? v4[i + 2] : v4[i]) + dpp_f64<0x4E>(hi ? v4[i] : v4[i + 2]);
+          v2[i] = (hi ? v4[i + 2] : v4[i]) + dpp_f64<kStep>(hi ? v4[i] : v4[i + 2]);
       }
-      const bool hi1 = (c16 & 1) != 0;         // c <-> c ^ 1
-      const double v1 = (hi1 ? v2[1] : v2[0]) + dpp_f64<0xB1>(hi1 ? v2[0] : v2[1]);
+      double v1;
+      {
+        constexpr int kStep = RIN ? 0x4E : 0xB1;    // c <-> c ^ 2, or c <-> c ^ 1
+        const bool hi1 = (c16 & (RIN ? 2 : 1)) != 0;
+        v1 = (hi1 ? v2[1] : v2[0]) + dpp_f64<kStep>(hi1 ? v2[0] : v2[1]);
+        if constexpr (RIN) v1 += dpp_f64<0xB1>(v1);   // c <-> c ^ 1: the full row total
+      }
       // One pixel per lane from here: lane l (and l + 32) holds pixel
       // qx = l mod 32 of the super-step, sub-step qx / 4, row qx mod 4.
       const int qx = lane & 31;
-      const double pp = __shfl(v1, 16 * (qx & 3) + (qx >> 2), 64) - muv;
-      const double rr = __shfl(v1, 16 * (qx & 3) + 8 + (qx >> 2), 64);
+      const double pp = __shfl(v1, 16 * (qx & 3) + (RIN ? 2 : 1) * (qx >> 2), 64) - muv;
+      const double rr = RIN ? rpl : __shfl(v1, 16 * (qx & 3) + 8 + (qx >> 2), 64);
       const int64_t px = bx + qx;
       const bool ok = px < end && (a.valid == nullptr || vbl != 0u);
       const double r = a.albedo ? rr : 1.0;
@@ -469,6 +491,9 @@ __device__ __forceinline__ void pass_item(const PassArgs& a, int item) {
       if (lane < 32 && px < end) {
         if (a.alpha_out) a.alpha_out[px] = al;
         if (a.alpha_final) a.alpha_final[px] = (float)al;
+        if constexpr (!RIN) {
+          if (a.r_out) a.r_out[px] = ok ? r : 0.0;
+        }
       }
       const double cenc = ok ? ((!dark && al > 0.0) ? r * al : 0.0) : -1.0;
 #pragma unroll
@@ -577,12 +602,12 @@ __device__ __forceinline__ void pass_item(const PassArgs& a, int item) {
   int64_t base = begin + 32 * wid;
   if (base < end) {
     float LA[8][NB], LB[8][NB];
-    double apA, apB;
+    double apA, apB, rA, rB;
     uint32_t vA, vB;
-    load_super<NB, WIDE>(a, base, end, lane, row, c16, LA, apA, vA);
+    load_super<NB, WIDE>(a, base, end, lane, row, c16, LA, apA, vA, rA);
     auto super_step = [&](int64_t bx) {
-      load_super<NB, WIDE>(a, bx + 128, end, lane, row, c16, LB, apB, vB);
-      compute(LA, apA, vA, bx);
+      load_super<NB, WIDE>(a, bx + 128, end, lane, row, c16, LB, apB, vB, rB);
+      compute(LA, apA, vA, rA, bx);
       __builtin_amdgcn_sched_barrier(0);   // the copy below waits for the loads
 #pragma unroll
       for (int s = 0; s < 8; ++s)
@@ -590,6 +615,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& a, int item) {
         for (int k = 0; k < NB; ++k) LA[s][k] = LB[s][k];
       apA = apB;
       vA = vB;
+      rA = rB;
     };
     for (; base < end; base += 128) super_step(base);
   }
@@ -1035,9 +1061,9 @@ __global__ void __launch_bounds__(64 * SW) stream_kernel(PassArgs a) {
 
 // The Gram passes run one workgroup per work item (their registers leave
 // no room for the persistent loop).
-template <int NB, bool WIDE, int MODE, bool SCORE>
+template <int NB, bool WIDE, int MODE, bool SCORE, bool RIN>
 __global__ void __launch_bounds__(kBlock, (MODE == PM_F64 && SCORE) ? 1 : 2) pass_kernel(PassArgs a) {
-  pass_item<NB, WIDE, MODE, SCORE>(a, (int)blockIdx.x);
+  pass_item<NB, WIDE, MODE, SCORE, RIN>(a, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -3002,16 +3028,20 @@ template <int NB, bool WIDE>
 void launch_pass_nb(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t s) {
   const dim3 g((unsigned)p->n_items), b(kBlock);
   const bool sc = a.j >= 1;
+  const bool rin = a.r_in != nullptr;
   switch (mode) {
     case PM_F64:
-      if (sc) hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F64, true>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F64, false>), g, b, 0, s, a);
+      if (!sc) hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F64, false, false>), g, b, 0, s, a);
+      else if (rin) hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F64, true, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F64, true, false>), g, b, 0, s, a);
       break;
     case PM_F32:      // scored passes only (pass 0 is FP64 in every form)
-      hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F32, true>), g, b, 0, s, a);
+      if (rin) hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F32, true, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F32, true, false>), g, b, 0, s, a);
       break;
     default:
-      hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16, true>), g, b, 0, s, a);
+      if (rin) hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16, true, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16, true, false>), g, b, 0, s, a);
       break;
   }
 }
@@ -3151,10 +3181,10 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
     }
     pa.alpha_final = j == K + 1 ? alpha : nullptr;
     pa.p_save = (ck_p && j >= 1) ? ck_p + (int64_t)(j - 1) * p->max_px : nullptr;
-    const bool lowrank = p->opt.cov == MF_COV_LOWRANK;
+    // r per pixel: written by pass 1, read by every later scored pass
     double* rbuf = (double*)(ws + p->off_r);
-    pa.r_out = (lowrank && j == 1) ? rbuf : nullptr;
-    pa.r_in = (lowrank && j >= 2) ? rbuf : nullptr;
+    pa.r_out = j == 1 ? rbuf : nullptr;
+    pa.r_in = j >= 2 ? rbuf : nullptr;
     const bool mom = j <= K;
     const int mode = pass_mode(p->opt.cov, j, K);
     {
@@ -3368,8 +3398,8 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   off = align256(off + (size_t)max_px * sizeof(double));
   p->off_alpha1 = off;
   off = align256(off + (size_t)max_px * sizeof(double));
-  p->off_r = off;                              // r per pixel (low-rank form)
-  if (opt->cov == MF_COV_LOWRANK) off = align256(off + (size_t)max_px * sizeof(double));
+  p->off_r = off;                              // r per pixel (written by pass 1)
+  off = align256(off + (size_t)max_px * sizeof(double));
   if (opt->save_for_backward) {
     const size_t K1 = (size_t)opt->n_iter + 1;
     p->off_ck_alpha = off;

@@ -1,6 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
 same seeded scenes.  Sizes span several work items per column and ragged
-tails; the full-size flightline is checked on sampled columns."""
+tails; the full-size flightline is checked on every pixel (default form) and
+on sampled columns (every form)."""
 import numpy as np
 import pytest
 
@@ -165,6 +166,18 @@ def flightline_sample(flightline):
     ref, _ = oracle_retrieve(flightline.radiance, flightline.s, 30, config_lambda("flightline"),
                              columns=cols, workers=6)
     return cols, ref
+
+
+def test_full_flightline_every_pixel(flightline):
+    """The default form on the whole 598 x 8000 x 74 flightline, 30
+    iterations, in the benchmark's launch configuration: every one of the
+    4.78 M pixels against the oracle run on every column."""
+    lam = config_lambda("flightline")
+    a, st = _gpu(flightline, n_iter=30, lam=lam)
+    ref, rst = oracle_retrieve(flightline.radiance, flightline.s, 30, lam, workers=16)
+    np.testing.assert_array_equal(st, rst)
+    rep = assert_fp32_parity(a, ref, label="flightline, every pixel, default form")
+    assert rep["flips_over_nonzero"] == 0.0
 
 
 @pytest.mark.parametrize("cov", FORMS)

@@ -108,7 +108,14 @@ def log(*a):
 
 
 def source_digest():
-    return hashlib.sha256(open(SOURCE, "rb").read()).hexdigest()[:16]
+    """sha256 prefix of the library's sources (mf.hip and its included parts)."""
+    d = os.path.dirname(SOURCE)
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".inc")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def main():

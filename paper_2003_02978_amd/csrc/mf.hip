@@ -738,33 +738,64 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
   ca.B = B;
   ca.refine = refine_steps_of(p->opt);
   ca.albedo = p->opt.albedo;
-  const size_t lds = bwd_lds_bytes(B), ldsA = bwdA_lds_bytes(B);
-  for (int k = K; k >= 0; --k) {
-    ba.k = ca.k = k;
-    ba.ck_k = ca.ck_k = ck_col + (int64_t)k * p->n_cols * kCk;
-    ca.ck_km1 = k >= 1 ? ck_col + (int64_t)(k - 1) * p->n_cols * kCk : nullptr;
+  const size_t lds = bwd_lds_bytes<false>(B), ldsF = bwd_lds_bytes<true>(B), ldsA = bwdA_lds_bytes(B);
+  // per-iteration pointers of the pass arguments (k = iteration of pass B)
+  auto set_iter = [&](int k) {
+    ba.k = k;
+    ba.ck_k = ck_col + (int64_t)k * p->n_cols * kCk;
+    ba.ck_km1 = k >= 1 ? ck_col + (int64_t)(k - 1) * p->n_cols * kCk : nullptr;
     ba.a_k = ck_alpha + (int64_t)k * mp;
     ba.a_km1 = k >= 1 ? ck_alpha + (int64_t)(k - 1) * mp : nullptr;
+    ba.a_km2 = k >= 2 ? ck_alpha + (int64_t)(k - 2) * mp : nullptr;
     ba.p_k = ck_p + (int64_t)k * mp;
+    ba.p_km1 = k >= 1 ? ck_p + (int64_t)(k - 1) * mp : nullptr;
     ba.coef_v = coef + (int64_t)(2 * k) * mp;
     ba.coef_u = coef + (int64_t)(2 * k + 1) * mp;
-    ba.u_k = ca.u_k = u_hist + (int64_t)k * p->n_cols * kPad;
+    ba.u_k = u_hist + (int64_t)k * p->n_cols * kPad;
+  };
+  auto set_col = [&](int k, int fused) {
+    ca.k = k;
+    ca.fused = fused;
+    ca.ck_k = ck_col + (int64_t)k * p->n_cols * kCk;
+    ca.ck_km1 = k >= 1 ? ck_col + (int64_t)(k - 1) * p->n_cols * kCk : nullptr;
+    ca.u_k = u_hist + (int64_t)k * p->n_cols * kPad;
+    ca.ck_b = fused ? ck_col + (int64_t)(k + 1) * p->n_cols * kCk : nullptr;
+    ca.u_b = fused ? u_hist + (int64_t)(k + 1) * p->n_cols * kPad : nullptr;
+  };
+  // pass A(K) and its column step, then per iteration k = K..1 one fused pass
+  // B(k) + A(k-1) followed by one column kernel (col B(k), then col A(k-1)),
+  // then pass B(0) and col B(0)
+  set_iter(K);
+  {
+    LaunchTimer tm(p, MF_KERNEL_PASS_VEC, st);
+    hipLaunchKernelGGL(bwd_passA_kernel, dim3((unsigned)p->n_items), dim3(kABlock), ldsA, st, ba);
+  }
+  set_col(K, 0);
+  {
+    LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
+    hipLaunchKernelGGL(bwd_colA_kernel, dim3((unsigned)p->n_cols), dim3(kBlock), 0, st, ca);
+  }
+  for (int k = K; k >= 1; --k) {
+    set_iter(k);
     {
       LaunchTimer tm(p, MF_KERNEL_PASS_VEC, st);
-      hipLaunchKernelGGL(bwd_passA_kernel, dim3((unsigned)p->n_items), dim3(kABlock), ldsA, st, ba);
+      hipLaunchKernelGGL(bwd_passB_kernel<true>, dim3((unsigned)p->n_items), dim3(kSBlock), ldsF, st, ba);
     }
+    set_col(k - 1, 1);
     {
       LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
       hipLaunchKernelGGL(bwd_colA_kernel, dim3((unsigned)p->n_cols), dim3(kBlock), 0, st, ca);
     }
-    {
-      LaunchTimer tm(p, MF_KERNEL_PASS_VEC, st);
-      hipLaunchKernelGGL(bwd_passB_kernel, dim3((unsigned)p->n_items), dim3(kSBlock), lds, st, ba);
-    }
-    {
-      LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
-      hipLaunchKernelGGL(bwd_colB_kernel, dim3((unsigned)p->n_cols), dim3(128), 0, st, ca);
-    }
+  }
+  set_iter(0);
+  {
+    LaunchTimer tm(p, MF_KERNEL_PASS_VEC, st);
+    hipLaunchKernelGGL(bwd_passB_kernel<false>, dim3((unsigned)p->n_items), dim3(kSBlock), lds, st, ba);
+  }
+  set_col(0, 0);
+  {
+    LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
+    hipLaunchKernelGGL(bwd_colB_kernel, dim3((unsigned)p->n_cols), dim3(128), 0, st, ca);
   }
   BwAsmArgs aa{};
   aa.items = p->items_d;

@@ -6,7 +6,7 @@ one whole retrieval (every pass of the hot path) of the flightline, with the
 radiance already resident in HBM.
 
 Prints ONE JSON line (rank 0).  Usage:
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms lowrank,fp64,fp32,bf16]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms lowrank,fp64,fp32,bf16,bf16x3]
                     [--no-cpu-baseline]
 """
 import argparse
@@ -25,13 +25,16 @@ HBM_PEAK_GBS = 8000.0
 # are FP64 in every form; the Gram forms accumulate their covariance on
 # FP64, FP32 or BF16 MFMA (the radiance input is FP32 throughout)
 FORM_DTYPE = {"lowrank": "f64", "fp64": "f64", "fp32": "f32 Gram, f64 scores and solves",
-              "bf16": "bf16 Gram (f32 accumulate), f64 scores and solves"}
+              "bf16": "bf16 Gram (f32 accumulate), f64 scores and solves",
+              "bf16x3": "split bf16 Gram (hi hi' + hi lo' + lo hi', f32 accumulate), f64 scores and solves"}
 FORM_LABEL = {"lowrank": "exact rank-3 covariance update (C^0 from one FP64 Gram; the low-rank variant)",
               "fp64": "per-iteration Gram on FP64 MFMA",
               "fp32": "plain FP32 form: per-iteration Gram on FP32 MFMA, FP64 Cholesky, refinement "
                       "against the exact C^k",
               "bf16": "precision form: per-iteration Gram on BF16 MFMA (FP32 accumulate), FP64 "
-                      "Cholesky, refinement against the exact C^k"}
+                      "Cholesky, refinement against the exact C^k",
+              "bf16x3": "precision form, split BF16: per-iteration Gram on BF16 MFMA of hi + lo operands "
+                        "(three products, FP32 accumulate), FP64 Cholesky, refinement against the exact C^k"}
 # Algorithmic bytes per pixel of the method: every pass reads the B-band FP32
 # spectrum once; alpha moves as FP32, written by pass 1 (alpha^0) and read and
 # written by every later scored pass (alpha^{j-2} in, alpha^{j-1} out).  The
@@ -61,7 +64,9 @@ def gram_tile_flops_per_px(B=74):
 
 # MI355X peaks: HBM 8 TB/s; dense MFMA FP32 157.3 TFLOP/s, BF16 2.5 PFLOP/s,
 # FP64 78.6 TFLOP/s
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
+# MFMA products per tile and step (the split BF16 form adds two cross terms)
+TILE_PRODUCTS = {"bf16x3": 3}
 
 
 def compare(gpu, ref, iterative=True):
@@ -123,7 +128,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--forms", default="lowrank,fp64,fp32,bf16,bf16@1",
+    ap.add_argument("--forms", default="lowrank,fp64,fp32,bf16,bf16x3,bf16@1",
                     help="covariance forms; form@n runs it with n refinement steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-lines", type=int, default=8000)
@@ -242,7 +247,8 @@ def main():
         res["dominant_GBps"] = res["dominant_bytes_per_px"] * n_px / (avg_ms * 1e-3) / 1e9
         if form != "lowrank":
             res["gram_TFLOPs_algorithmic"] = gram_flops_per_px(B) * n_px / (avg_ms * 1e-3) / 1e12
-            res["gram_TFLOPs_tiles"] = gram_tile_flops_per_px(B) * n_px / (avg_ms * 1e-3) / 1e12
+            res["gram_TFLOPs_tiles"] = (TILE_PRODUCTS.get(form, 1) * gram_tile_flops_per_px(B) * n_px /
+                                        (avg_ms * 1e-3) / 1e12)
             res["gram_frac_of_mfma_peak_tiles"] = res["gram_TFLOPs_tiles"] / PEAK_TFLOPS[form]
         results[label] = res
         log(f"{label}: {res['px_per_s'] / 1e6:.1f} Mpx/s, {res['ms_per_step']:.3f} ms/step, "
@@ -429,7 +435,7 @@ def main():
                          if "gram_TFLOPs_tiles" in r else {}),
                       "error_vs_fp64": errors.get(f)} for f, r in results.items()},
     }
-    for f in ("fp32", "bf16"):
+    for f in ("fp32", "bf16", "bf16x3"):
         if f in results:
             out[f"{f}_px_per_s"] = round(results[f]["px_per_s"], 1)
     out["grouped"] = grouped
@@ -439,6 +445,8 @@ def main():
     out["batch"] = batch
     if "bf16" in results and "fp32" in results:
         out["bf16_vs_fp32_gram_speedup"] = round(results["bf16"]["px_per_s"] / results["fp32"]["px_per_s"], 3)
+    if "bf16x3" in results and "fp32" in results:
+        out["bf16x3_vs_fp32_gram_speedup"] = round(results["bf16x3"]["px_per_s"] / results["fp32"]["px_per_s"], 3)
     print(json.dumps(out), flush=True)
 
 

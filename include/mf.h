@@ -85,12 +85,17 @@ typedef enum {
                             paper's canonical formulas, Sec. II-E), FP64 MFMA */
   MF_COV_GRAM_FP32 = 2,  /* ... on FP32 MFMA (FP32 accumulation per wave,
                             FP64 across waves and work items) */
-  MF_COV_GRAM_BF16 = 3   /* ... with BF16 operands on MFMA (FP32 accumulate).
-                            In both rounded forms the FP64 Cholesky factor of
-                            the rounded C^k preconditions iterative refinement
-                            whose residual t - C^k v takes C^k exactly (C^0
-                            from the FP64 Gram of the first pass plus the
-                            rank-3 update from FP64 moments of the same pass) */
+  MF_COV_GRAM_BF16 = 3,  /* ... with BF16 operands on MFMA (FP32 accumulate) */
+  MF_COV_GRAM_BF16X3 = 4 /* ... with split BF16 operands: each residual is
+                            hi + lo (both BF16, lo the rounded remainder) and
+                            the Gram adds hi hi' + hi lo' + lo hi' on the same
+                            MFMA (FP32 accumulate).
+                            In the three rounded forms the FP64 Cholesky factor
+                            of the rounded C^k preconditions iterative
+                            refinement whose residual t - C^k v takes C^k
+                            exactly (C^0 from the FP64 Gram of the first pass
+                            plus the rank-3 update from FP64 moments of the
+                            same pass) */
 } mf_cov;
 
 typedef struct {
@@ -106,8 +111,9 @@ typedef struct {
   int32_t  cov;           /* mf_cov */
   int32_t  refine_steps;  /* iterative-refinement steps of C^-1 t, 0..8, or -1
                              for the form's default: 1 for the exact forms, 3
-                             for MF_COV_GRAM_FP32, 5 for MF_COV_GRAM_BF16 (the
-                             steps that take the rounded forms to FP64 rounding) */
+                             for MF_COV_GRAM_FP32, 5 for MF_COV_GRAM_BF16, 4 for
+                             MF_COV_GRAM_BF16X3 (the steps that take the
+                             rounded forms to FP64 rounding) */
   int32_t  save_for_backward; /* 1: mf_retrieve keeps alpha^0..alpha^K and the
                              per-iteration column state for mf_backward (needs
                              MF_COV_LOWRANK and n_iter <= 30; larger workspace) */

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libmf.so")
 
 MF_OK, MF_E_ARG, MF_E_SHAPE, MF_E_UNSUPPORTED, MF_E_DEVICE, MF_E_STATE = range(6)
 MF_COL_OK, MF_COL_FEW_PIXELS, MF_COL_NOT_SPD, MF_COL_NONFINITE = range(4)
-COV = {"lowrank": 0, "fp64": 1, "fp32": 2, "bf16": 3}
+COV = {"lowrank": 0, "fp64": 1, "fp32": 2, "bf16": 3, "bf16x3": 4}
 
 # Every symbol declared in include/mf.h.
 EXPORTS = ("mf_abi_version", "mf_options_default", "mf_status_str", "mf_last_error",

@@ -13,7 +13,7 @@
 // The last pass writes alpha^K to the caller's buffer and computes no moments.
 //
 // Covariance forms (mf_cov), all exact algebra for C^j of Eq. 11:
-//  * per-iteration Gram (GRAM_FP64 / GRAM_FP32 / GRAM_BF16).  With d_i the
+//  * per-iteration Gram (GRAM_FP64 / GRAM_FP32 / GRAM_BF16 / GRAM_BF16X3).  With d_i the
 //    residual of Eq. 11 and y_i = L_i - mu_used - c_i t_used as the pass
 //    computed it (mu_used, t_used = the FP32 values it subtracted),
 //      d_i = y_i + D + c_i e,   D = mu_used - mu^j,   e = t_used - t^j,
@@ -212,9 +212,13 @@ void launch_pass_nb(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t
       if (rin) hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F32, true, true>), g, b, 0, s, a);
       else hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_F32, true, false>), g, b, 0, s, a);
       break;
-    default:
+    case PM_BF16:
       if (rin) hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16, true, true>), g, b, 0, s, a);
       else hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16, true, false>), g, b, 0, s, a);
+      break;
+    default:
+      if (rin) hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16X3, true, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((pass_kernel<NB, WIDE, PM_BF16X3, true, false>), g, b, 0, s, a);
       break;
   }
 }
@@ -255,11 +259,17 @@ void dispatch_solve(const mf_plan_s* p, const SolveArgs& a, hipStream_t s) {
   }
 }
 
+// The Gram forms with rounded operands (FP32, BF16, split BF16): their solve
+// refines against the exact C^j from FP64 moments kept beside the Gram.
+bool rounded_form(int cov) {
+  return cov == MF_COV_GRAM_FP32 || cov == MF_COV_GRAM_BF16 || cov == MF_COV_GRAM_BF16X3;
+}
+
 // Doubles per work item in the partial buffer: the item's partial Gram (T
 // tiles of 16 x 16; the low-rank form's vector moments fit in it), plus the
 // exact moments of the rounded Gram forms.
 int64_t partial_stride(const mf_plan_s* p) {
-  const bool rounded = p->opt.cov == MF_COV_GRAM_FP32 || p->opt.cov == MF_COV_GRAM_BF16;
+  const bool rounded = rounded_form(p->opt.cov);
   return (int64_t)n_tiles(p->nb) * 256 + (rounded ? kXMomSlots : 0);
 }
 
@@ -271,6 +281,7 @@ int refine_steps_of(const mf_options& o) {
   switch (o.cov) {
     case MF_COV_GRAM_FP32: return 3;
     case MF_COV_GRAM_BF16: return 5;
+    case MF_COV_GRAM_BF16X3: return 4;
     default: return 1;
   }
 }
@@ -283,6 +294,7 @@ int pass_mode(int cov, int j, int K) {
   switch (cov) {
     case MF_COV_GRAM_FP32: return j == 0 ? PM_F64 : PM_F32;
     case MF_COV_GRAM_BF16: return j == 0 ? PM_F64 : PM_BF16;
+    case MF_COV_GRAM_BF16X3: return j == 0 ? PM_F64 : PM_BF16X3;
     case MF_COV_GRAM_FP64: return PM_F64;
     default: return j == 0 ? PM_F64 : PM_VEC;   // MF_COV_LOWRANK
   }
@@ -334,7 +346,7 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   sa.B = B;
   sa.refine = refine_steps_of(p->opt);
   sa.lowrank = p->opt.cov == MF_COV_LOWRANK;
-  sa.exact_ref = p->opt.cov == MF_COV_GRAM_FP32 || p->opt.cov == MF_COV_GRAM_BF16;
+  sa.exact_ref = rounded_form(p->opt.cov);
   sa.ck = p->opt.save_for_backward ? (double*)(ws + p->off_ck_col) : nullptr;
   sa.n_cols = (int)p->n_cols;
   sa.energy = energy;
@@ -440,7 +452,7 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   if (!(opt->epsilon > 0.0) || !std::isfinite(opt->epsilon))
     return fail_with(MF_E_ARG, "epsilon must be finite and > 0");
   if (opt->albedo != 0 && opt->albedo != 1) return fail_with(MF_E_ARG, "albedo must be 0 or 1");
-  if (opt->cov < MF_COV_LOWRANK || opt->cov > MF_COV_GRAM_BF16)
+  if (opt->cov < MF_COV_LOWRANK || opt->cov > MF_COV_GRAM_BF16X3)
     return fail_with(MF_E_ARG, "cov must be one of MF_COV_*");
   if (opt->refine_steps < -1 || opt->refine_steps > 8)
     return fail_with(MF_E_ARG, "refine_steps must be -1 (the form's default) or in [0, 8]");

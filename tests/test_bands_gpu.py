@@ -39,7 +39,7 @@ def test_band_counts_match_oracle(B, cov):
     assert_fp32_parity(a.cpu().numpy(), ref, label=f"B={B} cov={cov}")
 
 
-@pytest.mark.parametrize("cov", ["fp32", "bf16"])
+@pytest.mark.parametrize("cov", ["fp32", "bf16", "bf16x3"])
 @pytest.mark.parametrize("B", BANDS)
 def test_band_counts_rounded_gram_forms(B, cov):
     """The rounded Gram forms at every register layout: refined against the

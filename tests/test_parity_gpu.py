@@ -34,7 +34,7 @@ def tiny():
 EXACT = ["lowrank", "fp64"]    # forms whose covariance is accumulated exactly
 # every form: the rounded Gram forms (FP32 and BF16 MFMA) refine against the
 # exact C^k and are held to the same FP32 bar
-FORMS = EXACT + ["fp32", "bf16"]
+FORMS = EXACT + ["fp32", "bf16", "bf16x3"]
 
 
 @pytest.mark.parametrize("cov", FORMS)
@@ -121,13 +121,13 @@ def test_degenerate_columns_get_status_and_zero(cov):
     assert_fp32_parity(a[2:3], ref[2:3], label=f"degenerate, healthy column, cov={cov}")
 
 
-@pytest.mark.parametrize("cov", ["fp32", "bf16"])
+@pytest.mark.parametrize("cov", ["fp32", "bf16", "bf16x3"])
 def test_rounded_forms_refinement_converges(tiny, cov):
     """The rounded Gram forms refine against the exact C^k: the error against
     the oracle after one step is larger than after the form's default steps,
     which meet the FP32 bar (the step counts are the ones whose contraction,
-    about 1e-3 per step for the FP32 Gram and 2e-2 for BF16, reaches FP64
-    rounding)."""
+    about 1e-3 per step for the FP32 Gram, 2e-2 for BF16 and 1e-2 for split
+    BF16, reaches FP64 rounding)."""
     lam = config_lambda("tiny")
     ref, _ = oracle_retrieve(tiny.radiance, tiny.s, 30, lam, workers=8)
     a1, _ = _gpu(tiny, n_iter=30, lam=lam, cov=cov, refine_steps=1)

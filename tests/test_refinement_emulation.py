@@ -1,10 +1,12 @@
 """Host emulation of the rounded Gram forms' solve (no GPU): the covariance of
-iteration k accumulated from FP32- or BF16-rounded residuals in FP32 per
-block (as the FP32 and BF16 MFMA passes do), factored in FP64, used only to
-precondition iterative refinement whose residual takes the exact C^k.  The
-error of v = C^-1 t contracts by about 1e-3 (FP32) and 2e-2 (BF16) per step
-and falls below 1e-10 (FP32) and 1e-9 (BF16) relative in the library's
-default step counts (3 and 5; FP64 rounding is about 1e-12 here),
+iteration k accumulated from FP32-, BF16- or split-BF16-rounded residuals in
+FP32 per block (as the FP32 and BF16 MFMA passes do; split BF16 takes
+hi hi' + hi lo' + lo hi' with hi = bf16(y), lo = bf16(y - hi)), factored in
+FP64, used only to precondition iterative refinement whose residual takes the
+exact C^k.  The error of v = C^-1 t contracts by about 1e-3 (FP32), 2e-2
+(BF16) and 1e-2 (split BF16) per step and falls below 1e-10 (FP32) and 1e-9
+(BF16, split BF16) relative in the library's default step counts (3, 5 and 4;
+FP64 rounding is about 1e-12 here),
 while a refinement against the rounded matrix itself keeps the Gram's
 rounding error.  The exact C^k, t^k and alpha^{k-1} come from the oracle's
 trace of one column of the flightline workload."""
@@ -36,7 +38,8 @@ def column_trace():
 
 
 @pytest.mark.parametrize("form,block,steps,rho_max,v_tol", [("fp32", 1024, 3, 5e-3, 1e-10),
-                                                            ("bf16", 1024, 5, 5e-2, 1e-9)])
+                                                            ("bf16", 1024, 5, 5e-2, 1e-9),
+                                                            ("bf16x3", 1024, 4, 3e-2, 1e-9)])
 def test_exact_residual_refinement_converges(column_trace, form, block, steps, rho_max, v_tol):
     L, trace = column_trace
     N, B = L.shape
@@ -52,7 +55,12 @@ def test_exact_residual_refinement_converges(column_trace, form, block, steps, r
         G = np.zeros((B + 2, B + 2))
         for b0 in range(0, N, block):                        # FP32 sums per block, FP64 across
             Yb = Y[b0:b0 + block].astype(np.float32)
-            G += (Yb.T @ Yb).astype(np.float64)
+            if form == "bf16x3":
+                hi = _bf16(Yb)
+                lo = _bf16(Yb - hi)
+                G += (hi.T @ hi + hi.T @ lo + lo.T @ hi).astype(np.float64)
+            else:
+                G += (Yb.T @ Yb).astype(np.float64)
         # the shifted-Gram assembly of C about mu^k (the solve's formula)
         D = prev.mu.astype(np.float32).astype(np.float64) - it.mu
         E = prev.t.astype(np.float32).astype(np.float64) - it.t

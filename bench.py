@@ -130,6 +130,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default="lowrank,fp64,fp32,bf16,bf16x3,bf16@1",
                     help="covariance forms; form@n runs it with n refinement steps")
+    ap.add_argument("--streams", default="1,2,3,4",
+                    help="concurrent partition groups per retrieval: one count, or candidates "
+                         "of which each form takes the fastest (mf_plan_set_streams)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-lines", type=int, default=8000)
     ap.add_argument("--save-alpha", default="", help="save each form's alpha as <path>_<form>.npy")
@@ -194,6 +197,7 @@ def main():
     log(f"stream read ceiling: {ceiling_GBps:.0f} GB/s ({ceiling_blocks} blocks); all {ceil}")
 
     forms = [f for f in args.forms.split(",") if f]
+    stream_candidates = [min(int(x), S) for x in args.streams.split(",") if x]
     head = forms[0]
     results = {}
     outputs = {}
@@ -206,6 +210,20 @@ def main():
             plan.retrieve(L, s, alpha, None, status, ws)
         torch.cuda.synchronize()
         steps = args.steps if form == head else max(3, args.steps // 4)
+        # concurrent partition groups: the fastest candidate (a launch choice;
+        # every count gives the same alpha bit for bit)
+        stream_ms = {}
+        for ns in stream_candidates:
+            plan.set_streams(ns)
+            plan.retrieve(L, s, alpha, None, status, ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                plan.retrieve(L, s, alpha, None, status, ws)
+            torch.cuda.synchronize()
+            stream_ms[ns] = 1e3 * (time.perf_counter() - t0) / 3
+        n_streams = min(stream_ms, key=stream_ms.get)
+        plan.set_streams(n_streams)
         # timed region (no instrumentation)
         t1 = time.perf_counter()
         for _ in range(steps):
@@ -213,7 +231,9 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         # instrumented region: per-kernel durations from HIP events recorded on
-        # the stream the kernels run on
+        # the stream the kernels run on, with one partition group, so that each
+        # launch has the GPU to itself (its duration is the kernel's own)
+        plan.set_streams(1)
         plan.set_timing(True)
         plan.kernel_times()
         t2 = time.perf_counter()
@@ -230,6 +250,8 @@ def main():
         res = {
             "px_per_s": n_px * steps / dt,
             "ms_per_step": 1e3 * dt / steps,
+            "streams": n_streams,
+            "ms_per_step_by_streams": {str(k): round(v, 3) for k, v in stream_ms.items()},
             "ms_per_step_instrumented": 1e3 * dt_ins / steps,
             "steps": steps,
             "columns_failed": int((st != 0).sum()),
@@ -251,8 +273,9 @@ def main():
                                         (avg_ms * 1e-3) / 1e12)
             res["gram_frac_of_mfma_peak_tiles"] = res["gram_TFLOPs_tiles"] / PEAK_TFLOPS[form]
         results[label] = res
-        log(f"{label}: {res['px_per_s'] / 1e6:.1f} Mpx/s, {res['ms_per_step']:.3f} ms/step, "
-            f"{dom} {avg_ms * 1e3:.1f} us = {res['dominant_GBps']:.0f} GB/s, kernels {res['kernels_ms_per_step']}")
+        log(f"{label}: {res['px_per_s'] / 1e6:.1f} Mpx/s, {res['ms_per_step']:.3f} ms/step with {n_streams} "
+            f"stream(s) {res['ms_per_step_by_streams']}, {dom} {avg_ms * 1e3:.1f} us = "
+            f"{res['dominant_GBps']:.0f} GB/s, kernels {res['kernels_ms_per_step']}")
         plan.close()
         del ws
 
@@ -415,7 +438,8 @@ def main():
         "config": {"workload": f"flightline {S}x{N}x{B}, {K} iterations, lambda {lam:.4g}, "
                                f"covariance form '{head}'",
                    "columns": S, "lines": N, "bands": B, "iterations": K,
-                   "covariance": head, "radiance": "f32", "parallelism": "single GPU"},
+                   "covariance": head, "radiance": "f32", "parallelism": "single GPU",
+                   "streams": results[head]["streams"]},
         "headline_form": FORM_LABEL.get(results[head]["form"], head),
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -423,6 +447,7 @@ def main():
         "forms": {f: {"dtype": FORM_DTYPE[r["form"]], "label": FORM_LABEL[r["form"]],
                       "refine_steps": r["refine_steps"],
                       "px_per_s": round(r["px_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                      "streams": r["streams"], "ms_per_step_by_streams": r["ms_per_step_by_streams"],
                       "hbm_fraction_whole_job": round(job_bytes_per_px(K, B) * n_px /
                                                       (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                       "kernels_ms_per_step": r["kernels_ms_per_step"],
@@ -636,11 +661,12 @@ def run_batch(mf, torch, np, dev, K, lam, eps, steps, warmup):
     with torch.cuda.stream(side):
         t_tune = time.perf_counter()
         best, tune = mf.autotune(fls, dL, ds, dV, chunks=(1024, 2048, 4096),
-                                 tiles=("32x4", "32x2", "64x2"), wgs=(0, 2, 3, 4), reps=2,
-                                 n_bands=B, n_iter=K, lam=lam, eps=eps)
+                                 tiles=("32x4", "32x2", "64x2"), wgs=(0, 2, 3, 4), streams=(1, 2, 3, 4),
+                                 reps=2, n_bands=B, n_iter=K, lam=lam, eps=eps)
         tune_s = time.perf_counter() - t_tune
         plan = mf.Plan(fls, B, K, lam, eps, True, "lowrank", chunk_lines=best["chunk_lines"])
         plan.set_launch(best["stream_tile"], best["wgs_per_cu"])
+        plan.set_streams(best["streams"])
         plan.set_graph(True)
         ws = plan.alloc_workspace(dev)
         alpha = torch.empty((total,), dtype=torch.float32, device=dev)

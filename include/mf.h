@@ -258,6 +258,31 @@ enum {
 };
 MF_API mf_status mf_plan_set_launch(mf_plan plan, int32_t stream_tile, int32_t wgs_per_cu);
 
+/* Concurrent partition groups (a tuning choice: every setting gives the same
+   result, bit for bit).  The partitions are independent problems (Sec. II-E),
+   so mf_retrieve splits the plan's partitions into n_streams contiguous
+   groups of about equal pixel counts and runs each group's launch sequence
+   on its own stream: group 0 on the caller's stream, the others on streams
+   the plan owns (default priority), forked from the caller's stream by an
+   event at the start and joined back into it before the call's last launch.
+   The call therefore still orders like one launch sequence on the caller's
+   stream.  While one group's streaming pass drains or its latency-bound
+   solves run, another group's pass keeps the GPU busy.
+     n_streams   1 (the default) .. MF_MAX_STREAMS, at most the plan's
+                 partitions
+   Call it with the plan's device current: it creates the streams and events
+   on first use (mf_retrieve and mf_retrieve_noalloc only record and wait on
+   them).  Graph capture follows the fork and join; a graph captured with the
+   previous setting is dropped.  With persistent launches (wgs_per_cu > 0)
+   each group takes its work items in plan order from its own counters.
+   mf_backward runs on the caller's stream alone.  Two calls on one plan that
+   overlap in time race on these streams, as they would on the workspace. */
+#define MF_MAX_STREAMS 8
+MF_API mf_status mf_plan_set_streams(mf_plan plan, int32_t n_streams);
+
+/* The plan's current n_streams. */
+MF_API int32_t mf_plan_streams(mf_plan plan);
+
 /* Kernel timing for benchmarks.  While enabled, mf_retrieve brackets each of
    its kernel launches with HIP events on the caller's stream (a few
    microseconds of extra stream work per launch). */

@@ -23,9 +23,11 @@ EXPORTS = ("mf_abi_version", "mf_options_default", "mf_status_str", "mf_last_err
            "mf_plan_create", "mf_workspace_bytes", "mf_plan_columns", "mf_plan_pixels",
            "mf_retrieve", "mf_backward", "mf_plan_set_graph", "mf_plan_set_timing",
            "mf_plan_kernel_times", "mf_plan_energy", "mf_repack_bil", "mf_stream_read",
-           "mf_retrieve_noalloc", "mf_plan_refine_steps", "mf_plan_set_launch", "mf_plan_destroy")
+           "mf_retrieve_noalloc", "mf_plan_refine_steps", "mf_plan_set_launch", "mf_plan_set_streams",
+           "mf_plan_streams", "mf_plan_destroy")
 TILES = {"32x4": 0, "32x2": 1, "64x2": 2, "64x1": 3}   # MF_TILE_*: pixels per wave chunk x waves
 NOALLOC_SCRATCH_BYTES = 64 << 20   # MF_NOALLOC_SCRATCH_BYTES
+MAX_STREAMS = 8                    # MF_MAX_STREAMS
 KERNEL_KINDS = ("pass_gram", "pass_vec", "pass_last", "solve", "other", "pass_init")
 ABI_VERSION = 4          # MF_ABI_VERSION of include/mf.h (mf_options layout)
 
@@ -89,6 +91,10 @@ def load_library(path: str = LIB_PATH):
     lib.mf_plan_set_graph.argtypes = [vp, ctypes.c_int]
     lib.mf_plan_set_launch.restype = ctypes.c_int
     lib.mf_plan_set_launch.argtypes = [vp, i32, i32]
+    lib.mf_plan_set_streams.restype = ctypes.c_int
+    lib.mf_plan_set_streams.argtypes = [vp, i32]
+    lib.mf_plan_streams.restype = i32
+    lib.mf_plan_streams.argtypes = [vp]
     lib.mf_plan_set_timing.restype = ctypes.c_int
     lib.mf_plan_set_timing.argtypes = [vp, ctypes.c_int]
     lib.mf_plan_kernel_times.restype = ctypes.c_int
@@ -175,6 +181,15 @@ class Plan:
         t = TILES[stream_tile] if isinstance(stream_tile, str) else int(stream_tile)
         _check(self._lib.mf_plan_set_launch(self._h, t, int(wgs_per_cu)))
         self.stream_tile, self.wgs_per_cu = t, int(wgs_per_cu)
+
+    def set_streams(self, n: int = 1):
+        """Run the partitions in n groups, each on its own stream (see
+        mf_plan_set_streams); call with the plan's device current."""
+        _check(self._lib.mf_plan_set_streams(self._h, int(n)))
+
+    @property
+    def streams(self) -> int:
+        return int(self._lib.mf_plan_streams(self._h))
 
     def set_timing(self, enable: bool):
         _check(self._lib.mf_plan_set_timing(self._h, int(bool(enable))))
@@ -299,23 +314,24 @@ def autotune_chunk(flightlines, radiance, s, valid=None, candidates=(512, 1024, 
 
 
 def autotune(flightlines, radiance, s, valid=None, chunks=(512, 1024, 2048, 4096),
-             tiles=("32x4", "32x2", "64x2", "64x1"), wgs=(0, 1, 2, 3, 4), reps: int = 2,
-             cache_path: Optional[str] = None, **plan_kwargs):
+             tiles=("32x4", "32x2", "64x2", "64x1"), wgs=(0, 1, 2, 3, 4), streams=(1, 2, 3, 4),
+             reps: int = 2, cache_path: Optional[str] = None, **plan_kwargs):
     """Pick the launch configuration of a batch geometry by timing whole
     retrievals: the work-item length (chunk_lines), then the streaming tile
     shape (pixels per wave chunk x waves per workgroup), then the persistent
-    grid (workgroups per compute unit, 0 = one workgroup per work item), each
-    step at the best of the previous ones.  Every configuration gives the
-    same alpha bit for bit.  Results are cached in a JSON file keyed by the
-    geometry, options, candidates and device.  Returns (best, {config: ms})
-    with best = {"chunk_lines", "stream_tile", "wgs_per_cu"}."""
+    grid (workgroups per compute unit, 0 = one workgroup per work item), then
+    the number of concurrent partition groups (streams), each step at the best
+    of the previous ones.  Every configuration gives the same alpha bit for
+    bit.  Results are cached in a JSON file keyed by the geometry, options,
+    candidates and device.  Returns (best, {config: ms}) with best =
+    {"chunk_lines", "stream_tile", "wgs_per_cu", "streams"}."""
     import hashlib
     import json
     import time
     import torch
     fls = [tuple(int(v) for v in f) for f in flightlines]
     key_src = json.dumps([fls, sorted(plan_kwargs.items()), list(chunks), list(tiles), list(wgs),
-                          torch.cuda.get_device_name(radiance.device)], default=str)
+                          list(streams), torch.cuda.get_device_name(radiance.device)], default=str)
     key = hashlib.sha256(key_src.encode()).hexdigest()[:20]
     cache = {}
     if cache_path and os.path.exists(cache_path):
@@ -327,12 +343,13 @@ def autotune(flightlines, radiance, s, valid=None, chunks=(512, 1024, 2048, 4096
     alpha = torch.empty(max_px, dtype=torch.float32, device=radiance.device)
     times = {}
 
-    def timed(chunk, tile, w):
-        name = f"chunk={chunk},tile={tile},wgs_per_cu={w}"
+    def timed(chunk, tile, w, ns):
+        name = f"chunk={chunk},tile={tile},wgs_per_cu={w},streams={ns}"
         if name in times:
             return times[name]
         plan = Plan(fls, chunk_lines=int(chunk), **plan_kwargs)
         plan.set_launch(tile, w)
+        plan.set_streams(min(int(ns), plan.n_columns))
         ws = plan.alloc_workspace(radiance.device)
         plan.retrieve(radiance, s, alpha, valid, None, ws)
         torch.cuda.synchronize(radiance.device)
@@ -345,12 +362,14 @@ def autotune(flightlines, radiance, s, valid=None, chunks=(512, 1024, 2048, 4096
         del ws
         return times[name]
 
-    best = {"chunk_lines": int(chunks[0]), "stream_tile": tiles[0], "wgs_per_cu": int(wgs[0])}
-    for field, cands in (("chunk_lines", chunks), ("stream_tile", tiles), ("wgs_per_cu", wgs)):
+    best = {"chunk_lines": int(chunks[0]), "stream_tile": tiles[0], "wgs_per_cu": int(wgs[0]),
+            "streams": int(streams[0])}
+    for field, cands in (("chunk_lines", chunks), ("stream_tile", tiles), ("wgs_per_cu", wgs),
+                         ("streams", streams)):
         scores = {}
         for c in cands:
             cfg = dict(best, **{field: c})
-            scores[c] = timed(cfg["chunk_lines"], cfg["stream_tile"], cfg["wgs_per_cu"])
+            scores[c] = timed(cfg["chunk_lines"], cfg["stream_tile"], cfg["wgs_per_cu"], cfg["streams"])
         best[field] = min(scores, key=scores.get)
     if cache_path:
         cache[key] = {"best": best, "ms": times}
@@ -491,12 +510,14 @@ def _need(t, dtype, name):
 
 def retrieve(radiance, s, n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9,
              albedo: bool = True, cov: str = "lowrank", valid=None, refine_steps: int = -1,
-             chunk_lines: int = 0, group: int = 1, stream_tile="32x4", wgs_per_cu: int = 0):
+             chunk_lines: int = 0, group: int = 1, stream_tile="32x4", wgs_per_cu: int = 0,
+             streams: int = 1):
     """Retrieve alpha (ppm*m) for a [S, N, B] float32 radiance cube on the GPU.
 
     group > 1 pools `group` adjacent columns per partition (the last one takes
     the remainder); stream_tile and wgs_per_cu set the launch shape (see
-    Plan.set_launch).  Returns (alpha [S, N] float32, status int32 per
+    Plan.set_launch), streams the concurrent partition groups (see
+    Plan.set_streams).  Returns (alpha [S, N] float32, status int32 per
     partition [ceil(S / group)]), both on the GPU.
     """
     import torch
@@ -504,6 +525,7 @@ def retrieve(radiance, s, n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9,
     plan = Plan([(0, S, N)], B, n_iter, lam, eps, albedo, cov, refine_steps, chunk_lines,
                 group=group)
     plan.set_launch(stream_tile, wgs_per_cu)
+    plan.set_streams(min(int(streams), plan.n_columns))
     alpha = torch.empty((S, N), dtype=torch.float32, device=radiance.device)
     status = torch.empty((plan.n_columns,), dtype=torch.int32, device=radiance.device)
     plan.retrieve(radiance.contiguous(), s.contiguous(), alpha,

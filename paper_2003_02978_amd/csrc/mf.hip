@@ -137,7 +137,17 @@ struct mf_plan_s {
   int wgs_per_cu = 0;        // 0: one workgroup per work item; n: persistent grid
   int n_cu = 0;
   int32_t* order_d = nullptr; // work items, longest first (persistent launches)
-  size_t off_queue = 0;      // K + 2 queue counters
+  size_t off_queue = 0;      // K + 2 queue counters per column group
+  // column groups (mf_plan_set_streams): group g holds columns
+  // [grp_col[g], grp_col[g + 1]) and their work items [grp_item[g],
+  // grp_item[g + 1]); group 0 runs on the caller's stream, group g >= 1 on
+  // aux[g - 1], forked from and joined to the caller's stream by events
+  int n_groups = 1;
+  std::vector<int64_t> grp_col, grp_item;
+  std::vector<ColInfo> cols_h;          // host copy of the column table
+  hipStream_t aux[MF_MAX_STREAMS - 1] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[MF_MAX_STREAMS - 1] = {};
 };
 
 namespace {
@@ -180,8 +190,8 @@ struct LaunchTimer {
 // Grid of a pass: one workgroup per work item, or the persistent grid of
 // wgs_per_cu workgroups per compute unit (at most one per work item).
 unsigned pass_grid(const mf_plan_s* p, const PassArgs& a) {
-  if (!a.queue) return (unsigned)p->n_items;
-  return (unsigned)std::min<int64_t>(p->n_items, (int64_t)p->wgs_per_cu * p->n_cu);
+  if (!a.queue) return (unsigned)a.n_items;
+  return (unsigned)std::min<int64_t>(a.n_items, (int64_t)p->wgs_per_cu * p->n_cu);
 }
 
 template <int CHUNK, int SW>
@@ -199,7 +209,7 @@ void launch_stream(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t 
 
 template <int NB, bool WIDE>
 void launch_pass_nb(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t s) {
-  const dim3 g((unsigned)p->n_items), b(kBlock);
+  const dim3 g((unsigned)a.n_items), b(kBlock);
   const bool sc = a.j >= 1;
   const bool rin = a.r_in != nullptr;
   switch (mode) {
@@ -245,8 +255,8 @@ void dispatch_pass(const mf_plan_s* p, const PassArgs& a, int mode, hipStream_t 
   }
 }
 
-void dispatch_solve(const mf_plan_s* p, const SolveArgs& a, hipStream_t s) {
-  const dim3 g((unsigned)p->n_cols), b(kBlock);
+void dispatch_solve(const mf_plan_s* p, const SolveArgs& a, int64_t n_cols, hipStream_t s) {
+  const dim3 g((unsigned)n_cols), b(kBlock);
   switch (p->nb) {
     case 1: hipLaunchKernelGGL((solve_kernel<1, false>), g, b, 0, s, a); break;
     case 2: hipLaunchKernelGGL((solve_kernel<2, false>), g, b, 0, s, a); break;
@@ -304,7 +314,11 @@ int pass_mode(int cov, int j, int K) {
 }  // namespace
 
 namespace {
-// The launch sequence of one retrieval (also what a graph captures).
+// The launch sequence of one retrieval (also what a graph captures).  Each
+// column group runs its own sequence on its own stream; the groups share
+// nothing but the read-only inputs, so their launches interleave freely on
+// the GPU (one group's streaming pass fills the machine while another drains
+// or solves).
 void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid, const float* s,
                       float* alpha, int32_t* column_status, void* workspace, hipStream_t st) {
   char* ws = (char*)workspace;
@@ -315,14 +329,19 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   double* ck_p = p->opt.save_for_backward ? (double*)(ws + p->off_ck_p) : nullptr;
   const int B = p->opt.n_bands;
   const int K = p->opt.n_iter;
+  const int G = p->n_groups;
   double* energy = p->opt.track_energy ? (double*)(ws + p->off_energy) : nullptr;
   int* queue = p->wgs_per_cu > 0 ? (int*)(ws + p->off_queue) : nullptr;
-
-  {
-    LaunchTimer tm(p, MF_KERNEL_OTHER, st);
-    hipLaunchKernelGGL(setup_kernel, dim3((unsigned)p->n_cols), dim3(64), 0, st, radiance, valid,
-                       p->cols_d, state, B, energy, K + 1, p->n_cols, queue, K + 2);
+  hipStream_t gs[MF_MAX_STREAMS];
+  gs[0] = st;
+  if (G > 1) {
+    (void)hipEventRecord(p->fork_ev, st);
+    for (int g = 1; g < G; ++g) {
+      gs[g] = p->aux[g - 1];
+      (void)hipStreamWaitEvent(gs[g], p->fork_ev, 0);
+    }
   }
+
   PassArgs pa{};
   pa.L = radiance;
   pa.valid = valid;
@@ -335,6 +354,7 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   pa.eps = p->opt.epsilon;
   pa.n_floats = p->max_px * B;
   pa.partial_stride = (int)partial_stride(p);
+  pa.order = G == 1 ? p->order_d : nullptr;   // longest-first order over the whole plan
   SolveArgs sa{};
   sa.cols = p->cols_d;
   sa.state = state;
@@ -350,11 +370,18 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   sa.ck = p->opt.save_for_backward ? (double*)(ws + p->off_ck_col) : nullptr;
   sa.n_cols = (int)p->n_cols;
   sa.energy = energy;
-  pa.order = p->order_d;
-  pa.n_items = (int)p->n_items;
+  // a group's queue counters: K + 2 per group
+  auto group_queue = [&](int g) { return queue ? queue + (int64_t)g * (K + 2) : nullptr; };
+  for (int g = 0; g < G; ++g) {
+    const int64_t c0 = p->grp_col[g], nc = p->grp_col[g + 1] - c0;
+    LaunchTimer tm(p, MF_KERNEL_OTHER, gs[g]);
+    hipLaunchKernelGGL(setup_kernel, dim3((unsigned)nc), dim3(64), 0, gs[g], radiance, valid, p->cols_d,
+                       state, B, energy, K + 1, p->n_cols, group_queue(g), K + 2, (int)c0);
+  }
+  // pass j and solve j of every group before pass j + 1 of any, so that the
+  // groups start together
   for (int j = 0; j <= K + 1; ++j) {
     pa.j = j;
-    pa.queue = queue ? queue + j : nullptr;
     pa.track_energy = (energy && j >= 1) ? 1 : 0;
     pa.unclamped = (j == 1 && K == 0) ? 1 : 0;
     if (ck_alpha) {          // save_for_backward: keep alpha^0..alpha^K
@@ -372,21 +399,33 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
     pa.r_in = j >= 2 ? rbuf : nullptr;
     const bool mom = j <= K;
     const int mode = pass_mode(p->opt.cov, j, K);
-    {
-      LaunchTimer tm(p, j == 0 ? MF_KERNEL_PASS_INIT
-                        : mode == PM_NONE ? MF_KERNEL_PASS_LAST
-                        : mode == PM_VEC ? MF_KERNEL_PASS_VEC : MF_KERNEL_PASS_GRAM, st);
-      dispatch_pass(p, pa, mode, st);
-    }
-    if (mom) {
-      sa.j = j;
-      LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
-      if (sa.lowrank && j >= 1)
-        hipLaunchKernelGGL(lowrank_kernel, dim3((unsigned)p->n_cols), dim3(kBlock), 0, st, sa);
-      else
-        dispatch_solve(p, sa, st);
+    sa.j = j;
+    for (int g = 0; g < G; ++g) {
+      pa.queue = queue ? group_queue(g) + j : nullptr;
+      pa.item_base = (int)p->grp_item[g];
+      pa.n_items = (int)(p->grp_item[g + 1] - p->grp_item[g]);
+      {
+        LaunchTimer tm(p, j == 0 ? MF_KERNEL_PASS_INIT
+                          : mode == PM_NONE ? MF_KERNEL_PASS_LAST
+                          : mode == PM_VEC ? MF_KERNEL_PASS_VEC : MF_KERNEL_PASS_GRAM, gs[g]);
+        dispatch_pass(p, pa, mode, gs[g]);
+      }
+      if (mom) {
+        sa.col_base = (int)p->grp_col[g];
+        const int64_t nc = p->grp_col[g + 1] - p->grp_col[g];
+        LaunchTimer tm(p, MF_KERNEL_SOLVE, gs[g]);
+        if (sa.lowrank && j >= 1)
+          hipLaunchKernelGGL(lowrank_kernel, dim3((unsigned)nc), dim3(kBlock), 0, gs[g], sa);
+        else
+          dispatch_solve(p, sa, nc, gs[g]);
+      }
     }
   }
+  if (G > 1)
+    for (int g = 1; g < G; ++g) {
+      (void)hipEventRecord(p->join_ev[g - 1], gs[g]);
+      (void)hipStreamWaitEvent(st, p->join_ev[g - 1], 0);
+    }
   if (energy) {
     LaunchTimer tm(p, MF_KERNEL_OTHER, st);
     hipLaunchKernelGGL(energy_last_kernel, dim3((unsigned)((p->n_cols + 255) / 256)), dim3(256), 0, st,
@@ -528,6 +567,9 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   p->n_items = (int64_t)items.size();
   p->n_px = n_px;
   p->max_px = max_px;
+  p->cols_h = cols;
+  p->grp_col = {0, p->n_cols};
+  p->grp_item = {0, p->n_items};
   if (hipGetDevice(&p->device) != hipSuccess ||
       hipMalloc(&p->cols_d, cols.size() * sizeof(ColInfo)) != hipSuccess ||
       hipMalloc(&p->items_d, items.size() * sizeof(WorkItem)) != hipSuccess ||
@@ -607,7 +649,7 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
     off = align256(off + ((size_t)opt->n_iter + 1) * (size_t)p->n_cols * sizeof(double));
   }
   p->off_queue = off;                          // persistent launches' queue counters
-  off = align256(off + ((size_t)opt->n_iter + 2) * sizeof(int));
+  off = align256(off + (size_t)MF_MAX_STREAMS * ((size_t)opt->n_iter + 2) * sizeof(int));
   p->ws_bytes = off;
   *out = p;
   g_last_error.clear();
@@ -913,6 +955,52 @@ mf_status mf_plan_set_launch(mf_plan p, int32_t stream_tile, int32_t wgs_per_cu)
   return MF_OK;
 }
 
+mf_status mf_plan_set_streams(mf_plan p, int32_t n_streams) {
+  if (!p) return fail_with(MF_E_ARG, "plan is NULL");
+  if (n_streams < 1 || n_streams > MF_MAX_STREAMS)
+    return fail_with(MF_E_ARG, "n_streams must be in [1, " + std::to_string(MF_MAX_STREAMS) + "]");
+  if (n_streams > p->n_cols) return fail_with(MF_E_ARG, "n_streams exceeds the plan's partitions");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail_with(MF_E_DEVICE, "current device differs from the plan's device");
+  if (n_streams > 1 && !p->fork_ev &&
+      hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming) != hipSuccess)
+    return fail_with(MF_E_DEVICE, "event creation failed");
+  for (int g = 1; g < n_streams; ++g) {
+    // default priority (streams of other priorities are not used here)
+    if (!p->aux[g - 1] && hipStreamCreateWithFlags(&p->aux[g - 1], hipStreamNonBlocking) != hipSuccess)
+      return fail_with(MF_E_DEVICE, "stream creation failed");
+    if (!p->join_ev[g - 1] && hipEventCreateWithFlags(&p->join_ev[g - 1], hipEventDisableTiming) != hipSuccess)
+      return fail_with(MF_E_DEVICE, "event creation failed");
+  }
+  // contiguous partition ranges of about equal pixel counts, each non-empty
+  std::vector<int64_t> gc(n_streams + 1, 0), gi(n_streams + 1, 0);
+  int64_t total = 0;
+  for (const ColInfo& c : p->cols_h) total += c.n_px;
+  int64_t acc = 0, c = 0;
+  for (int g = 1; g < n_streams; ++g) {
+    const int64_t target = total * g / n_streams;
+    while (c < p->n_cols - (n_streams - g) && (c < gc[g - 1] + 1 || acc + p->cols_h[c].n_px <= target))
+      acc += p->cols_h[c++].n_px;
+    gc[g] = c;
+  }
+  gc[n_streams] = p->n_cols;
+  for (int g = 0; g < n_streams; ++g) gi[g] = p->cols_h[gc[g]].first_item;
+  gi[n_streams] = p->n_items;
+  if (n_streams != p->n_groups || gc != p->grp_col) {
+    p->n_groups = n_streams;
+    p->grp_col = gc;
+    p->grp_item = gi;
+    if (p->graph_exec) {                       // the captured launches no longer apply
+      (void)hipGraphExecDestroy(p->graph_exec);
+      p->graph_exec = nullptr;
+    }
+  }
+  return MF_OK;
+}
+
+int32_t mf_plan_streams(mf_plan p) { return p ? p->n_groups : 0; }
+
 mf_status mf_plan_set_timing(mf_plan p, int enable) {
   if (!p) return fail_with(MF_E_ARG, "plan is NULL");
   p->timing = enable != 0;
@@ -962,6 +1050,11 @@ void mf_plan_destroy(mf_plan p) {
   }
   for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  for (int g = 0; g < MF_MAX_STREAMS - 1; ++g) {
+    if (p->aux[g]) (void)hipStreamDestroy(p->aux[g]);
+    if (p->join_ev[g]) (void)hipEventDestroy(p->join_ev[g]);
+  }
+  if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
   if (p->cols_d) (void)hipFree(p->cols_d);
   if (p->items_d) (void)hipFree(p->items_d);
   if (p->order_d) (void)hipFree(p->order_d);

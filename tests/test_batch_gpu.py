@@ -169,9 +169,9 @@ def test_persistent_graph_replays_match_eager():
 
 
 def test_launch_autotuner(tmp_path):
-    """The autotuner searches work-item length, tile shape and persistent
-    grid, returns candidates it timed, caches them, and its choice retrieves
-    the same alpha as the default launch."""
+    """The autotuner searches work-item length, tile shape, persistent grid
+    and concurrent partition groups, returns candidates it timed, caches
+    them, and its choice retrieves the same alpha as the default launch."""
     scenes, fls, L, V = _batch()
     Lt = torch.from_numpy(L).to(DEV)
     Vt = torch.from_numpy(V).to(DEV)
@@ -179,16 +179,17 @@ def test_launch_autotuner(tmp_path):
     cache = str(tmp_path / "tune.json")
     kw = dict(n_iter=5, lam=2.0)
     best, times = mf.autotune(fls, Lt, st, Vt, chunks=(256, 512), tiles=("32x4", "32x2", "64x2"),
-                              wgs=(0, 2), reps=1, cache_path=cache, **kw)
+                              wgs=(0, 2), streams=(1, 2), reps=1, cache_path=cache, **kw)
     assert best["chunk_lines"] in (256, 512) and best["stream_tile"] in ("32x4", "32x2", "64x2")
-    assert best["wgs_per_cu"] in (0, 2) and len(times) >= 4
+    assert best["wgs_per_cu"] in (0, 2) and best["streams"] in (1, 2) and len(times) >= 5
     best2, _ = mf.autotune(fls, Lt, st, Vt, chunks=(256, 512), tiles=("32x4", "32x2", "64x2"),
-                           wgs=(0, 2), reps=1, cache_path=cache, **kw)
+                           wgs=(0, 2), streams=(1, 2), reps=1, cache_path=cache, **kw)
     assert best2 == best
     outs = []
-    for cfg in ({"chunk_lines": 512, "stream_tile": "32x4", "wgs_per_cu": 0}, best):
+    for cfg in ({"chunk_lines": 512, "stream_tile": "32x4", "wgs_per_cu": 0, "streams": 1}, best):
         plan = mf.Plan(fls, 74, 5, 2.0, 1e-9, True, "lowrank", chunk_lines=cfg["chunk_lines"])
         plan.set_launch(cfg["stream_tile"], cfg["wgs_per_cu"])
+        plan.set_streams(cfg["streams"])
         a = torch.empty(L.shape[0], dtype=torch.float32, device=DEV)
         plan.retrieve(Lt, st, a, Vt)
         torch.cuda.synchronize()
@@ -201,3 +202,109 @@ def test_launch_autotuner(tmp_path):
     # the comparison is the FP32 bar against the default launch
     d = np.abs(outs[0][inplan] - outs[1][inplan])
     assert np.all(d <= 1e-4 * np.abs(outs[0][inplan]) + 0.1)
+
+
+@pytest.mark.parametrize("cov,n_streams,wgs", [("lowrank", 2, 0), ("lowrank", 3, 0), ("lowrank", 8, 0),
+                                               ("lowrank", 3, 2), ("fp64", 2, 0), ("bf16x3", 3, 0)])
+def test_streams_give_the_same_alpha(cov, n_streams, wgs):
+    """Partition groups on concurrent streams (mf_plan_set_streams) give the
+    one-stream alpha and statuses bit for bit on the ragged masked batch,
+    from 2 groups up to the most the library takes (8), with one workgroup per work
+    item or a persistent grid (each group on its own queue counters), for
+    the low-rank and Gram forms; the call stays ordered on the caller's
+    stream (read right after it without a device-wide synchronisation)."""
+    scenes, fls, L, V = _batch()
+    Lt = torch.from_numpy(L).to(DEV)
+    Vt = torch.from_numpy(V).to(DEV)
+    st = torch.from_numpy(scenes[0].s).to(DEV)
+    caller = torch.cuda.Stream()
+    outs = []
+    for ns in (1, n_streams):
+        plan = mf.Plan(fls, 74, 12, 3.0, 1e-9, True, cov, chunk_lines=256)
+        plan.set_launch("32x4", wgs)
+        plan.set_streams(ns)
+        assert plan.streams == ns
+        alpha = torch.full((L.shape[0],), -7.0, dtype=torch.float32, device=DEV)
+        status = torch.full((plan.n_columns,), -1, dtype=torch.int32, device=DEV)
+        ws = plan.alloc_workspace()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(caller):
+            for _ in range(2):                                  # the queue counters restart
+                plan.retrieve(Lt, st, alpha, Vt, status, ws, stream=caller)
+            a_host = alpha.to("cpu", non_blocking=False)         # ordered after the call on `caller`
+            s_host = status.to("cpu", non_blocking=False)
+        caller.synchronize()
+        outs.append((a_host.numpy(), s_host.numpy()))
+        plan.close()
+    np.testing.assert_array_equal(outs[1][1], outs[0][1])
+    np.testing.assert_array_equal(outs[1][0], outs[0][0])
+    assert np.all(outs[0][0][fls[0][1] * fls[0][2]:fls[1][0]] == -7.0)   # the gap is never written
+
+
+def test_streams_graph_replays_match_eager():
+    """A graph captured with three concurrent partition groups (the capture
+    follows the fork to the plan's streams and the join back): every replay,
+    with eager work in between, equals the one-stream eager result."""
+    scenes, fls, L, V = _batch()
+    Lt = torch.from_numpy(L).to(DEV)
+    Vt = torch.from_numpy(V).to(DEV)
+    st = torch.from_numpy(scenes[0].s).to(DEV)
+    plan = mf.Plan(fls, 74, 12, 2.0, 1e-9, True, "lowrank", chunk_lines=256)
+    ws = plan.alloc_workspace()
+    eager = torch.empty(L.shape[0], dtype=torch.float32, device=DEV)
+    plan.retrieve(Lt, st, eager, Vt, None, ws)
+    torch.cuda.synchronize()
+    inplan = np.zeros(L.shape[0], bool)
+    for o, S, N in fls:
+        inplan[o:o + S * N] = True
+    ref = eager.cpu().numpy()[inplan]
+    plan.set_streams(3)
+    stream = torch.cuda.Stream()
+    plan.set_graph(True)
+    out = torch.empty_like(eager)
+    for rep in range(4):
+        out.fill_(123.0)
+        junk = torch.randn(1 << 20, device=DEV).sum()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            plan.retrieve(Lt, st, out, Vt, None, ws, stream=stream)
+        stream.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy()[inplan], ref, err_msg=f"replay {rep}")
+        del junk
+    plan.set_graph(False)
+    plan.close()
+
+
+def test_streams_energy_matches_one_stream():
+    """The energy monitor's E^k per partition is the same with concurrent
+    partition groups (its last kernel runs after the join)."""
+    scenes, fls, L, V = _batch()
+    Lt = torch.from_numpy(L).to(DEV)
+    Vt = torch.from_numpy(V).to(DEV)
+    st = torch.from_numpy(scenes[0].s).to(DEV)
+    Es = []
+    for ns in (1, 4):
+        plan = mf.Plan(fls, 74, 8, 2.0, 1e-9, True, "lowrank", track_energy=True)
+        plan.set_streams(ns)
+        ws = plan.alloc_workspace()
+        alpha = torch.empty(L.shape[0], dtype=torch.float32, device=DEV)
+        plan.retrieve(Lt, st, alpha, Vt, None, ws)
+        Es.append(plan.energy(ws).cpu().numpy())
+        torch.cuda.synchronize()
+        plan.close()
+    np.testing.assert_array_equal(Es[1], Es[0])
+    assert np.all(np.isfinite(Es[0]))
+
+
+def test_set_streams_rejects_bad_counts():
+    scenes, fls, L, V = _batch()
+    plan = mf.Plan(fls, 74, 5, 2.0, 1e-9, True, "lowrank")
+    lib = mf.load_library()
+    for n in (0, -1, mf.MAX_STREAMS + 1):
+        assert lib.mf_plan_set_streams(plan._h, n) == mf.MF_E_ARG
+    one = mf.Plan([fls[1]], 74, 5, 2.0, 1e-9, True, "lowrank")   # 3 partitions
+    assert lib.mf_plan_set_streams(one._h, 4) == mf.MF_E_ARG
+    assert lib.mf_plan_set_streams(one._h, 3) == 0 and one.streams == 3
+    assert plan.streams == 1
+    plan.close()
+    one.close()

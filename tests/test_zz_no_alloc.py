@@ -67,3 +67,29 @@ def test_noalloc_rejects_what_does_not_fit():
     rc = lib.mf_retrieve_noalloc(sfb._h, one, None, one, one, None, None)
     assert rc == mf.MF_E_UNSUPPORTED
     sfb.close()
+
+
+def test_noalloc_with_streams_matches_retrieve():
+    """With concurrent partition groups (streams and events the plan created
+    beforehand), the no-alloc call still equals mf_retrieve bit for bit, on
+    two calls in a row, the second with a smaller plan."""
+    a_sc = make_scene(tiny_spec())
+    b_sc = make_scene(SceneSpec(8, 300, 74, 2, (500.0, 5000.0), (3.0, 30.0), seed=33,
+                                mask_max_frac=0.2))
+    lam = config_lambda("tiny")
+    runs = []
+    for sc, ns in ((a_sc, 3), (b_sc, 2)):
+        S, N, B = sc.radiance.shape
+        plan = mf.Plan([(0, S, N)], B, 12, lam, 1e-9, True, "lowrank")
+        plan.set_streams(ns)
+        L, s, V = _inputs(sc)
+        ref = torch.empty((S, N), dtype=torch.float32, device=DEV)
+        plan.retrieve(L, s, ref, V, None, plan.alloc_workspace(DEV))
+        torch.cuda.synchronize()
+        runs.append((plan, L, s, V, ref))
+    for plan, L, s, V, ref in runs:
+        a = torch.full_like(ref, float("nan"))
+        plan.retrieve_noalloc(L, s, a, V)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(a.cpu().numpy(), ref.cpu().numpy())
+        plan.close()

@@ -289,6 +289,18 @@ def main():
         for _ in range(max(1, args.warmup)):
             plan.retrieve(L, s, alpha, None, gst, ws)
         torch.cuda.synchronize()
+        g_ms = {}
+        for ns in stream_candidates:
+            plan.set_streams(min(ns, plan.n_columns))
+            plan.retrieve(L, s, alpha, None, gst, ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                plan.retrieve(L, s, alpha, None, gst, ws)
+            torch.cuda.synchronize()
+            g_ms[ns] = 1e3 * (time.perf_counter() - t0) / 3
+        g_streams = min(g_ms, key=g_ms.get)
+        plan.set_streams(min(g_streams, plan.n_columns))
         gsteps = max(3, args.steps // 4)
         t6 = time.perf_counter()
         for _ in range(gsteps):
@@ -298,8 +310,10 @@ def main():
         grouped = {"workload": f"flightline {S}x{N}x{B}, partitions of 5 columns "
                                f"({plan.n_columns} partitions), {K} iterations, low-rank form",
                    "px_per_s": round(n_px / dtg, 1), "ms_per_step": round(1e3 * dtg, 3),
+                   "streams": g_streams, "ms_per_step_by_streams": {str(k): round(v, 3) for k, v in g_ms.items()},
                    "partitions_failed": int((gst.cpu().numpy() != 0).sum())}
-        log(f"grouped (5 columns): {grouped['px_per_s'] / 1e6:.1f} Mpx/s, {grouped['ms_per_step']:.2f} ms")
+        log(f"grouped (5 columns): {grouped['px_per_s'] / 1e6:.1f} Mpx/s, {grouped['ms_per_step']:.2f} ms "
+            f"with {g_streams} stream(s) {grouped['ms_per_step_by_streams']}")
         plan.close()
         del ws
 
@@ -332,6 +346,18 @@ def main():
         for _ in range(max(1, args.warmup)):
             fb()
         torch.cuda.synchronize()
+        fb_ms = {}
+        for ns in stream_candidates:                 # concurrent partition groups (both sweeps)
+            plan.set_streams(ns)
+            fb()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                fb()
+            torch.cuda.synchronize()
+            fb_ms[ns] = 1e3 * (time.perf_counter() - t0) / 2
+        fb_streams = min(fb_ms, key=fb_ms.get)
+        plan.set_streams(fb_streams)
         t4 = time.perf_counter()
         for _ in range(steps):
             fb()
@@ -342,6 +368,7 @@ def main():
             plan.retrieve(dL, ds_, da, None, None, ws)
         torch.cuda.synchronize()
         dtf = (time.perf_counter() - t5) / steps
+        plan.set_streams(1)                           # kernel timing: each launch alone
         plan.set_timing(True)
         plan.kernel_times()
         fb()
@@ -350,10 +377,11 @@ def main():
         fwdbwd = {"workload": f"differentiation scene {dS}x{dN}x{B}, {K} iterations, lambda "
                               f"{dcfg['lambda']:.4g}, loss sum (alpha - alpha_true)^2",
                   "px_per_s": round(dS * dN / dtfb, 1), "ms_per_step": round(1e3 * dtfb, 3),
+                  "streams": fb_streams, "ms_per_step_by_streams": {str(k): round(v, 3) for k, v in fb_ms.items()},
                   "forward_ms": round(1e3 * dtf, 3), "backward_ms": round(1e3 * (dtfb - dtf), 3),
                   "kernels_ms_fwd_plus_bwd": {k: round(v[0], 4) for k, v in kt.items()}}
         log(f"fwd+bwd: {fwdbwd['px_per_s'] / 1e6:.1f} Mpx/s, {fwdbwd['ms_per_step']:.2f} ms "
-            f"(forward {fwdbwd['forward_ms']:.2f} ms)")
+            f"(forward {fwdbwd['forward_ms']:.2f} ms) with {fb_streams} stream(s) {fwdbwd['ms_per_step_by_streams']}")
         plan.close()
         del ws, dL
 

@@ -275,8 +275,9 @@ MF_API mf_status mf_plan_set_launch(mf_plan plan, int32_t stream_tile, int32_t w
    them).  Graph capture follows the fork and join; a graph captured with the
    previous setting is dropped.  With persistent launches (wgs_per_cu > 0)
    each group takes its work items in plan order from its own counters.
-   mf_backward runs on the caller's stream alone.  Two calls on one plan that
-   overlap in time race on these streams, as they would on the workspace. */
+   mf_backward runs its reverse sweep the same way, one group per stream.
+   Two calls on one plan that overlap in time race on these streams, as they
+   would on the workspace. */
 #define MF_MAX_STREAMS 8
 MF_API mf_status mf_plan_set_streams(mf_plan plan, int32_t n_streams);
 

@@ -462,10 +462,11 @@ def _make_autograd():
 
         @staticmethod
         def forward(ctx, radiance, s, n_iter, lam, eps, albedo, valid, refine_steps, chunk_lines,
-                    group):
+                    group, streams):
             S, N, B = radiance.shape
             plan = Plan([(0, S, N)], B, n_iter, lam, eps, albedo, "lowrank", refine_steps,
                         chunk_lines, save_for_backward=True, group=group)
+            plan.set_streams(min(int(streams), plan.n_columns))
             ws = plan.alloc_workspace(radiance.device)
             L = radiance.detach().contiguous()
             sv = s.detach().contiguous()
@@ -480,7 +481,7 @@ def _make_autograd():
             plan, ws, L, sv, vv = ctx.state
             gL, gs = plan.backward(L, sv, grad_alpha.contiguous().float(), vv, ws)
             ctx.state = None
-            return gL, gs.to(sv.dtype), None, None, None, None, None, None, None, None
+            return gL, gs.to(sv.dtype), None, None, None, None, None, None, None, None, None
 
     return RetrieveFunction
 
@@ -490,13 +491,14 @@ _RetrieveFunction = None
 
 def retrieve_differentiable(radiance, s, n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9,
                             albedo: bool = True, valid=None, refine_steps: int = -1,
-                            chunk_lines: int = 0, group: int = 1):
-    """alpha [S, N] with autograd support (radiance and s), low-rank form."""
+                            chunk_lines: int = 0, group: int = 1, streams: int = 1):
+    """alpha [S, N] with autograd support (radiance and s), low-rank form;
+    streams: concurrent partition groups of both sweeps (Plan.set_streams)."""
     global _RetrieveFunction
     if _RetrieveFunction is None:
         _RetrieveFunction = _make_autograd()
     return _RetrieveFunction.apply(radiance, s, n_iter, lam, eps, albedo, valid, refine_steps,
-                                   chunk_lines, group)
+                                   chunk_lines, group, streams)
 
 
 def _need(t, dtype, name):

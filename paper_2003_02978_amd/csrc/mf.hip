@@ -818,38 +818,49 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
   };
   // pass A(K) and its column step, then per iteration k = K..1 one fused pass
   // B(k) + A(k-1) followed by one column kernel (col B(k), then col A(k-1)),
-  // then pass B(0) and col B(0)
-  set_iter(K);
-  {
-    LaunchTimer tm(p, MF_KERNEL_PASS_VEC, st);
-    hipLaunchKernelGGL(bwd_passA_kernel, dim3((unsigned)p->n_items), dim3(kABlock), ldsA, st, ba);
+  // then pass B(0) and col B(0); every step for each partition group on its
+  // own stream (mf_plan_set_streams), forked after the init kernel
+  const int G = p->n_groups;
+  hipStream_t gs[MF_MAX_STREAMS];
+  gs[0] = st;
+  if (G > 1) {
+    (void)hipEventRecord(p->fork_ev, st);
+    for (int g = 1; g < G; ++g) {
+      gs[g] = p->aux[g - 1];
+      (void)hipStreamWaitEvent(gs[g], p->fork_ev, 0);
+    }
   }
+  auto pass = [&](int g, auto kernel, int kind, size_t lds_bytes, int block) {
+    ba.item_base = (int)p->grp_item[g];
+    const unsigned n = (unsigned)(p->grp_item[g + 1] - p->grp_item[g]);
+    LaunchTimer tm(p, kind, gs[g]);
+    hipLaunchKernelGGL(kernel, dim3(n), dim3(block), lds_bytes, gs[g], ba);
+  };
+  auto column = [&](int g, auto kernel, int block) {
+    ca.col_base = (int)p->grp_col[g];
+    const unsigned n = (unsigned)(p->grp_col[g + 1] - p->grp_col[g]);
+    LaunchTimer tm(p, MF_KERNEL_SOLVE, gs[g]);
+    hipLaunchKernelGGL(kernel, dim3(n), dim3(block), 0, gs[g], ca);
+  };
+  set_iter(K);
   set_col(K, 0);
-  {
-    LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
-    hipLaunchKernelGGL(bwd_colA_kernel, dim3((unsigned)p->n_cols), dim3(kBlock), 0, st, ca);
+  for (int g = 0; g < G; ++g) {
+    pass(g, bwd_passA_kernel, MF_KERNEL_PASS_VEC, ldsA, kABlock);
+    column(g, bwd_colA_kernel, kBlock);
   }
   for (int k = K; k >= 1; --k) {
     set_iter(k);
-    {
-      LaunchTimer tm(p, MF_KERNEL_PASS_VEC, st);
-      hipLaunchKernelGGL(bwd_passB_kernel<true>, dim3((unsigned)p->n_items), dim3(kSBlock), ldsF, st, ba);
-    }
     set_col(k - 1, 1);
-    {
-      LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
-      hipLaunchKernelGGL(bwd_colA_kernel, dim3((unsigned)p->n_cols), dim3(kBlock), 0, st, ca);
+    for (int g = 0; g < G; ++g) {
+      pass(g, bwd_passB_kernel<true>, MF_KERNEL_PASS_VEC, ldsF, kSBlock);
+      column(g, bwd_colA_kernel, kBlock);
     }
   }
   set_iter(0);
-  {
-    LaunchTimer tm(p, MF_KERNEL_PASS_VEC, st);
-    hipLaunchKernelGGL(bwd_passB_kernel<false>, dim3((unsigned)p->n_items), dim3(kSBlock), lds, st, ba);
-  }
   set_col(0, 0);
-  {
-    LaunchTimer tm(p, MF_KERNEL_SOLVE, st);
-    hipLaunchKernelGGL(bwd_colB_kernel, dim3((unsigned)p->n_cols), dim3(128), 0, st, ca);
+  for (int g = 0; g < G; ++g) {
+    pass(g, bwd_passB_kernel<false>, MF_KERNEL_PASS_VEC, lds, kSBlock);
+    column(g, bwd_colB_kernel, 128);
   }
   BwAsmArgs aa{};
   aa.items = p->items_d;
@@ -866,11 +877,17 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
   aa.B = B;
   aa.K = K;
   aa.albedo = p->opt.albedo;
-  {
-    LaunchTimer tm(p, MF_KERNEL_PASS_LAST, st);
-    hipLaunchKernelGGL(bwd_assemble_kernel, dim3((unsigned)p->n_items), dim3(256), asm_lds_bytes(B, K),
-                       st, aa);
+  for (int g = 0; g < G; ++g) {
+    aa.item_base = (int)p->grp_item[g];
+    const unsigned n = (unsigned)(p->grp_item[g + 1] - p->grp_item[g]);
+    LaunchTimer tm(p, MF_KERNEL_PASS_LAST, gs[g]);
+    hipLaunchKernelGGL(bwd_assemble_kernel, dim3(n), dim3(256), asm_lds_bytes(B, K), gs[g], aa);
   }
+  if (G > 1)
+    for (int g = 1; g < G; ++g) {
+      (void)hipEventRecord(p->join_ev[g - 1], gs[g]);
+      (void)hipStreamWaitEvent(st, p->join_ev[g - 1], 0);
+    }
   {
     LaunchTimer tm(p, MF_KERNEL_OTHER, st);
     hipLaunchKernelGGL(bwd_sbar_kernel, dim3((unsigned)B), dim3(256), 0, st, state, bwcol,

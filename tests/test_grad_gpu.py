@@ -311,3 +311,32 @@ def test_adjoint_finite_differences():
     for b in np.argsort(np.abs(sc.s))[-3:]:
         fd = fd_target(L, sc.s, sc.alpha_true, int(b), 1e-4, K, lam)
         assert abs(gs[b] - fd) <= 2e-3 * abs(fd), (int(b), gs[b], fd)
+
+
+@pytest.mark.parametrize("n_streams", [2, 5])
+def test_adjoint_streams_bit_identical(n_streams):
+    """Both sweeps with concurrent partition groups (up to one per partition)
+    give the one-stream gradients bit for bit: odd line counts, ragged
+    128-line work items, masks."""
+    sc = make_scene(SceneSpec(5, 333, 74, 2, (800.0, 5000.0), (3.0, 12.0), seed=41, mask_max_frac=0.1))
+    S, N, B = sc.radiance.shape
+    L = torch.from_numpy(sc.radiance).to(DEV)
+    s = torch.from_numpy(sc.s).to(DEV)
+    valid = torch.from_numpy(sc.valid).to(DEV)
+    at = torch.from_numpy(sc.alpha_true).to(DEV)
+    outs = []
+    for ns in (1, n_streams):
+        plan = mf.Plan([(0, S, N)], B, 8, 2.0, 1e-9, True, "lowrank", chunk_lines=128,
+                       save_for_backward=True)
+        plan.set_streams(ns)
+        ws = plan.alloc_workspace(DEV)
+        alpha = torch.empty((S, N), dtype=torch.float32, device=DEV)
+        plan.retrieve(L, s, alpha, valid, None, ws)
+        g = (2.0 * (alpha.double() - at) * valid.double()).float()
+        gL, gs = plan.backward(L, s, g, valid, ws)
+        torch.cuda.synchronize()
+        outs.append((alpha.cpu().numpy(), gL.cpu().numpy(), gs.cpu().numpy()))
+        plan.close()
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(b, a)
+    assert np.abs(outs[0][1]).max() > 0

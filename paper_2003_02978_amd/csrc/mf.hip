@@ -393,12 +393,15 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
     }
     pa.alpha_final = j == K + 1 ? alpha : nullptr;
     pa.p_save = (ck_p && j >= 1) ? ck_p + (int64_t)(j - 1) * p->max_px : nullptr;
-    // r per pixel: written by pass 1, read by every later scored pass
-    double* rbuf = (double*)(ws + p->off_r);
-    pa.r_out = j == 1 ? rbuf : nullptr;
-    pa.r_in = j >= 2 ? rbuf : nullptr;
+    // r per pixel: written by pass 1 (the adjoint reads it too), read by the
+    // later Gram passes; the streaming passes form it again from the
+    // radiance tile they hold (same arithmetic as pass 1), which costs FP64
+    // FMAs they have room for and saves 8 bytes per pixel of traffic
     const bool mom = j <= K;
     const int mode = pass_mode(p->opt.cov, j, K);
+    double* rbuf = (double*)(ws + p->off_r);
+    pa.r_out = j == 1 ? rbuf : nullptr;
+    pa.r_in = (j >= 2 && mode != PM_VEC && mode != PM_NONE) ? rbuf : nullptr;
     sa.j = j;
     for (int g = 0; g < G; ++g) {
       pa.queue = queue ? group_queue(g) + j : nullptr;

@@ -133,6 +133,9 @@ def main():
     ap.add_argument("--streams", default="1,2,3,4",
                     help="concurrent partition groups per retrieval: one count, or candidates "
                          "of which each form takes the fastest (mf_plan_set_streams)")
+    ap.add_argument("--chunks", default="",
+                    help="work-item lengths (lines) each flightline form tunes with the stream count; "
+                         "default 1024,2048,4096 for the low-rank form, 2048,4096,8192 for the Gram forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-lines", type=int, default=8000)
     ap.add_argument("--save-alpha", default="", help="save each form's alpha as <path>_<form>.npy")
@@ -204,35 +207,58 @@ def main():
     for label in forms:
         form, _, rs = label.partition("@")
         refine = int(rs) if rs else -1
-        plan = mf.Plan([(0, S, N)], B, K, lam, eps, True, form, refine_steps=refine)
+        # launch choice: work-item length and concurrent partition groups,
+        # timed together (every group count gives the same alpha bit for bit;
+        # the length changes the order of the partial sums)
+        chunk_cands = ([int(x) for x in args.chunks.split(",") if x] if args.chunks else
+                       ([1024, 2048, 4096] if form == "lowrank" else [2048, 4096, 8192]))
+        tune_ms = {}
+        for ch in chunk_cands:
+            plan = mf.Plan([(0, S, N)], B, K, lam, eps, True, form, refine_steps=refine, chunk_lines=ch)
+            ws = plan.alloc_workspace(dev)
+            plan.retrieve(L, s, alpha, None, status, ws)
+            for ns in stream_candidates:
+                plan.set_streams(ns)
+                plan.retrieve(L, s, alpha, None, status, ws)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(3):
+                    plan.retrieve(L, s, alpha, None, status, ws)
+                torch.cuda.synchronize()
+                tune_ms[(ch, ns)] = 1e3 * (time.perf_counter() - t0) / 3
+            plan.close()
+            del ws
+        chunk, n_streams = min(tune_ms, key=tune_ms.get)
+        stream_ms = {ns: v for (ch, ns), v in tune_ms.items() if ch == chunk}
+        plan = mf.Plan([(0, S, N)], B, K, lam, eps, True, form, refine_steps=refine, chunk_lines=chunk)
         ws = plan.alloc_workspace(dev)
+        plan.set_streams(n_streams)
         for _ in range(args.warmup):
             plan.retrieve(L, s, alpha, None, status, ws)
         torch.cuda.synchronize()
         steps = args.steps if form == head else max(3, args.steps // 4)
-        # concurrent partition groups: the fastest candidate (a launch choice;
-        # every count gives the same alpha bit for bit)
-        stream_ms = {}
-        for ns in stream_candidates:
-            plan.set_streams(ns)
-            plan.retrieve(L, s, alpha, None, status, ws)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(3):
-                plan.retrieve(L, s, alpha, None, status, ws)
-            torch.cuda.synchronize()
-            stream_ms[ns] = 1e3 * (time.perf_counter() - t0) / 3
-        n_streams = min(stream_ms, key=stream_ms.get)
-        plan.set_streams(n_streams)
         # timed region (no instrumentation)
         t1 = time.perf_counter()
         for _ in range(steps):
             plan.retrieve(L, s, alpha, None, status, ws)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
+        outputs[label] = alpha.cpu().numpy().copy()      # the timed launch setting's result
+        if args.save_alpha:
+            np.save(f"{args.save_alpha}_{label}.npy", outputs[label])
+        st = status.cpu().numpy()
         # instrumented region: per-kernel durations from HIP events recorded on
         # the stream the kernels run on, with one partition group, so that each
-        # launch has the GPU to itself (its duration is the kernel's own)
+        # launch has the GPU to itself (its duration is the kernel's own), at the
+        # work-item length that is fastest with one group
+        one = {ch: v for (ch, ns), v in tune_ms.items() if ns == 1}
+        chunk1 = min(one, key=one.get) if one else chunk
+        if chunk1 != chunk:
+            plan.close()
+            del ws
+            plan = mf.Plan([(0, S, N)], B, K, lam, eps, True, form, refine_steps=refine, chunk_lines=chunk1)
+            ws = plan.alloc_workspace(dev)
+            plan.retrieve(L, s, alpha, None, status, ws)
         plan.set_streams(1)
         plan.set_timing(True)
         plan.kernel_times()
@@ -243,15 +269,14 @@ def main():
         dt_ins = time.perf_counter() - t2
         kt = plan.kernel_times()
         plan.set_timing(False)
-        outputs[label] = alpha.cpu().numpy().copy()
-        if args.save_alpha:
-            np.save(f"{args.save_alpha}_{label}.npy", outputs[label])
-        st = status.cpu().numpy()
         res = {
             "px_per_s": n_px * steps / dt,
             "ms_per_step": 1e3 * dt / steps,
             "streams": n_streams,
+            "chunk_lines": chunk,
+            "kernel_timing_launch": {"streams": 1, "chunk_lines": chunk1},
             "ms_per_step_by_streams": {str(k): round(v, 3) for k, v in stream_ms.items()},
+            "tune_ms": {f"chunk={c},streams={n}": round(v, 3) for (c, n), v in tune_ms.items()},
             "ms_per_step_instrumented": 1e3 * dt_ins / steps,
             "steps": steps,
             "columns_failed": int((st != 0).sum()),
@@ -274,7 +299,7 @@ def main():
             res["gram_frac_of_mfma_peak_tiles"] = res["gram_TFLOPs_tiles"] / PEAK_TFLOPS[form]
         results[label] = res
         log(f"{label}: {res['px_per_s'] / 1e6:.1f} Mpx/s, {res['ms_per_step']:.3f} ms/step with {n_streams} "
-            f"stream(s) {res['ms_per_step_by_streams']}, {dom} {avg_ms * 1e3:.1f} us = "
+            f"stream(s), {chunk}-line items {res['tune_ms']}, {dom} {avg_ms * 1e3:.1f} us = "
             f"{res['dominant_GBps']:.0f} GB/s, kernels {res['kernels_ms_per_step']}")
         plan.close()
         del ws
@@ -320,7 +345,7 @@ def main():
     energy = None
     if "lowrank" in forms and not args.no_energy:
         energy = run_energy(mf, torch, np, dev, L, s, S, N, B, K, lam, eps, results["lowrank"]["ms_per_step"],
-                            args.energy_iters)
+                            args.energy_iters, results["lowrank"]["chunk_lines"], results["lowrank"]["streams"])
 
     # forward + backward (hand-written adjoint) on the differentiation scene:
     # 598 x 4000 x 74, 30 iterations, J = sum (alpha - alpha_true)^2
@@ -448,6 +473,9 @@ def main():
         "avg_launch_ms": round(hr["dominant_avg_ms"], 5),
         "measured_read_ceiling_GBps": round(ceiling_GBps, 1),
         "frac_of_measured_ceiling": round(hr["dominant_GBps"] / ceiling_GBps, 4),
+        # each launch timed alone on the GPU (one partition group); the
+        # timed throughput runs the groups of `config` concurrently
+        "launch": hr["kernel_timing_launch"],
     }
     whole_job_GBps = job_bytes_per_px(K, B) * n_px / (hr["ms_per_step"] * 1e-3) / 1e9
     out = {
@@ -467,7 +495,7 @@ def main():
                                f"covariance form '{head}'",
                    "columns": S, "lines": N, "bands": B, "iterations": K,
                    "covariance": head, "radiance": "f32", "parallelism": "single GPU",
-                   "streams": results[head]["streams"]},
+                   "streams": results[head]["streams"], "chunk_lines": results[head]["chunk_lines"]},
         "headline_form": FORM_LABEL.get(results[head]["form"], head),
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -475,7 +503,8 @@ def main():
         "forms": {f: {"dtype": FORM_DTYPE[r["form"]], "label": FORM_LABEL[r["form"]],
                       "refine_steps": r["refine_steps"],
                       "px_per_s": round(r["px_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
-                      "streams": r["streams"], "ms_per_step_by_streams": r["ms_per_step_by_streams"],
+                      "streams": r["streams"], "chunk_lines": r["chunk_lines"],
+                      "ms_per_step_by_streams": r["ms_per_step_by_streams"],
                       "hbm_fraction_whole_job": round(job_bytes_per_px(K, B) * n_px /
                                                       (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                       "kernels_ms_per_step": r["kernels_ms_per_step"],
@@ -517,7 +546,7 @@ def _stable_from(E, rtol):
     return k
 
 
-def run_energy(mf, torch, np, dev, L, s, S, N, B, K, lam, eps, plain_ms, n_long):
+def run_energy(mf, torch, np, dev, L, s, S, N, B, K, lam, eps, plain_ms, n_long, chunk=0, streams=1):
     """The energy monitor (Eq. 8 per iteration, low-rank form): its cost at the
     flightline workload (K iterations, one partition per column), and a long
     run of n_long iterations with every detector of the flightline in one
@@ -526,7 +555,8 @@ def run_energy(mf, torch, np, dev, L, s, S, N, B, K, lam, eps, plain_ms, n_long)
     n_long iterations (fraction of columns stable by iteration 20)."""
     res = {}
     alpha = torch.empty((S, N), dtype=torch.float32, device=dev)
-    plan = mf.Plan([(0, S, N)], B, K, lam, eps, True, "lowrank", track_energy=True)
+    plan = mf.Plan([(0, S, N)], B, K, lam, eps, True, "lowrank", track_energy=True, chunk_lines=chunk)
+    plan.set_streams(streams)                  # the untracked run's launch setting
     ws = plan.alloc_workspace(dev)
     st = torch.empty((plan.n_columns,), dtype=torch.int32, device=dev)
     plan.retrieve(L, s, alpha, None, st, ws)

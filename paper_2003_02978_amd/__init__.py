@@ -317,12 +317,14 @@ def autotune(flightlines, radiance, s, valid=None, chunks=(512, 1024, 2048, 4096
              tiles=("32x4", "32x2", "64x2", "64x1"), wgs=(0, 1, 2, 3, 4), streams=(1, 2, 3, 4),
              reps: int = 2, cache_path: Optional[str] = None, **plan_kwargs):
     """Pick the launch configuration of a batch geometry by timing whole
-    retrievals: the work-item length (chunk_lines), then the streaming tile
-    shape (pixels per wave chunk x waves per workgroup), then the persistent
-    grid (workgroups per compute unit, 0 = one workgroup per work item), then
-    the number of concurrent partition groups (streams), each step at the best
-    of the previous ones.  Every configuration gives the same alpha bit for
-    bit.  Results are cached in a JSON file keyed by the geometry, options,
+    retrievals: the work-item length (chunk_lines) and the number of
+    concurrent partition groups (streams) together (the best length depends
+    on the group count), then the streaming tile shape (pixels per wave chunk
+    x waves per workgroup), then the persistent grid (workgroups per compute
+    unit, 0 = one workgroup per work item), each step at the best of the
+    previous ones.  Every configuration but the work-item length gives the
+    same alpha bit for bit (the length changes the order of the partial
+    sums).  Results are cached in a JSON file keyed by the geometry, options,
     candidates and device.  Returns (best, {config: ms}) with best =
     {"chunk_lines", "stream_tile", "wgs_per_cu", "streams"}."""
     import hashlib
@@ -364,8 +366,10 @@ def autotune(flightlines, radiance, s, valid=None, chunks=(512, 1024, 2048, 4096
 
     best = {"chunk_lines": int(chunks[0]), "stream_tile": tiles[0], "wgs_per_cu": int(wgs[0]),
             "streams": int(streams[0])}
-    for field, cands in (("chunk_lines", chunks), ("stream_tile", tiles), ("wgs_per_cu", wgs),
-                         ("streams", streams)):
+    joint = {(int(c), int(n)): timed(c, best["stream_tile"], best["wgs_per_cu"], n)
+             for c in chunks for n in streams}
+    best["chunk_lines"], best["streams"] = min(joint, key=joint.get)
+    for field, cands in (("stream_tile", tiles), ("wgs_per_cu", wgs)):
         scores = {}
         for c in cands:
             cfg = dict(best, **{field: c})

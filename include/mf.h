@@ -54,6 +54,7 @@ extern "C" {
 
 #define MF_ABI_VERSION 4
 #define MF_MAX_BANDS 78      /* B + 2 <= 80: five 16-band MFMA blocks */
+#define MF_MAX_BACKWARD_ITER 1000  /* n_iter limit of a plan with save_for_backward */
 
 typedef struct mf_plan_s* mf_plan;
 
@@ -116,7 +117,9 @@ typedef struct {
                              rounded forms to FP64 rounding) */
   int32_t  save_for_backward; /* 1: mf_retrieve keeps alpha^0..alpha^K and the
                              per-iteration column state for mf_backward (needs
-                             MF_COV_LOWRANK and n_iter <= 30; larger workspace) */
+                             MF_COV_LOWRANK and n_iter <= MF_MAX_BACKWARD_ITER;
+                             a workspace about 32 (K + 1) bytes per pixel larger,
+                             plus 8 B per pixel and band when K > 30) */
   int32_t  chunk_lines;   /* pixels per work item along a column (multiple of
                              128; 0 = library default: 1024 for the low-rank
                              form, 4096 for the Gram forms) */

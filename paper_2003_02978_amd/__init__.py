@@ -28,6 +28,7 @@ EXPORTS = ("mf_abi_version", "mf_options_default", "mf_status_str", "mf_last_err
 TILES = {"32x4": 0, "32x2": 1, "64x2": 2, "64x1": 3}   # MF_TILE_*: pixels per wave chunk x waves
 NOALLOC_SCRATCH_BYTES = 64 << 20   # MF_NOALLOC_SCRATCH_BYTES
 MAX_STREAMS = 8                    # MF_MAX_STREAMS
+MAX_BACKWARD_ITER = 1000           # MF_MAX_BACKWARD_ITER
 KERNEL_KINDS = ("pass_gram", "pass_vec", "pass_last", "solve", "other", "pass_init")
 ABI_VERSION = 4          # MF_ABI_VERSION of include/mf.h (mf_options layout)
 
@@ -496,8 +497,9 @@ _RetrieveFunction = None
 def retrieve_differentiable(radiance, s, n_iter: int = 30, lam: float = 1.0, eps: float = 1e-9,
                             albedo: bool = True, valid=None, refine_steps: int = -1,
                             chunk_lines: int = 0, group: int = 1, streams: int = 1):
-    """alpha [S, N] with autograd support (radiance and s), low-rank form;
-    streams: concurrent partition groups of both sweeps (Plan.set_streams)."""
+    """alpha [S, N] with autograd support (radiance and s), low-rank form,
+    n_iter up to MAX_BACKWARD_ITER; streams: concurrent partition groups of
+    both sweeps (Plan.set_streams)."""
     global _RetrieveFunction
     if _RetrieveFunction is None:
         _RetrieveFunction = _make_autograd()

@@ -66,6 +66,7 @@ static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 thread_local std::string g_last_error;
 
 constexpr int kMaxDevices = 64;
+constexpr int kMaxBackwardIter = MF_MAX_BACKWARD_ITER;
 std::mutex g_scratch_mutex;
 void* g_scratch_ptr[kMaxDevices] = {};
 
@@ -128,7 +129,7 @@ struct mf_plan_s {
   size_t off_state = 0, off_partials = 0, off_c0 = 0, off_pinv = 0, off_alpha0 = 0, off_alpha1 = 0;
   // save_for_backward: checkpoints and adjoint buffers
   size_t off_r = 0, off_ck_alpha = 0, off_ck_col = 0, off_ck_p = 0, off_bw_px = 0, off_bw_coef = 0, off_bw_u = 0,
-         off_bw_col = 0;
+         off_bw_col = 0, off_bw_acc = 0;
   size_t off_energy = 0;     // track_energy: E^k per partition [K+1][n_cols]
   size_t ws_bytes = 0;
   void* scratch_d = nullptr; // this device's `scratch` (mf_retrieve_noalloc)
@@ -502,8 +503,9 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
     return fail_with(MF_E_ARG, "save_for_backward must be 0 or 1");
   if (opt->save_for_backward && opt->cov != MF_COV_LOWRANK)
     return fail_with(MF_E_UNSUPPORTED, "save_for_backward needs the low-rank covariance form");
-  if (opt->save_for_backward && opt->n_iter > 30)
-    return fail_with(MF_E_UNSUPPORTED, "save_for_backward supports n_iter <= 30");
+  if (opt->save_for_backward && opt->n_iter > kMaxBackwardIter)
+    return fail_with(MF_E_UNSUPPORTED,
+                     "save_for_backward supports n_iter <= " + std::to_string(kMaxBackwardIter));
   if (opt->chunk_lines < 0 || opt->chunk_lines % 128 != 0)
     return fail_with(MF_E_ARG, "chunk_lines must be a non-negative multiple of 128");
   if (opt->group < 1) return fail_with(MF_E_ARG, "group must be >= 1");
@@ -646,6 +648,10 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
     off = align256(off + K1 * (size_t)p->n_cols * kPad * sizeof(double));
     p->off_bw_col = off;
     off = align256(off + (size_t)p->n_cols * kBw * sizeof(double));
+    if (asm_blocks(opt->n_iter) > 1) {       // FP64 running sum of the gradient assembly
+      p->off_bw_acc = off;
+      off = align256(off + (size_t)max_px * opt->n_bands * sizeof(double));
+    }
   }
   if (opt->track_energy) {
     p->off_energy = off;
@@ -880,11 +886,16 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
   aa.B = B;
   aa.K = K;
   aa.albedo = p->opt.albedo;
+  aa.n_blocks = asm_blocks(K);
+  aa.acc = aa.n_blocks > 1 ? (double*)(ws + p->off_bw_acc) : nullptr;
   for (int g = 0; g < G; ++g) {
     aa.item_base = (int)p->grp_item[g];
     const unsigned n = (unsigned)(p->grp_item[g + 1] - p->grp_item[g]);
-    LaunchTimer tm(p, MF_KERNEL_PASS_LAST, gs[g]);
-    hipLaunchKernelGGL(bwd_assemble_kernel, dim3(n), dim3(256), asm_lds_bytes(B, K), gs[g], aa);
+    for (int q = 0; q < aa.n_blocks; ++q) {      // in order on the group's stream
+      aa.block = q;
+      LaunchTimer tm(p, MF_KERNEL_PASS_LAST, gs[g]);
+      hipLaunchKernelGGL(bwd_assemble_kernel, dim3(n), dim3(256), asm_lds_bytes(B, K), gs[g], aa);
+    }
   }
   if (G > 1)
     for (int g = 1; g < G; ++g) {

@@ -70,11 +70,24 @@ def test_bad_options_rejected_on_host(field, value, code):
     assert rc == code and not h.value and msg
 
 
-def test_backward_needs_low_rank_form_and_k_le_30():
+def test_header_limits_match_the_binding():
+    src = open(os.path.join(ROOT, "include", "mf.h")).read()
+
+    def define(name):
+        return re.search(r"#define\s+" + name + r"\s+(.+?)\s*(/\*|$)", src, re.M).group(1)
+
+    assert int(define("MF_MAX_BANDS")) == 78
+    assert int(define("MF_MAX_STREAMS")) == mf.MAX_STREAMS
+    assert int(define("MF_MAX_BACKWARD_ITER")) == mf.MAX_BACKWARD_ITER
+    assert define("MF_NOALLOC_SCRATCH_BYTES") == "((size_t)64 << 20)" == "((size_t)%d << 20)" % (
+        mf.NOALLOC_SCRATCH_BYTES >> 20)
+
+
+def test_backward_needs_low_rank_form_and_bounded_k():
     rc, h, msg = _create(save_for_backward=1, cov=1)
     assert rc == mf.MF_E_UNSUPPORTED and "low-rank" in msg
-    rc, h, msg = _create(save_for_backward=1, n_iter=31)
-    assert rc == mf.MF_E_UNSUPPORTED
+    rc, h, msg = _create(save_for_backward=1, n_iter=mf.MAX_BACKWARD_ITER + 1)
+    assert rc == mf.MF_E_UNSUPPORTED and str(mf.MAX_BACKWARD_ITER) in msg
     lib = mf.load_library()
     assert lib.mf_backward(None, None, None, None, None, None, None, None, None) == mf.MF_E_ARG
 

@@ -313,6 +313,41 @@ def test_adjoint_finite_differences():
         assert abs(gs[b] - fd) <= 2e-3 * abs(fd), (int(b), gs[b], fd)
 
 
+@pytest.mark.parametrize("K,n_streams", [(31, 1), (61, 1), (94, 2), (95, 1)])
+def test_adjoint_more_than_thirty_iterations(K, n_streams):
+    """K > 30: the gradient assembly runs in several blocks of 64 coefficient
+    slots (K = 31: a second block with two slots; 61: two full blocks; 94:
+    three full blocks; 95: a fourth with two) summed in FP64; odd line
+    counts, 128-line work items, masks."""
+    sc = make_scene(SceneSpec(4, 301, 74, 2, (800.0, 5000.0), (3.0, 12.0), seed=53, mask_max_frac=0.1))
+    S, N, B = sc.radiance.shape
+    lam = 2.0
+    plan = mf.Plan([(0, S, N)], B, K, lam, 1e-9, True, "lowrank", chunk_lines=128,
+                   save_for_backward=True)
+    plan.set_streams(n_streams)
+    ws = plan.alloc_workspace(DEV)
+    L = torch.from_numpy(sc.radiance).to(DEV)
+    s = torch.from_numpy(sc.s).to(DEV)
+    valid = torch.from_numpy(sc.valid).to(DEV)
+    alpha = torch.empty((S, N), dtype=torch.float32, device=DEV)
+    plan.retrieve(L, s, alpha, valid, None, ws)
+    at = torch.from_numpy(sc.alpha_true).to(DEV)
+    g = (2.0 * (alpha.double() - at) * valid.double()).float()
+    gL, gs = plan.backward(L, s, g, valid, ws)
+    torch.cuda.synchronize()
+    Lr = sc.radiance.astype(np.float64)
+    Lr[np.isnan(Lr)] = 0.0
+    Jr, gLr, gsr = loss_and_grads(Lr, sc.s, sc.alpha_true, K, lam, valid=sc.valid)
+    gL = gL.cpu().numpy().astype(np.float64)
+    gs = gs.cpu().numpy()
+    print(f"K={K} streams={n_streams}: grad L rel err {_rel_err(gL, gLr):.2e}, "
+          f"grad s rel err {_rel_err(gs, gsr):.2e}", flush=True)
+    assert np.all(gL[sc.valid == 0] == 0)
+    assert _rel_err(gL, gLr) < 1e-4
+    assert _rel_err(gs, gsr) < 1e-4
+    plan.close()
+
+
 @pytest.mark.parametrize("n_streams", [2, 5])
 def test_adjoint_streams_bit_identical(n_streams):
     """Both sweeps with concurrent partition groups (up to one per partition)

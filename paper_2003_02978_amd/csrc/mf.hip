@@ -894,7 +894,15 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
     for (int q = 0; q < aa.n_blocks; ++q) {      // in order on the group's stream
       aa.block = q;
       LaunchTimer tm(p, MF_KERNEL_PASS_LAST, gs[g]);
-      hipLaunchKernelGGL(bwd_assemble_kernel, dim3(n), dim3(256), asm_lds_bytes(B, K), gs[g], aa);
+      const size_t lds = asm_lds_bytes(B, K);
+      if (aa.n_blocks == 1)
+        hipLaunchKernelGGL(bwd_assemble_kernel<kAsmOnly>, dim3(n), dim3(256), lds, gs[g], aa);
+      else if (q == 0)
+        hipLaunchKernelGGL(bwd_assemble_kernel<kAsmFirst>, dim3(n), dim3(256), lds, gs[g], aa);
+      else if (q + 1 < aa.n_blocks)
+        hipLaunchKernelGGL(bwd_assemble_kernel<kAsmMid>, dim3(n), dim3(256), lds, gs[g], aa);
+      else
+        hipLaunchKernelGGL(bwd_assemble_kernel<kAsmLast>, dim3(n), dim3(256), lds, gs[g], aa);
     }
   }
   if (G > 1)

@@ -348,6 +348,38 @@ def test_adjoint_more_than_thirty_iterations(K, n_streams):
     plan.close()
 
 
+def test_adjoint_forty_iterations_grouped_autograd():
+    """K = 40 (two assembly blocks) through torch.autograd, with partitions of
+    3 columns (remainder 2), albedo off and two partition groups: against
+    the reference gradient of each partition run as one column."""
+    sc = make_scene(SceneSpec(5, 200, 74, 2, (800.0, 5000.0), (3.0, 12.0), seed=59))
+    S, N, B = sc.radiance.shape
+    K, lam, g = 40, 2.0, 3
+    L = torch.from_numpy(sc.radiance).to(DEV).requires_grad_(True)
+    s = torch.from_numpy(sc.s).to(DEV).requires_grad_(True)
+    at = torch.from_numpy(sc.alpha_true).to(DEV)
+    alpha = mf.retrieve_differentiable(L, s, K, lam, 1e-9, False, None, group=g, streams=2)
+    J = ((alpha.double() - at) ** 2).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    gL = L.grad.cpu().numpy().astype(np.float64)
+    gs = s.grad.cpu().numpy().astype(np.float64)
+    Jr, gLr, gsr = 0.0, np.zeros_like(gL), np.zeros(B)
+    for c0 in range(0, S, g):
+        c1 = min(S, c0 + g)
+        Lp = sc.radiance[c0:c1].astype(np.float64).reshape(1, (c1 - c0) * N, B)
+        Ap = sc.alpha_true[c0:c1].reshape(1, -1)
+        j, gl, gsp = loss_and_grads(Lp, sc.s, Ap, K, lam, albedo=False)
+        Jr += j
+        gLr[c0:c1] = gl.reshape(c1 - c0, N, B)
+        gsr += gsp
+    print(f"K=40 grouped autograd: J {float(J):.6e} ref {Jr:.6e}, grad L rel err {_rel_err(gL, gLr):.2e}, "
+          f"grad s rel err {_rel_err(gs, gsr):.2e}", flush=True)
+    assert abs(float(J) - Jr) <= 1e-6 * Jr
+    assert _rel_err(gL, gLr) < 1e-4
+    assert _rel_err(gs, gsr) < 1e-4
+
+
 @pytest.mark.parametrize("n_streams", [2, 5])
 def test_adjoint_streams_bit_identical(n_streams):
     """Both sweeps with concurrent partition groups (up to one per partition)

@@ -127,6 +127,7 @@ struct mf_plan_s {
   ColInfo* cols_d = nullptr;
   WorkItem* items_d = nullptr;
   size_t off_state = 0, off_partials = 0, off_c0 = 0, off_pinv = 0, off_alpha0 = 0, off_alpha1 = 0;
+  size_t off_mask0 = 0, off_mask1 = 0;   // sparse alpha: one word per 32-pixel piece
   // save_for_backward: checkpoints and adjoint buffers
   size_t off_r = 0, off_ck_alpha = 0, off_ck_col = 0, off_ck_p = 0, off_bw_px = 0, off_bw_coef = 0, off_bw_u = 0,
          off_bw_col = 0, off_bw_acc = 0;
@@ -326,6 +327,7 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   ColState* state = (ColState*)(ws + p->off_state);
   double* partials = (double*)(ws + p->off_partials);
   double* abuf[2] = {(double*)(ws + p->off_alpha0), (double*)(ws + p->off_alpha1)};
+  uint32_t* mbuf[2] = {(uint32_t*)(ws + p->off_mask0), (uint32_t*)(ws + p->off_mask1)};
   double* ck_alpha = p->opt.save_for_backward ? (double*)(ws + p->off_ck_alpha) : nullptr;
   double* ck_p = p->opt.save_for_backward ? (double*)(ws + p->off_ck_p) : nullptr;
   const int B = p->opt.n_bands;
@@ -392,6 +394,11 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
       pa.alpha_prev = j >= 2 ? abuf[(j - 2) & 1] : nullptr;
       pa.alpha_out = (j >= 1 && j <= K) ? abuf[(j - 1) & 1] : nullptr;
     }
+    // sparse alpha between the streaming passes of the low-rank form (the
+    // checkpoints and the Gram passes keep every entry)
+    const bool sparse = p->opt.cov == MF_COV_LOWRANK && !ck_alpha;
+    pa.mask_prev = (sparse && pa.alpha_prev) ? mbuf[(j - 2) & 1] : nullptr;
+    pa.mask_out = (sparse && pa.alpha_out) ? mbuf[(j - 1) & 1] : nullptr;
     pa.alpha_final = j == K + 1 ? alpha : nullptr;
     pa.p_save = (ck_p && j >= 1) ? ck_p + (int64_t)(j - 1) * p->max_px : nullptr;
     // r per pixel: written by pass 1 (the adjoint reads it too), read by the
@@ -630,6 +637,11 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   off = align256(off + (size_t)max_px * sizeof(double));
   p->off_alpha1 = off;
   off = align256(off + (size_t)max_px * sizeof(double));
+  const size_t mask_words = (size_t)max_px / 32 + (size_t)p->n_items + 2;
+  p->off_mask0 = off;
+  off = align256(off + mask_words * sizeof(uint32_t));
+  p->off_mask1 = off;
+  off = align256(off + mask_words * sizeof(uint32_t));
   p->off_r = off;                              // r per pixel (written by pass 1)
   off = align256(off + (size_t)max_px * sizeof(double));
   if (opt->save_for_backward) {

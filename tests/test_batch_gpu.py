@@ -308,3 +308,32 @@ def test_set_streams_rejects_bad_counts():
     assert plan.streams == 1
     plan.close()
     one.close()
+
+
+@pytest.mark.parametrize("tile,wgs,n_streams", [("32x4", 0, 1), ("64x2", 0, 1), ("64x1", 0, 1),
+                                                ("32x4", 2, 3)])
+def test_sparse_alpha_matches_every_entry(tile, wgs, n_streams):
+    """A low-rank retrieval passes alpha between its streaming passes sparsely
+    (nonzero entries plus a mask per 32-pixel piece); one with checkpoints
+    (save_for_backward) writes and reads every entry.  Both give the same
+    alpha bit for bit: ragged masked flightlines with a gap, odd line
+    counts, every tile shape's piece layout."""
+    scenes, fls, L, V = _batch()
+    Lt = torch.from_numpy(L).to(DEV)
+    Vt = torch.from_numpy(V).to(DEV)
+    s = torch.from_numpy(scenes[0].s).to(DEV)
+    outs = []
+    for save in (False, True):
+        plan = mf.Plan(fls, 74, 12, 2.0, 1e-9, True, "lowrank", chunk_lines=128, save_for_backward=save)
+        plan.set_launch(tile, wgs)
+        plan.set_streams(n_streams)
+        ws = plan.alloc_workspace(DEV)
+        alpha = torch.full((L.shape[0],), -1.0, dtype=torch.float32, device=DEV)
+        st = torch.empty((plan.n_columns,), dtype=torch.int32, device=DEV)
+        plan.retrieve(Lt, s, alpha, Vt, st, ws)
+        torch.cuda.synchronize()
+        outs.append((alpha.cpu().numpy(), st.cpu().numpy()))
+        plan.close()
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    assert (outs[0][0] > 0).sum() > 100

@@ -394,9 +394,8 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
       pa.alpha_prev = j >= 2 ? abuf[(j - 2) & 1] : nullptr;
       pa.alpha_out = (j >= 1 && j <= K) ? abuf[(j - 1) & 1] : nullptr;
     }
-    // sparse alpha between the streaming passes of the low-rank form (the
-    // checkpoints and the Gram passes keep every entry)
-    const bool sparse = p->opt.cov == MF_COV_LOWRANK && !ck_alpha;
+    // sparse alpha between the passes (the checkpoints keep every entry)
+    const bool sparse = !ck_alpha;
     pa.mask_prev = (sparse && pa.alpha_prev) ? mbuf[(j - 2) & 1] : nullptr;
     pa.mask_out = (sparse && pa.alpha_out) ? mbuf[(j - 1) & 1] : nullptr;
     pa.alpha_final = j == K + 1 ? alpha : nullptr;
@@ -408,7 +407,9 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
     const bool mom = j <= K;
     const int mode = pass_mode(p->opt.cov, j, K);
     double* rbuf = (double*)(ws + p->off_r);
-    pa.r_out = j == 1 ? rbuf : nullptr;
+    // (read by the Gram passes and the adjoint; the low-rank form's
+    // streaming passes without checkpoints have no reader, so skip the write)
+    pa.r_out = (j == 1 && (p->opt.cov != MF_COV_LOWRANK || ck_alpha)) ? rbuf : nullptr;
     pa.r_in = (j >= 2 && mode != PM_VEC && mode != PM_NONE) ? rbuf : nullptr;
     sa.j = j;
     for (int g = 0; g < G; ++g) {

@@ -310,7 +310,7 @@ def test_set_streams_rejects_bad_counts():
     one.close()
 
 
-@pytest.mark.parametrize("tile,wgs,n_streams", [("32x4", 0, 1), ("64x2", 0, 1), ("64x1", 0, 1),
+@pytest.mark.parametrize("tile,wgs,n_streams", [("32x4", 0, 1), ("64x2", 0, 1), ("64x1", 0, 1), ("32x2", 3, 2),
                                                 ("32x4", 2, 3)])
 def test_sparse_alpha_matches_every_entry(tile, wgs, n_streams):
     """A low-rank retrieval passes alpha between its streaming passes sparsely

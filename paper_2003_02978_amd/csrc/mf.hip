@@ -124,6 +124,7 @@ struct mf_plan_s {
   int nb = 0;
   int device = 0;
   int64_t n_cols = 0, n_items = 0, n_px = 0, max_px = 0;
+  int64_t n_words = 0;       // sparse alpha: mask words (32-pixel pieces of every work item)
   ColInfo* cols_d = nullptr;
   WorkItem* items_d = nullptr;
   size_t off_state = 0, off_partials = 0, off_c0 = 0, off_pinv = 0, off_alpha0 = 0, off_alpha1 = 0;
@@ -528,7 +529,7 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   std::vector<ColInfo> cols;
   std::vector<WorkItem> items;
   std::vector<std::pair<int64_t, int64_t>> ranges;
-  int64_t n_px = 0, max_px = 0;
+  int64_t n_px = 0, max_px = 0, n_words = 0;
   for (int f = 0; f < n_fl; ++f) {
     const mf_flightline& F = fl[f];
     if (F.n_columns < 1 || F.n_lines < 1 || F.first_px < 0)
@@ -556,9 +557,11 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
       for (int k = 0; k < nit && done < npart; ++k) {
         WorkItem w{};
         w.px_begin = ci.first_px + done;
+        w.word0 = n_words;
         w.col = (int32_t)cols.size();
         w.n_px = std::min(per, npart - done);
         done += w.n_px;
+        n_words += (w.n_px + 31) / 32;
         items.push_back(w);
       }
       ci.n_items = (int32_t)items.size() - ci.first_item;
@@ -580,6 +583,7 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   p->n_items = (int64_t)items.size();
   p->n_px = n_px;
   p->max_px = max_px;
+  p->n_words = n_words;
   p->cols_h = cols;
   p->grp_col = {0, p->n_cols};
   p->grp_item = {0, p->n_items};
@@ -638,7 +642,7 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
   off = align256(off + (size_t)max_px * sizeof(double));
   p->off_alpha1 = off;
   off = align256(off + (size_t)max_px * sizeof(double));
-  const size_t mask_words = (size_t)max_px / 32 + (size_t)p->n_items + 2;
+  const size_t mask_words = (size_t)p->n_words + 2;
   p->off_mask0 = off;
   off = align256(off + mask_words * sizeof(uint32_t));
   p->off_mask1 = off;

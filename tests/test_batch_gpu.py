@@ -310,15 +310,19 @@ def test_set_streams_rejects_bad_counts():
     one.close()
 
 
-@pytest.mark.parametrize("tile,wgs,n_streams", [("32x4", 0, 1), ("64x2", 0, 1), ("64x1", 0, 1), ("32x2", 3, 2),
-                                                ("32x4", 2, 3)])
-def test_sparse_alpha_matches_every_entry(tile, wgs, n_streams):
+@pytest.mark.parametrize("tile,wgs,n_streams,reverse", [("32x4", 0, 1, False), ("64x2", 0, 1, False),
+                                                        ("64x1", 0, 1, True), ("32x2", 3, 2, False),
+                                                        ("32x4", 2, 3, True)])
+def test_sparse_alpha_matches_every_entry(tile, wgs, n_streams, reverse):
     """A low-rank retrieval passes alpha between its streaming passes sparsely
     (nonzero entries plus a mask per 32-pixel piece); one with checkpoints
     (save_for_backward) writes and reads every entry.  Both give the same
     alpha bit for bit: ragged masked flightlines with a gap, odd line
-    counts, every tile shape's piece layout."""
+    counts, every tile shape's piece layout, and flightlines listed out of
+    pixel order (reverse)."""
     scenes, fls, L, V = _batch()
+    if reverse:
+        fls = fls[::-1]
     Lt = torch.from_numpy(L).to(DEV)
     Vt = torch.from_numpy(V).to(DEV)
     s = torch.from_numpy(scenes[0].s).to(DEV)

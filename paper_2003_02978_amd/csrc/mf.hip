@@ -129,6 +129,7 @@ struct mf_plan_s {
   WorkItem* items_d = nullptr;
   size_t off_state = 0, off_partials = 0, off_c0 = 0, off_pinv = 0, off_alpha0 = 0, off_alpha1 = 0;
   size_t off_mask0 = 0, off_mask1 = 0;   // sparse alpha: one word per 32-pixel piece
+  size_t off_ck_mask = 0;                // save_for_backward: the masks of alpha^0..alpha^K
   // save_for_backward: checkpoints and adjoint buffers
   size_t off_r = 0, off_ck_alpha = 0, off_ck_col = 0, off_ck_p = 0, off_bw_px = 0, off_bw_coef = 0, off_bw_u = 0,
          off_bw_col = 0, off_bw_acc = 0;
@@ -329,6 +330,8 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
   double* partials = (double*)(ws + p->off_partials);
   double* abuf[2] = {(double*)(ws + p->off_alpha0), (double*)(ws + p->off_alpha1)};
   uint32_t* mbuf[2] = {(uint32_t*)(ws + p->off_mask0), (uint32_t*)(ws + p->off_mask1)};
+  const int64_t mask_words = p->n_words + 2;
+  uint32_t* ck_mask = p->opt.save_for_backward ? (uint32_t*)(ws + p->off_ck_mask) : nullptr;
   double* ck_alpha = p->opt.save_for_backward ? (double*)(ws + p->off_ck_alpha) : nullptr;
   double* ck_p = p->opt.save_for_backward ? (double*)(ws + p->off_ck_p) : nullptr;
   const int B = p->opt.n_bands;
@@ -395,10 +398,15 @@ void enqueue_retrieve(mf_plan_s* p, const float* radiance, const uint8_t* valid,
       pa.alpha_prev = j >= 2 ? abuf[(j - 2) & 1] : nullptr;
       pa.alpha_out = (j >= 1 && j <= K) ? abuf[(j - 1) & 1] : nullptr;
     }
-    // sparse alpha between the passes (the checkpoints keep every entry)
-    const bool sparse = !ck_alpha;
-    pa.mask_prev = (sparse && pa.alpha_prev) ? mbuf[(j - 2) & 1] : nullptr;
-    pa.mask_out = (sparse && pa.alpha_out) ? mbuf[(j - 1) & 1] : nullptr;
+    // sparse alpha between the passes, the checkpoints included (each
+    // checkpoint with its own mask array)
+    if (ck_alpha) {
+      pa.mask_prev = j >= 2 ? ck_mask + (int64_t)(j - 2) * mask_words : nullptr;
+      pa.mask_out = j >= 1 ? ck_mask + (int64_t)(j - 1) * mask_words : nullptr;
+    } else {
+      pa.mask_prev = pa.alpha_prev ? mbuf[(j - 2) & 1] : nullptr;
+      pa.mask_out = pa.alpha_out ? mbuf[(j - 1) & 1] : nullptr;
+    }
     pa.alpha_final = j == K + 1 ? alpha : nullptr;
     pa.p_save = (ck_p && j >= 1) ? ck_p + (int64_t)(j - 1) * p->max_px : nullptr;
     // r per pixel: written by pass 1 (the adjoint reads it too), read by the
@@ -653,6 +661,8 @@ mf_status mf_plan_create(const mf_options* opt, const mf_flightline* fl, int32_t
     const size_t K1 = (size_t)opt->n_iter + 1;
     p->off_ck_alpha = off;
     off = align256(off + K1 * (size_t)max_px * sizeof(double));
+    p->off_ck_mask = off;                    // K + 1 mask arrays of mask_words words
+    off = align256(off + K1 * mask_words * sizeof(uint32_t));
     p->off_ck_col = off;
     off = align256(off + K1 * (size_t)p->n_cols * kCk * sizeof(double));
     p->off_ck_p = off;                       // p^0..p^K
@@ -774,6 +784,8 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
   ColState* state = (ColState*)(ws + p->off_state);
   double* partials = (double*)(ws + p->off_partials);
   double* ck_alpha = (double*)(ws + p->off_ck_alpha);
+  const uint32_t* ck_mask = (const uint32_t*)(ws + p->off_ck_mask);
+  const int64_t mask_words = p->n_words + 2;
   double* ck_col = (double*)(ws + p->off_ck_col);
   double* ck_p = (double*)(ws + p->off_ck_p);
   double* bwpx = (double*)(ws + p->off_bw_px);
@@ -827,6 +839,8 @@ mf_status mf_backward(mf_plan p, const float* radiance, const uint8_t* valid, co
     ba.a_k = ck_alpha + (int64_t)k * mp;
     ba.a_km1 = k >= 1 ? ck_alpha + (int64_t)(k - 1) * mp : nullptr;
     ba.a_km2 = k >= 2 ? ck_alpha + (int64_t)(k - 2) * mp : nullptr;
+    ba.m_km1 = k >= 1 ? ck_mask + (int64_t)(k - 1) * mask_words : nullptr;
+    ba.m_km2 = k >= 2 ? ck_mask + (int64_t)(k - 2) * mask_words : nullptr;
     ba.p_k = ck_p + (int64_t)k * mp;
     ba.p_km1 = k >= 1 ? ck_p + (int64_t)(k - 1) * mp : nullptr;
     ba.coef_v = coef + (int64_t)(2 * k) * mp;

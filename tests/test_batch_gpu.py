@@ -315,8 +315,9 @@ def test_set_streams_rejects_bad_counts():
                                                         ("32x4", 2, 3, True)])
 def test_sparse_alpha_matches_every_entry(tile, wgs, n_streams, reverse):
     """A low-rank retrieval passes alpha between its streaming passes sparsely
-    (nonzero entries plus a mask per 32-pixel piece); one with checkpoints
-    (save_for_backward) writes and reads every entry.  Both give the same
+    (nonzero entries plus a mask per 32-pixel piece) through two ping-pong
+    buffers; one with checkpoints (save_for_backward) keeps every
+    iteration's alpha, each with its own mask array.  Both give the same
     alpha bit for bit: ragged masked flightlines with a gap, odd line
     counts, every tile shape's piece layout, and flightlines listed out of
     pixel order (reverse)."""

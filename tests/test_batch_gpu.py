@@ -342,3 +342,28 @@ def test_sparse_alpha_matches_every_entry(tile, wgs, n_streams, reverse):
     np.testing.assert_array_equal(outs[0][0], outs[1][0])
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
     assert (outs[0][0] > 0).sum() > 100
+
+
+def test_sparse_alpha_workspace_reused_across_tile_shapes():
+    """The masks of the sparse alpha live in the workspace and every pass
+    rewrites every word of its pieces, so a workspace reused by retrievals
+    with other tile shapes (pieces written by 64-pixel chunks, then by
+    32-pixel ones, then by a persistent launch) gives each the alpha of a
+    fresh workspace, bit for bit."""
+    scenes, fls, L, V = _batch()
+    Lt = torch.from_numpy(L).to(DEV)
+    Vt = torch.from_numpy(V).to(DEV)
+    s = torch.from_numpy(scenes[0].s).to(DEV)
+    plan = mf.Plan(fls, 74, 12, 2.0, 1e-9, True, "lowrank", chunk_lines=128)
+    shared = plan.alloc_workspace(DEV)
+    shared.fill_(0xFF)                       # garbage in every mask word at the start
+    for tile, wgs in (("64x2", 0), ("32x4", 0), ("32x2", 2), ("64x1", 0)):
+        plan.set_launch(tile, wgs)
+        fresh = plan.alloc_workspace(DEV)
+        a1 = torch.full((L.shape[0],), -1.0, dtype=torch.float32, device=DEV)
+        a2 = torch.full((L.shape[0],), -1.0, dtype=torch.float32, device=DEV)
+        plan.retrieve(Lt, s, a1, Vt, None, shared)
+        plan.retrieve(Lt, s, a2, Vt, None, fresh)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(a1.cpu().numpy(), a2.cpu().numpy())
+    plan.close()
